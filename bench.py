@@ -1,0 +1,225 @@
+#!/usr/bin/env python3
+"""Benchmark of the downsampled SST + direct inverse on one MI355X.
+
+One step = the whole hot path over one synthetic signal already resident in
+HBM: threshold pre-pass (max |S| over every frame), fused forward transform
+(framing, FFT pair, IF, selective subdivided reassignment, T rows), ridge
+argmax per component, and the direct inverse of every component.
+
+Workload (default): N = 2^20 samples at 25.6 kHz, three AM-FM components plus
+white noise at 10 dB, Gaussian window of 1023 taps (sigma 128), hop 16,
+N_f = 4096, band [0, 6.4 kHz], subdivision 4, threshold 1e-3 max|S|, three
+reconstruction zones of half-width 6 bins.
+
+Prints ONE JSON line.  Per-kernel times come from HIP events recorded on the
+stream the library launches on.  The roofline object refers to the fused
+forward kernel (the dominant HBM writer); its algorithmic bytes are the signal
+read plus the dense complex64 T write.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, GB/s
+FP32_VALU_TFLOPS = 157.3   # MI355X vector FP32 (dual-issue / packed) peak
+METRIC = "SST Msamples/s and % of HBM/MFMA roofline, batched vs plain, at stated error"
+
+
+def kernel_source_hash() -> str:
+    p = os.path.join(ROOT, "paper_2003_07065_amd", "csrc", "sst_kernels.hip")
+    with open(p, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def load_traffic(workload: str):
+    """HBM traffic of the fused forward kernel from committed rocprofv3 counter runs,
+    or None when absent or taken on another version of the kernels."""
+    p = os.path.join(ROOT, "profiles", f"fwd_kernel_{workload}_traffic.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        d = json.load(f)
+    if d.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return d
+
+
+def cpu_baseline(n_sample: int):
+    """The float64 oracle, as it stands, on the first n_sample samples of the workload:
+    threshold maximum, STFT pair, reassignment, and the inverse of the three components."""
+    import numpy as np
+    import oracle
+    from workloads import make_c2, ridge_bins
+    w = make_c2(n=n_sample)
+    c = w.cfg
+    x = w.x.astype(np.float64)
+    t0 = time.perf_counter()
+    o = oracle.forward(x, c)
+    ridge = ridge_bins(w.inst_freq(w.frame_times()), c.fs, c.nfft, o.band.k1, c.subdiv,
+                       o.band.n_dst)
+    for q in range(ridge.shape[0]):
+        oracle.inverse(o.T, ridge[q], c.hw, o.g, c.hop, c.nfft, o.band.k1, c.subdiv, w.n)
+    dt = time.perf_counter() - t0
+    return {"value": n_sample / dt / 1e6, "unit": "Msamples/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"first {n_sample} samples of the workload ({n_sample / (1 << 20):.3g} of "
+                      f"it), whole pipeline in float64, {dt:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=1 << 20, help="signal length (default 2^20)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=1 << 18)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="also run one device copy of this many MiB (counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(sharding is described in DESIGN.md); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2003_07065_amd as sst
+    from workloads import make_c2, ridge_bins
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        sys.exit(2)
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+
+    w = make_c2(n=args.n)
+    c = w.cfg
+    plan = sst.Plan.from_config(w.n, c, device=dev)
+    xg = torch.from_numpy(w.x).to(dev)
+    T = torch.empty((plan.n_frames, plan.n_dst), dtype=torch.complex64, device=dev)
+    f_true = w.inst_freq(w.frame_times())
+    ridge_true = ridge_bins(f_true, c.fs, c.nfft, plan.k1, c.subdiv, plan.n_dst)
+    n_comp = ridge_true.shape[0]
+    # ridge search bands: +-8% around each component's nominal frequency
+    bands = []
+    for q in range(n_comp):
+        f0 = float(np.median(f_true[q]))
+        lo = int(math.floor(c.subdiv * (0.92 * f0 / c.delta_f - plan.k1)))
+        hi = int(math.ceil(c.subdiv * (1.08 * f0 / c.delta_f - plan.k1)))
+        bands.append((max(lo, 0), min(hi, plan.n_dst - 1)))
+    ridge = torch.empty((n_comp, plan.n_frames), dtype=torch.int32, device=dev)
+    xhat = torch.empty((n_comp, w.n), dtype=torch.float32, device=dev)
+    xref = torch.from_numpy(w.comps.astype(np.float32)).to(dev)
+    err = torch.zeros((n_comp, 2), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream(dev)
+
+    def step(evs=None):
+        if evs:
+            evs[0].record(stream)
+        plan.forward(xg, T, 0, 0)                          # gamma: pre-pass over every frame
+        if evs:
+            evs[1].record(stream)
+        plan.forward(xg, T, 0, plan.n_frames, reuse_gamma=True)   # fused forward kernel
+        if evs:
+            evs[2].record(stream)
+        plan.ridge(T, bands, out=ridge)
+        if evs:
+            evs[3].record(stream)
+        plan.inverse(T, ridge, c.hw, xhat=xhat)
+        if evs:
+            evs[4].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    seg = np.array([[evs[k][i].elapsed_time(evs[k][i + 1]) for i in range(4)]
+                    for k in range(args.steps)])          # ms
+    step_ms = np.array([evs[k][0].elapsed_time(evs[k][4]) for k in range(args.steps)])
+    total_ms = float(step_ms.sum())
+    ms_per_step = total_ms / args.steps
+    value = w.n * args.steps / (total_ms / 1e3) / 1e6
+
+    # Accuracy of the timed result: SNR of every component (Eq. 33, FP64 on the GPU).
+    plan.inverse(T, ridge, c.hw, xhat=xhat, xref=xref, err=err)
+    torch.cuda.synchronize()
+    e = err.cpu().numpy()
+    snr = [float(10.0 * np.log10(e[q, 1] / e[q, 0])) for q in range(n_comp)]
+    ridge_hit = float((ridge.cpu().numpy() == ridge_true).mean())
+
+    calib = None
+    if args.calib_copy_mib > 0:
+        nb = args.calib_copy_mib << 20
+        a = torch.empty(nb // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        calib = {"copy_bytes_each_way": nb}
+
+    fwd_ms = float(np.mean(seg[:, 1]))
+    thr_ms = float(np.mean(seg[:, 0]))
+    ridge_ms = float(np.mean(seg[:, 2]))
+    inv_ms = float(np.mean(seg[:, 3]))
+    t_bytes = 8 * plan.n_dst * plan.n_frames
+    x_bytes = 4 * w.n
+    fwd_alg_bytes = t_bytes + x_bytes
+    achieved = fwd_alg_bytes / (fwd_ms / 1e3) / 1e9
+    traffic = load_traffic("c2")
+    roof = {"kernel": "fwd_kernel<4096,4> (fused framing + FFT pair + IF + reassignment)",
+            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": (traffic or {}).get("bytes_per_launch"),
+            "algorithmic_bytes_per_launch": fwd_alg_bytes,
+            "avg_launch_ms": round(fwd_ms, 4)}
+    # whole-step HBM roofline: every algorithmic byte of the step at peak bandwidth
+    inv_bytes = n_comp * (8 * (2 * c.hw + 1) * plan.n_frames + 4 * w.n)
+    step_bytes = fwd_alg_bytes + inv_bytes + x_bytes
+    out = {
+        "metric": METRIC, "value": round(value, 2), "unit": "Msamples/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "downsampled SST + direct inverse, one channel, N=2^20 at "
+                               "25.6 kHz, 3 AM-FM components + white noise 10 dB (seed 0), "
+                               "Gaussian L=1023 sigma=128, H=16, N_f=4096, band [0, 6.4 kHz], "
+                               "z=4, gamma=1e-3 max|S|, 3 ridges hw=6",
+                   "n_samples": w.n, "n_frames": plan.n_frames, "n_dst": plan.n_dst,
+                   "T_bytes": t_bytes},
+        "roofline": roof,
+        "segments_ms": {"threshold_prepass": round(thr_ms, 4), "forward": round(fwd_ms, 4),
+                        "ridge": round(ridge_ms, 4), "inverse": round(inv_ms, 4)},
+        "step_hbm_roofline_frac": round(step_bytes / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+        "accuracy": {"snr_db": [round(s, 3) for s in snr], "ridge_equals_true_if_bin": ridge_hit},
+        "wall_s": round(wall, 3),
+        "kernel_source_sha256_16": kernel_source_hash(),
+    }
+    if calib:
+        out["calibration"] = calib
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_sample)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

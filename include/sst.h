@@ -1,0 +1,239 @@
+/*
+ * sst.h -- C ABI of the MI355X (gfx950) downsampled synchrosqueezing
+ * transform library.
+ *
+ * Method: D. He, H. Cao, "Fast implementation of synchrosqueezing transform
+ * based on downsampling for large-scale vibration signal analysis",
+ * arXiv 2003.07065.  The library computes
+ *   - the downsampled STFT pair S, S' with a Gaussian window g and its
+ *     derivative g' (Sec. 2.1, Eqs. 7-9; Sec. 2.2),
+ *   - the IF estimate and the selective, subdivided reassignment into the SST
+ *     matrix T (Sec. 2.2, Eqs. 12-14; Sec. 2.4, Eqs. 27-29),
+ *   - ridges per component (Sec. 2.2, the zone M_q[m]),
+ *   - the direct downsampled inverse (Sec. 2.3, Eqs. 25-26, with the band /
+ *     subdivision remark closing Sec. 2.5) and the standard hop-1 inverse
+ *     (Sec. 2.2, Eq. 15).
+ *
+ * Conventions used by every call:
+ *   - sigma, window taps and hops are in samples; window index j in [-M, M],
+ *     M = (L-1)/2; frame m is centred at sample m*H, m = 0 .. ceil(N/H)-1;
+ *     x[n] = 0 outside [0, N);
+ *   - the band [f_lo, f_hi] is snapped outward to source bins k1..k2:
+ *     k1 = floor(f_lo/df + 1e-9), k2 = min(ceil(f_hi/df - 1e-9), N_f/2),
+ *     df = fs/N_f; n_src = k2-k1+1 source bins, n_dst = z*(k2-k1)+1
+ *     destination bins at f*_l = (k1 + l/z) df;
+ *   - a coefficient is retained when |S| > gamma and lands in destination
+ *     l = floor(z(|k - delta| - k1) + 1/2), delta = N_f Im(S'/S)/(2 pi);
+ *     destinations outside [0, n_dst) are dropped;
+ *   - complex arrays are interleaved float pairs (re, im), row-major;
+ *   - all device pointers are caller-owned HIP device memory on the device
+ *     that was current at sst_plan_bind; "stream" is a hipStream_t (NULL =
+ *     the default stream); every call is asynchronous on that stream unless
+ *     stated otherwise and never blocks the host;
+ *   - every function returns an sst_status; nothing throws or aborts across
+ *     the ABI.  On error, sst_last_error() returns a thread-local message.
+ *
+ * The library never allocates device memory: the caller binds one workspace
+ * buffer per plan (size from sst_plan_query).
+ */
+#ifndef SST_H
+#define SST_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t sst_status;
+
+#define SST_OK 0
+#define SST_E_ARG (-1)          /* invalid argument; see sst_last_error() */
+#define SST_E_UNSUPPORTED (-2)  /* valid for the method, not built here (e.g. N_f > 8192) */
+#define SST_E_WORKSPACE (-3)    /* workspace missing, misaligned or too small */
+#define SST_E_DEVICE (-4)       /* a HIP call failed; sst_last_error() names it */
+#define SST_E_STATE (-5)        /* plan not bound */
+#define SST_E_NOMEM (-6)        /* host allocation failed */
+
+/* Threshold modes (Sec. 2.2, Eq. 13: |S| > gamma). */
+#define SST_THR_ABS 0           /* gamma = thr */
+#define SST_THR_REL_MAX 1       /* gamma = thr * max |S| over every frame and in-band bin */
+
+/* STFT arithmetic of the forward transform. */
+#define SST_PREC_FP32_FFT 0     /* FP32 LDS FFT pair (the only precision built) */
+
+/* sst_forward flags */
+#define SST_FWD_REUSE_GAMMA 1u  /* keep the gamma computed by the previous forward call
+                                   on this plan (chunked calls after the first) */
+
+/* sst_inverse flags */
+#define SST_INV_ACCUMULATE 1u   /* add into xhat instead of overwriting it */
+#define SST_INV_EQ15 2u         /* standard inverse of Eq. 15 (hop must be 1) */
+
+/*
+ * Transform parameters, copied at plan time (Sec. 2.1, 2.2, 2.4).
+ *   struct_size  sizeof(sst_params), for forward compatibility
+ *   n_samples    N, signal length, >= 1
+ *   fs           sampling rate in Hz, > 0
+ *   win_len      L = 2M+1, odd, 1 <= L <= nfft
+ *   sigma        Gaussian width in samples, > 0 (ignored when window given)
+ *   window       optional host array of L doubles g[-M..M]; NULL = Gaussian
+ *   dwindow      optional host array of L doubles g'[-M..M]; required iff window
+ *   hop          H_t >= 1
+ *   nfft         N_f, power of two, 512 <= N_f <= 8192, L <= N_f
+ *   f_lo, f_hi   band of interest in Hz, 0 <= f_lo < f_hi <= fs/2
+ *   subdiv       z >= 1, z*N_f <= 2^20
+ *   thr_mode     SST_THR_ABS or SST_THR_REL_MAX
+ *   thr          gamma (ABS, >= 0) or rho (REL_MAX, >= 0)
+ *   precision    SST_PREC_FP32_FFT
+ *   flags        reserved, 0
+ */
+typedef struct {
+    uint32_t struct_size;
+    int64_t n_samples;
+    double fs;
+    int32_t win_len;
+    double sigma;
+    const double *window;
+    const double *dwindow;
+    int32_t hop;
+    int32_t nfft;
+    double f_lo;
+    double f_hi;
+    int32_t subdiv;
+    int32_t thr_mode;
+    double thr;
+    int32_t precision;
+    uint32_t flags;
+} sst_params;
+
+/* Shapes derived at plan time (sst_plan_query). */
+typedef struct {
+    int64_t n_samples;        /* N */
+    int64_t n_frames;         /* ceil(N / hop) */
+    int32_t win_len, hop, nfft, subdiv;
+    int32_t k1, k2;           /* source-bin band */
+    int32_t n_src;            /* k2 - k1 + 1 */
+    int32_t n_dst;            /* z (k2 - k1) + 1 */
+    size_t workspace_bytes;   /* device workspace the caller must bind */
+    size_t t_row_bytes;       /* 8 * n_dst: bytes of one T row (frame) */
+} sst_shape;
+
+typedef struct sst_plan_s *sst_plan_t;
+
+/*
+ * sst_plan -- validate parameters, build the float64 host tables (windows,
+ * centre-phase factors exp(i 2 pi (k M mod N_f)/N_f) of Eq. 9, inverse
+ * phasor tables) and choose kernel shapes.  Host only: no HIP call, no device
+ * allocation.  *out receives a plan owned by the caller (sst_destroy).
+ * Errors: SST_E_ARG (reason in sst_last_error), SST_E_UNSUPPORTED, SST_E_NOMEM.
+ */
+sst_status sst_plan(const sst_params *params, sst_plan_t *out);
+
+/* sst_plan_query -- fill *out (host only). */
+sst_status sst_plan_query(sst_plan_t plan, sst_shape *out);
+
+/*
+ * sst_plan_bind -- attach a caller-owned device workspace of at least
+ * workspace_bytes bytes (256-byte aligned) and upload the plan's tables with
+ * one asynchronous host-to-device copy on `stream`.  The plan keeps the host
+ * tables alive, so the call returns at once.  Binding again replaces the
+ * workspace.  Errors: SST_E_WORKSPACE, SST_E_DEVICE.
+ */
+sst_status sst_plan_bind(sst_plan_t plan, void *workspace_dev, size_t bytes, void *stream);
+
+/*
+ * Optional per-coefficient / per-frame outputs of sst_forward (debug and
+ * parity).  Every pointer may be NULL.  Rows cover the frames of the call.
+ *   S        complex float [nframes][n_src]: S[m, k1 + i] of Eq. 9
+ *   Sd       complex float [nframes][n_src]: S'[m, k1 + i] (g' window)
+ *   idx      int32 [nframes][n_src]: destination l, -1 below threshold,
+ *            -2 destination outside [0, n_dst)
+ *   colstats double [nframes][3]: sum_l Re T, sum_l Im T, sum_l |T|^2,
+ *            accumulated in FP64 from the FP32 row of T
+ *   gamma    float [1]: the threshold gamma used by the call
+ */
+typedef struct {
+    float *S;
+    float *Sd;
+    int32_t *idx;
+    double *colstats;
+    float *gamma;
+} sst_fwd_aux;
+
+/*
+ * sst_forward -- forward SST of frames [frame0, frame0 + nframes) of x
+ * (Eqs. 7-9, 12-14, 27-29): framing with g and g', FP32 FFT pair of size N_f,
+ * IF estimate, threshold, selective subdivided reassignment into T.
+ *   x        device float [n_samples]; read only
+ *   T        device complex float [nframes][n_dst], row r = frame frame0 + r;
+ *            every element of the rows is written (zeros included)
+ *   aux      optional outputs, may be NULL
+ *   flags    0 or SST_FWD_REUSE_GAMMA
+ * With SST_THR_REL_MAX and no SST_FWD_REUSE_GAMMA the call first computes
+ * max |S| over ALL frames of x (not only the chunk).  Calls on one plan share
+ * the workspace: calls that overlap in time on different streams race.
+ * Errors: SST_E_ARG (range, NULL x/T), SST_E_STATE, SST_E_DEVICE.
+ */
+sst_status sst_forward(sst_plan_t plan, const float *x, int64_t frame0, int64_t nframes,
+                       float *T, const sst_fwd_aux *aux, uint32_t flags, void *stream);
+
+/*
+ * sst_ridge -- ridge of each component (Sec. 2.2, zone M_q[m]): for every
+ * frame of the chunk and component q, the destination bin of largest |T| in
+ * [band[2q], band[2q+1]] (clipped to [0, n_dst)); ties go to the smallest l;
+ * -1 when the range is all zero.
+ *   T        device complex float [nframes][n_dst]
+ *   band     host int32 [2 n_comp]: inclusive destination-bin ranges
+ *   ridge    device int32 [n_comp][nframes]
+ * Errors: SST_E_ARG, SST_E_STATE, SST_E_DEVICE.
+ */
+sst_status sst_ridge(sst_plan_t plan, const float *T, int64_t nframes, const int32_t *band,
+                     int32_t n_comp, int32_t *ridge, void *stream);
+
+/*
+ * sst_inverse -- direct downsampled inverse (Eqs. 25-26; zN_f grid for z > 1)
+ * of n_comp components from the T rows of frames [frame0, frame0 + nframes):
+ *   r[m,j] = (1/N_f) sum_{l in zone} a_l Re(T[m,l] e^{i 2 pi ((z k1 + l) j mod z N_f)/(z N_f)})
+ *   xhat_q[n] += sum_{m in chunk} g[n - mH] r[m, n - mH] / sum_{all m} g[0] g[n - mH]
+ * zone = [ridge - hw, ridge + hw] intersected with [0, n_dst); a_l = 2 except 1 at
+ * DC and at fs/2.  The denominator runs over every frame of the signal, so
+ * chunked calls with SST_INV_ACCUMULATE sum to the whole-signal result.
+ * Without SST_INV_ACCUMULATE the samples the chunk reaches are overwritten.
+ * With SST_INV_EQ15 (hop 1 only): xhat_q[m] = (1/(N_f g[0])) sum_zone a_l Re T[m,l].
+ *   T        device complex float [nframes][n_dst]
+ *   ridge    device int32 [n_comp][nframes]; -1 = no contribution from that frame
+ *   hw       zone half-width in destination bins, >= 0
+ *   xhat     device float [n_comp][n_samples]
+ *   xref     optional device float [n_comp][n_samples] (noise-free components)
+ *   err      optional device double [n_comp][2]: sum (xref - xhat)^2 and sum xref^2
+ *            over n in [M, N - M), FP64 (Eq. 33); needs xref and a whole-signal call
+ * Errors: SST_E_ARG, SST_E_STATE, SST_E_DEVICE.
+ */
+sst_status sst_inverse(sst_plan_t plan, const float *T, int64_t frame0, int64_t nframes,
+                       const int32_t *ridge, int32_t n_comp, int32_t hw, float *xhat,
+                       const float *xref, double *err, uint32_t flags, void *stream);
+
+/* sst_destroy -- release the plan's host memory (the workspace stays the caller's). */
+void sst_destroy(sst_plan_t plan);
+
+/* sst_status_string -- static text for a status code. */
+const char *sst_status_string(sst_status status);
+
+/* sst_last_error -- thread-local detail of the last failing call on this thread. */
+const char *sst_last_error(void);
+
+/*
+ * sst_critical_hf -- plan-time advisory bounds on H_f = N/N_f (Sec. 4):
+ *   Eq. 38: H_f < 3N / (4 pi sigma fs)           (reassignment still acts)
+ *   Eq. 46: H_f < sqrt(2) N / (2 pi sigma fs)    (no global reassignment)
+ * sigma_s in seconds.  Host only.  Errors: SST_E_ARG for non-positive inputs.
+ */
+sst_status sst_critical_hf(double n, double sigma_s, double fs, double *eq38, double *eq46);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SST_H */

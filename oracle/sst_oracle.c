@@ -122,11 +122,12 @@ static void sso_stft_frame(const double *x, int64_t n, const double *g, const do
 {
     for (int k = k1; k <= k2; ++k) {
         double sr = 0.0, si = 0.0, dr = 0.0, di = 0.0;
-        for (int j = -M; j <= M; ++j) {
+        /* r = (k j) mod N_f, stepped exactly in integers as j increases */
+        int64_t r = sso_mod((int64_t)k * (-M), nfft);
+        for (int j = -M; j <= M; ++j, r = (r + k >= nfft) ? r + k - nfft : r + k) {
             int64_t idx = c + j;
             if (idx < 0 || idx >= n)
                 continue;
-            int64_t r = sso_mod((int64_t)k * j, nfft);
             double xv = x[idx];
             double a = xv * g[j + M];
             sr += a * wre[r];

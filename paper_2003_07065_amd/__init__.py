@@ -1,0 +1,318 @@
+"""Python binding of the gfx950 downsampled SST library (libsst_hip.so).
+
+Argument marshalling only: every step of the transform runs in the HIP kernels
+behind the C ABI of include/sst.h.  PyTorch provides device memory and the
+current stream.  There is no CPU fallback: importing works without a GPU, but
+every call that reaches the library needs the built shared object and a HIP
+device, and raises otherwise.
+
+Names mirror the C ABI: ``Plan`` wraps sst_plan / sst_plan_query /
+sst_plan_bind / sst_destroy, and its methods ``forward``, ``ridge`` and
+``inverse`` wrap sst_forward, sst_ridge and sst_inverse.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsst_hip.so")
+
+SST_OK = 0
+SST_E_ARG = -1
+SST_E_UNSUPPORTED = -2
+SST_E_WORKSPACE = -3
+SST_E_DEVICE = -4
+SST_E_STATE = -5
+SST_E_NOMEM = -6
+
+SST_THR_ABS = 0
+SST_THR_REL_MAX = 1
+SST_PREC_FP32_FFT = 0
+SST_FWD_REUSE_GAMMA = 1
+SST_INV_ACCUMULATE = 1
+SST_INV_EQ15 = 2
+
+EXPORTED = ("sst_plan", "sst_plan_query", "sst_plan_bind", "sst_forward", "sst_ridge",
+            "sst_inverse", "sst_destroy", "sst_status_string", "sst_last_error",
+            "sst_critical_hf")
+
+
+class SSTError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where}: status {status}: {detail}")
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32),
+        ("n_samples", ctypes.c_int64),
+        ("fs", ctypes.c_double),
+        ("win_len", ctypes.c_int32),
+        ("sigma", ctypes.c_double),
+        ("window", ctypes.POINTER(ctypes.c_double)),
+        ("dwindow", ctypes.POINTER(ctypes.c_double)),
+        ("hop", ctypes.c_int32),
+        ("nfft", ctypes.c_int32),
+        ("f_lo", ctypes.c_double),
+        ("f_hi", ctypes.c_double),
+        ("subdiv", ctypes.c_int32),
+        ("thr_mode", ctypes.c_int32),
+        ("thr", ctypes.c_double),
+        ("precision", ctypes.c_int32),
+        ("flags", ctypes.c_uint32),
+    ]
+
+
+class Shape(ctypes.Structure):
+    _fields_ = [
+        ("n_samples", ctypes.c_int64),
+        ("n_frames", ctypes.c_int64),
+        ("win_len", ctypes.c_int32),
+        ("hop", ctypes.c_int32),
+        ("nfft", ctypes.c_int32),
+        ("subdiv", ctypes.c_int32),
+        ("k1", ctypes.c_int32),
+        ("k2", ctypes.c_int32),
+        ("n_src", ctypes.c_int32),
+        ("n_dst", ctypes.c_int32),
+        ("workspace_bytes", ctypes.c_size_t),
+        ("t_row_bytes", ctypes.c_size_t),
+    ]
+
+
+class FwdAux(ctypes.Structure):
+    _fields_ = [
+        ("S", ctypes.c_void_p),
+        ("Sd", ctypes.c_void_p),
+        ("idx", ctypes.c_void_p),
+        ("colstats", ctypes.c_void_p),
+        ("gamma", ctypes.c_void_p),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded C library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                          "(hipcc, gfx950); there is no fallback path")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+    L.sst_plan.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(vp)]
+    L.sst_plan_query.argtypes = [vp, ctypes.POINTER(Shape)]
+    L.sst_plan_bind.argtypes = [vp, vp, ctypes.c_size_t, vp]
+    L.sst_forward.argtypes = [vp, vp, i64, i64, vp, ctypes.POINTER(FwdAux), u32, vp]
+    L.sst_ridge.argtypes = [vp, vp, i64, ctypes.POINTER(i32), i32, vp, vp]
+    L.sst_inverse.argtypes = [vp, vp, i64, i64, vp, i32, i32, vp, vp, vp, u32, vp]
+    L.sst_destroy.argtypes = [vp]
+    L.sst_destroy.restype = None
+    L.sst_status_string.argtypes = [i32]
+    L.sst_status_string.restype = ctypes.c_char_p
+    L.sst_last_error.argtypes = []
+    L.sst_last_error.restype = ctypes.c_char_p
+    L.sst_critical_hf.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                  ctypes.POINTER(ctypes.c_double),
+                                  ctypes.POINTER(ctypes.c_double)]
+    for name in ("sst_plan", "sst_plan_query", "sst_plan_bind", "sst_forward", "sst_ridge",
+                 "sst_inverse", "sst_critical_hf"):
+        getattr(L, name).restype = i32
+    _lib = L
+    return L
+
+
+def _check(status: int, where: str):
+    if status != SST_OK:
+        detail = lib().sst_last_error().decode(errors="replace")
+        raise SSTError(status, where, detail)
+
+
+def status_string(status: int) -> str:
+    return lib().sst_status_string(int(status)).decode()
+
+
+def critical_hf(n: float, sigma_s: float, fs: float):
+    """Advisory H_f bounds of Eq. 38 and Eq. 46 (host only)."""
+    a, b = ctypes.c_double(), ctypes.c_double()
+    _check(lib().sst_critical_hf(float(n), float(sigma_s), float(fs), ctypes.byref(a),
+                                 ctypes.byref(b)), "sst_critical_hf")
+    return a.value, b.value
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else int(t.data_ptr())
+
+
+def _stream_handle(device) -> int:
+    import torch
+    return int(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Plan:
+    """A transform plan (host tables) bound to a torch-allocated device workspace."""
+
+    def __init__(self, n_samples: int, fs: float, win_len: int, sigma: float, hop: int,
+                 nfft: int, f_lo: float, f_hi: float, subdiv: int = 1, thr_mode: str = "rel",
+                 thr: float = 1e-3, window=None, dwindow=None, device=None):
+        self._h = None
+        p = Params()
+        p.struct_size = ctypes.sizeof(Params)
+        p.n_samples = int(n_samples)
+        p.fs = float(fs)
+        p.win_len = int(win_len)
+        p.sigma = float(sigma)
+        keep = []
+        if window is not None:
+            import numpy as np
+            w = np.ascontiguousarray(np.asarray(window, dtype=np.float64))
+            dw = np.ascontiguousarray(np.asarray(dwindow, dtype=np.float64))
+            keep += [w, dw]
+            p.window = w.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            p.dwindow = dw.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        p.hop = int(hop)
+        p.nfft = int(nfft)
+        p.f_lo = float(f_lo)
+        p.f_hi = float(f_hi)
+        p.subdiv = int(subdiv)
+        p.thr_mode = SST_THR_ABS if thr_mode == "abs" else SST_THR_REL_MAX
+        p.thr = float(thr)
+        p.precision = SST_PREC_FP32_FFT
+        p.flags = 0
+        h = ctypes.c_void_p()
+        _check(lib().sst_plan(ctypes.byref(p), ctypes.byref(h)), "sst_plan")
+        self._h = h
+        sh = Shape()
+        _check(lib().sst_plan_query(self._h, ctypes.byref(sh)), "sst_plan_query")
+        self.shape = sh
+        self.n_samples = sh.n_samples
+        self.n_frames = sh.n_frames
+        self.k1, self.k2 = sh.k1, sh.k2
+        self.n_src, self.n_dst = sh.n_src, sh.n_dst
+        self.nfft, self.hop, self.subdiv, self.win_len = sh.nfft, sh.hop, sh.subdiv, sh.win_len
+        self.workspace = None
+        self.device = None
+        if device is not None:
+            self.bind(device)
+
+    @classmethod
+    def from_config(cls, n_samples: int, cfg, device=None) -> "Plan":
+        return cls(n_samples, cfg.fs, cfg.win_len, cfg.sigma, cfg.hop, cfg.nfft, cfg.f_lo,
+                   cfg.f_hi, cfg.subdiv, cfg.thr_mode, cfg.thr, device=device)
+
+    def bind(self, device="cuda"):
+        import torch
+        device = torch.device(device)
+        if device.type != "cuda":
+            raise ValueError("the workspace must live on a HIP device")
+        if device.index is None:
+            device = torch.device("cuda", torch.cuda.current_device())
+        with torch.cuda.device(device):
+            ws = torch.empty(int(self.shape.workspace_bytes) + 256, dtype=torch.uint8,
+                             device=device)
+            off = (-int(ws.data_ptr())) % 256
+            base = int(ws.data_ptr()) + off
+            _check(lib().sst_plan_bind(self._h, ctypes.c_void_p(base),
+                                       ctypes.c_size_t(self.shape.workspace_bytes),
+                                       ctypes.c_void_p(_stream_handle(device))),
+                   "sst_plan_bind")
+        self.workspace = ws
+        self.device = device
+        return self
+
+    def _need_bound(self):
+        if self.workspace is None:
+            raise SSTError(SST_E_STATE, "Plan", "bind() the plan to a device first")
+
+    def forward(self, x, T=None, frame0: int = 0, nframes: Optional[int] = None, *,
+                S=None, Sd=None, idx=None, colstats=None, gamma=None,
+                reuse_gamma: bool = False):
+        """SST rows of frames [frame0, frame0+nframes) into T (complex64 [nframes, n_dst])."""
+        import torch
+        self._need_bound()
+        if nframes is None:
+            nframes = self.n_frames - frame0
+        if x.dtype != torch.float32 or not x.is_contiguous() or x.device != self.device:
+            raise ValueError("x must be a contiguous float32 tensor on the plan's device")
+        if x.numel() != self.n_samples:
+            raise ValueError("x length differs from the plan's n_samples")
+        if T is None:
+            T = torch.empty((nframes, self.n_dst), dtype=torch.complex64, device=self.device)
+        if T.dtype != torch.complex64 or not T.is_contiguous() or T.numel() < nframes * self.n_dst:
+            raise ValueError("T must be a contiguous complex64 tensor of nframes * n_dst")
+        for t, n, dt in ((S, self.n_src, torch.complex64), (Sd, self.n_src, torch.complex64),
+                         (idx, self.n_src, torch.int32), (colstats, 3, torch.float64)):
+            if t is not None and (t.dtype != dt or not t.is_contiguous()
+                                  or t.numel() < nframes * n):
+                raise ValueError("debug output has the wrong dtype or size")
+        if gamma is not None and (gamma.dtype != torch.float32 or gamma.numel() < 1):
+            raise ValueError("gamma must be a float32 tensor with one element")
+        aux = FwdAux(_ptr(S), _ptr(Sd), _ptr(idx), _ptr(colstats), _ptr(gamma))
+        _check(lib().sst_forward(self._h, ctypes.c_void_p(x.data_ptr()), int(frame0),
+                                 int(nframes), ctypes.c_void_p(T.data_ptr()), ctypes.byref(aux),
+                                 SST_FWD_REUSE_GAMMA if reuse_gamma else 0,
+                                 ctypes.c_void_p(_stream_handle(self.device))), "sst_forward")
+        return T
+
+    def ridge(self, T, bands: Sequence[Sequence[int]], nframes: Optional[int] = None,
+              out=None):
+        """Per-frame argmax ridge of each component inside its destination-bin band."""
+        import torch
+        self._need_bound()
+        if nframes is None:
+            nframes = T.shape[0]
+        n_comp = len(bands)
+        arr = (ctypes.c_int32 * (2 * n_comp))(*[int(v) for b in bands for v in b])
+        if out is None:
+            out = torch.empty((n_comp, nframes), dtype=torch.int32, device=self.device)
+        _check(lib().sst_ridge(self._h, ctypes.c_void_p(T.data_ptr()), int(nframes), arr,
+                               n_comp, ctypes.c_void_p(out.data_ptr()),
+                               ctypes.c_void_p(_stream_handle(self.device))), "sst_ridge")
+        return out
+
+    def inverse(self, T, ridge, hw: int, xhat=None, frame0: int = 0,
+                nframes: Optional[int] = None, xref=None, err=None, accumulate: bool = False,
+                eq15: bool = False):
+        """Direct inverse (Eqs. 25-26, or Eq. 15 with eq15=True) of every ridge component."""
+        import torch
+        self._need_bound()
+        if nframes is None:
+            nframes = T.shape[0]
+        if ridge.dtype != torch.int32 or not ridge.is_contiguous():
+            raise ValueError("ridge must be a contiguous int32 tensor [n_comp, nframes]")
+        n_comp = ridge.shape[0] if ridge.dim() == 2 else 1
+        if ridge.numel() != n_comp * nframes:
+            raise ValueError("ridge must hold n_comp * nframes entries")
+        if xhat is None:
+            xhat = torch.empty((n_comp, self.n_samples), dtype=torch.float32, device=self.device)
+        if xhat.dtype != torch.float32 or xhat.numel() < n_comp * self.n_samples:
+            raise ValueError("xhat must be float32 [n_comp, n_samples]")
+        if xref is not None and (xref.dtype != torch.float32 or
+                                 xref.numel() < n_comp * self.n_samples):
+            raise ValueError("xref must be float32 [n_comp, n_samples]")
+        if err is not None and (err.dtype != torch.float64 or err.numel() < 2 * n_comp):
+            raise ValueError("err must be float64 [n_comp, 2]")
+        flags = (SST_INV_ACCUMULATE if accumulate else 0) | (SST_INV_EQ15 if eq15 else 0)
+        _check(lib().sst_inverse(self._h, ctypes.c_void_p(T.data_ptr()), int(frame0),
+                                 int(nframes), ctypes.c_void_p(ridge.data_ptr()), int(n_comp),
+                                 int(hw), ctypes.c_void_p(xhat.data_ptr()),
+                                 ctypes.c_void_p(_ptr(xref)), ctypes.c_void_p(_ptr(err)), flags,
+                                 ctypes.c_void_p(_stream_handle(self.device))), "sst_inverse")
+        return xhat
+
+    def close(self):
+        if self._h is not None and _lib is not None:
+            _lib.sst_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

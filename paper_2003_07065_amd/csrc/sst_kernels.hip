@@ -1,0 +1,949 @@
+// gfx950 kernels of the downsampled synchrosqueezing transform.
+//
+// Method: He & Cao, arXiv 2003.07065.
+//   fwd_kernel   -- framing with g and g' (Sec. 2.1, Eqs. 7-8), the N_f-point
+//                   FFT pair with centre phase (Eq. 9), the IF estimate and the
+//                   threshold (Sec. 2.2, Eqs. 12-13), and the selective,
+//                   subdivided reassignment (Eq. 14; Sec. 2.4, Eqs. 27-29)
+//                   into an LDS histogram that is streamed to HBM as rows of T.
+//   max_kernel   -- max |S| over every frame for the relative threshold.
+//   inv_kernel   -- the direct downsampled inverse (Sec. 2.3, Eqs. 25-26, zN_f
+//                   phase grid of the band / subdivision remark of Sec. 2.5).
+//   eq15_kernel  -- the standard hop-1 inverse (Sec. 2.2, Eq. 15).
+//   ridge_kernel -- per-frame argmax of |T| inside a band (zone M_q[m]).
+//
+// FFT layout.  A workgroup transforms V = max(N_f, 4096) complex points per
+// iteration: F = V / N_f frames of N_f points, NT = V / 16 threads.  Stockham
+// autosort passes of radix 16 (the last pass radix N_f / 256 or 16, plus a
+// radix-2 pass at N_f = 8192) run in place in LDS with two barriers per pass.
+// Every thread owns one radix-16 butterfly (or 16/R radix-R butterflies) per
+// pass.  The LDS index a is padded to a + a/16 so that the stride-16 writes of
+// the first pass and the contiguous reads of later passes are free of bank
+// conflicts.  Pass 1 reads the signal straight from HBM (coalesced: adjacent
+// lanes read adjacent samples) and skips the zero padding of Eq. 9: when the
+// window is at most N_f/4 (or N_f/2) long, only 4 (or 8) of each butterfly's 16
+// inputs can be non-zero and a pruned radix-16 is used.
+//
+// Packed pair.  g x and s g' x are transformed together as one complex signal
+// y = g x + i s g' x, s = ||g|| / ||g'||, which keeps both halves at the same
+// scale so that neither loses precision in the shared FFT.  With Y = FFT(y):
+//   A[k] = (Y[k] + conj Y[N-k]) / 2 = FFT(g x)[k],
+//   B[k] = (Y[k] - conj Y[N-k]) / 2i = s FFT(g' x)[k].
+// The centre phase of Eq. 9 multiplies A and B alike, so it cancels in
+// Im(S' conj S) and is applied only to the values written out.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sst_internal.h"
+
+namespace sst {
+namespace {
+
+typedef float v2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ v2 mk(float a, float b)
+{
+    v2 r;
+    r.x = a;
+    r.y = b;
+    return r;
+}
+__device__ __forceinline__ v2 cmul(v2 a, v2 b)
+{
+    return mk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ v2 mul_mi(v2 a) { return mk(a.y, -a.x); }   // -i a
+__device__ __forceinline__ v2 conjv(v2 a) { return mk(a.x, -a.y); }
+__device__ __forceinline__ int pad16(int a) { return a + (a >> 4); }
+
+// ---------------------------------------------------------------------------
+// Register DFTs (forward, exp(-i ...)), natural order in and out.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void bf4(v2 &a0, v2 &a1, v2 &a2, v2 &a3)
+{
+    v2 t0 = a0 + a2, t1 = a0 - a2, t2 = a1 + a3, t3 = a1 - a3;
+    a0 = t0 + t2;
+    a2 = t0 - t2;
+    a1 = t1 + mul_mi(t3);
+    a3 = t1 - mul_mi(t3);
+}
+
+constexpr float kC1 = 0.92387953251128674f;  // cos(pi/8)
+constexpr float kS1 = 0.38268343236508978f;  // sin(pi/8)
+constexpr float kR2 = 0.70710678118654752f;  // sqrt(1/2)
+
+// Inner twiddles of the 4 x 4 radix-16: a[n2 + 4 k1] *= W16^(n2 k1).
+__device__ __forceinline__ void tw16(v2 *a)
+{
+    a[5] = cmul(a[5], mk(kC1, -kS1));    // W^1
+    a[9] = cmul(a[9], mk(kR2, -kR2));    // W^2
+    a[13] = cmul(a[13], mk(kS1, -kC1));  // W^3
+    a[6] = cmul(a[6], mk(kR2, -kR2));    // W^2
+    a[10] = mul_mi(a[10]);               // W^4
+    a[14] = cmul(a[14], mk(-kR2, -kR2)); // W^6
+    a[7] = cmul(a[7], mk(kS1, -kC1));    // W^3
+    a[11] = cmul(a[11], mk(-kR2, -kR2)); // W^6
+    a[15] = cmul(a[15], mk(-kC1, kS1));  // W^9
+}
+
+// Outer radix-4 over n2 for every k1, then the transposition to natural order.
+__device__ __forceinline__ void outer16(v2 *a)
+{
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1)
+        bf4(a[4 * k1], a[4 * k1 + 1], a[4 * k1 + 2], a[4 * k1 + 3]);
+    v2 b[16];
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1)
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2)
+            b[k1 + 4 * k2] = a[4 * k1 + k2];
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+        a[i] = b[i];
+}
+
+// Full radix-16: n = 4 n1 + n2, k = k1 + 4 k2.
+__device__ __forceinline__ void dft16(v2 *a)
+{
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2)
+        bf4(a[n2], a[n2 + 4], a[n2 + 8], a[n2 + 12]);
+    tw16(a);
+    outer16(a);
+}
+
+// Radix-16 whose inputs 4..15 are zero (n1 = 0 only).
+__device__ __forceinline__ void dft16_nz4(v2 *a)
+{
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+        a[n2 + 4] = a[n2];
+        a[n2 + 8] = a[n2];
+        a[n2 + 12] = a[n2];
+    }
+    tw16(a);
+    outer16(a);
+}
+
+// Radix-16 whose inputs 8..15 are zero (n1 in {0, 1}).
+__device__ __forceinline__ void dft16_nz8(v2 *a)
+{
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+        v2 p = a[n2], q = a[n2 + 4];
+        a[n2] = p + q;
+        a[n2 + 4] = p + mul_mi(q);
+        a[n2 + 8] = p - q;
+        a[n2 + 12] = p - mul_mi(q);
+    }
+    tw16(a);
+    outer16(a);
+}
+
+__device__ __forceinline__ void dft8(v2 *a)
+{
+    v2 e0 = a[0], e1 = a[2], e2 = a[4], e3 = a[6];
+    v2 o0 = a[1], o1 = a[3], o2 = a[5], o3 = a[7];
+    bf4(e0, e1, e2, e3);
+    bf4(o0, o1, o2, o3);
+    o1 = mk(kR2 * (o1.x + o1.y), kR2 * (o1.y - o1.x));    // * W8^1
+    o2 = mul_mi(o2);                                      // * W8^2
+    o3 = mk(kR2 * (o3.y - o3.x), -kR2 * (o3.x + o3.y));   // * W8^3
+    a[0] = e0 + o0;
+    a[4] = e0 - o0;
+    a[1] = e1 + o1;
+    a[5] = e1 - o1;
+    a[2] = e2 + o2;
+    a[6] = e2 - o2;
+    a[3] = e3 + o3;
+    a[7] = e3 - o3;
+}
+
+template <int R>
+__device__ __forceinline__ void dftR(v2 *a);
+template <>
+__device__ __forceinline__ void dftR<2>(v2 *a)
+{
+    v2 t = a[0];
+    a[0] = t + a[1];
+    a[1] = t - a[1];
+}
+template <>
+__device__ __forceinline__ void dftR<4>(v2 *a) { bf4(a[0], a[1], a[2], a[3]); }
+template <>
+__device__ __forceinline__ void dftR<8>(v2 *a) { dft8(a); }
+template <>
+__device__ __forceinline__ void dftR<16>(v2 *a) { dft16(a); }
+
+// ---------------------------------------------------------------------------
+// Geometry per DFT size.
+// ---------------------------------------------------------------------------
+
+template <int NF>
+struct Geo {
+    static constexpr int V = NF > 4096 ? NF : 4096;   // points per iteration
+    static constexpr int F = V / NF;                  // frames per iteration
+    static constexpr int NT = V / 16;                 // threads per workgroup
+    static constexpr int LDS = V + V / 16;            // padded float2 capacity
+    // separate LDS histogram (float2 entries): F * n_dst bins in one chunk for
+    // every configuration with F * n_dst <= HIST; larger rows are chunked
+    static constexpr int HIST = NF == 8192 ? 10240 : 4608;
+    static constexpr int R3 = NF >= 4096 ? 16 : NF / 256;  // radix of pass 3
+    static constexpr bool P4 = NF == 8192;            // radix-2 pass 4
+};
+
+// One Stockham pass of radix R and stride NS over the F frames in LDS.
+template <int NF, int R, int NS>
+struct Pass {
+    using G = Geo<NF>;
+    static constexpr int NR = NF / R;
+    static constexpr int NB = (NF * G::F / R) / G::NT;   // butterflies per thread
+    static constexpr int NTW = NS > 1 ? NB * (R - 1) : 1;
+
+    static __device__ __forceinline__ void load_tw(v2 *tw, const v2 *__restrict__ twid)
+    {
+        if (NS == 1)
+            return;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int j = threadIdx.x + b * G::NT;
+            const int k = (j % NR) % NS;
+#pragma unroll
+            for (int r = 1; r < R; ++r)
+                tw[b * (R - 1) + r - 1] = twid[(unsigned)((NF / (NS * R)) * k * r)];
+        }
+    }
+
+    static __device__ __forceinline__ void run(v2 *lds, const v2 *tw)
+    {
+        v2 v[NB][R];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int j = threadIdx.x + b * G::NT;
+            const int f = j / NR, jj = j % NR;
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                v[b][r] = lds[pad16(f * NF + jj + r * NR)];
+            if (NS > 1) {
+#pragma unroll
+                for (int r = 1; r < R; ++r)
+                    v[b][r] = cmul(v[b][r], tw[b * (R - 1) + r - 1]);
+            }
+            dftR<R>(v[b]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int j = threadIdx.x + b * G::NT;
+            const int f = j / NR, jj = j % NR;
+            const int k = jj % NS;
+            const int base = f * NF + (jj / NS) * NS * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                lds[pad16(base + r * NS)] = v[b][r];
+        }
+        __syncthreads();
+    }
+};
+
+// Twiddles of passes 2..4 held in registers for the kernel's lifetime.
+template <int NF>
+struct Twiddles {
+    using G = Geo<NF>;
+    using P2 = Pass<NF, 16, 16>;
+    using P3 = Pass<NF, G::R3, 256>;
+    using P4 = Pass<NF, 2, 4096>;
+    v2 t2[P2::NTW];
+    v2 t3[P3::NTW];
+    v2 t4[G::P4 ? P4::NTW : 1];
+
+    __device__ __forceinline__ void load(const v2 *twid)
+    {
+        P2::load_tw(t2, twid);
+        P3::load_tw(t3, twid);
+        if constexpr (G::P4)
+            P4::load_tw(t4, twid);
+    }
+    __device__ __forceinline__ void passes(v2 *lds) const
+    {
+        P2::run(lds, t2);
+        P3::run(lds, t3);
+        if constexpr (G::P4)
+            P4::run(lds, t4);
+    }
+};
+
+// Pass 1 (radix 16, stride 1): each thread's 16 inputs come from HBM through
+// `load(f, n)`; the outputs go to LDS.  Only the first NZ of the 16 inputs can
+// be non-zero (NZ = 4, 8 or 16 covers ceil(L / (N_f/16)) rows of taps).
+template <int NF, int NZ, typename Loader>
+__device__ __forceinline__ void pass1(v2 *lds, const Loader &load)
+{
+    constexpr int Q = NF / 16;
+    const int f = threadIdx.x / Q, jj = threadIdx.x % Q;
+    v2 v[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+        v[r] = (r < NZ) ? load(f, jj + r * Q) : mk(0.f, 0.f);
+    if constexpr (NZ == 4)
+        dft16_nz4(v);
+    else if constexpr (NZ == 8)
+        dft16_nz8(v);
+    else
+        dft16(v);
+    const int base = f * NF + jj * 16;
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+        lds[pad16(base + r)] = v[r];
+    __syncthreads();
+}
+
+// Flat coefficient e of an iteration -> (frame f, in-band offset ik).
+__device__ __forceinline__ void split_flat(int e, int n_src, float inv_nsrc, int &f, int &ik)
+{
+    int q = (int)(((float)e + 0.5f) * inv_nsrc);
+    if (q * n_src > e)
+        --q;
+    else if ((q + 1) * n_src <= e)
+        ++q;
+    f = q;
+    ik = e - q * n_src;
+}
+
+// ---------------------------------------------------------------------------
+// Forward kernel: framing, FFT pair, IF, threshold, reassignment, T rows.
+//
+// LDS: the FFT buffer and a separate destination histogram.  The IF stage
+// scatters straight into the histogram; the store phase reads each bin, writes
+// it to HBM and zeroes it for the next iteration, so the histogram needs no
+// separate clearing pass.
+// ---------------------------------------------------------------------------
+
+template <int NF, int NZ>
+__global__ __launch_bounds__(Geo<NF>::NT, 2) void fwd_kernel(FwdArgs a)
+{
+    using G = Geo<NF>;
+    constexpr int F = G::F, NT = G::NT, CAP = G::HIST;
+    __shared__ v2 lds[G::LDS];
+    __shared__ v2 hist[G::HIST];
+    __shared__ double colacc[3 * F];
+    float *histf = reinterpret_cast<float *>(hist);
+
+    Twiddles<NF> tw;
+    tw.load(reinterpret_cast<const v2 *>(a.twid));
+
+    const v2 *__restrict__ win = reinterpret_cast<const v2 *>(a.win);
+    const v2 *__restrict__ cph = reinterpret_cast<const v2 *>(a.cphase);
+    const float *__restrict__ x = a.x;
+    const float gamma2 = a.ctrl->gamma2;
+    const float inv_nsrc = 1.0f / (float)a.n_src;
+    const int64_t n_iter = (a.nframes + F - 1) / F;
+
+    for (int e = threadIdx.x; e < CAP; e += NT)
+        hist[e] = mk(0.f, 0.f);
+    if (threadIdx.x < 3 * F)
+        colacc[threadIdx.x] = 0.0;
+    // (the barriers of the first FFT order these stores before any use)
+
+    for (int64_t it = blockIdx.x; it < n_iter; it += gridDim.x) {
+        const int64_t m0 = it * F;   // first frame of the iteration, relative to frame0
+        const int nvalid = (int)((a.nframes - m0) < F ? (a.nframes - m0) : F);
+
+        // Eq. 8: frame m covers samples mH - M .. mH + M; tap n = j + M.
+        // Tap 0 of frame m0; signals are limited to 2^30 samples so sample
+        // indices fit 32 bits.
+        const int cm = (int)((a.frame0 + m0) * (int64_t)a.hop - a.M);
+        pass1<NF, NZ>(lds, [&](int f, int n) -> v2 {
+            // branch-free: clamp the addresses, zero the value when out of range
+            const int s = cm + f * a.hop + n;
+            const bool ok = (f < nvalid) & (n < a.L) & ((unsigned)s < (unsigned)a.n);
+            const float xv = x[ok ? (unsigned)s : 0u];
+            const v2 w = win[n < a.L ? (unsigned)n : 0u];
+            return (ok ? xv : 0.f) * w;
+        });
+        tw.passes(lds);
+
+        // Eqs. 12-13 and 27-29 for every in-band coefficient of the F frames,
+        // scattered into the destination bins [c0, c0 + CAP) of the flat
+        // (frame, l) index; one chunk unless F n_dst exceeds the histogram.
+        const int E = nvalid * a.n_src;
+        const int EH = nvalid * a.n_dst;
+        v2 *__restrict__ trow = reinterpret_cast<v2 *>(a.T) + m0 * (int64_t)a.n_dst;
+        for (int c0 = 0; c0 < EH; c0 += CAP) {
+            const int cn = (EH - c0) < CAP ? (EH - c0) : CAP;
+            for (int e = threadIdx.x; e < E; e += NT) {
+                int f, ik;
+                split_flat(e, a.n_src, inv_nsrc, f, ik);
+                const int k = a.k1 + ik;
+                const v2 P = lds[pad16(f * NF + k)];
+                const v2 Q = conjv(lds[pad16(f * NF + ((NF - k) & (NF - 1)))]);
+                const v2 A = 0.5f * (P + Q);
+                const v2 D = P - Q;
+                const v2 B = mk(0.5f * D.y, -0.5f * D.x);
+                const float mag2 = A.x * A.x + A.y * A.y;
+                const v2 ph = cph[(unsigned)ik];
+                const v2 S = cmul(ph, A);
+                int code = -1;
+                if (mag2 > gamma2) {
+                    const float im = B.y * A.x - B.x * A.y;   // Im(B conj A)
+                    const float delta = a.cdelta * im * __builtin_amdgcn_rcpf(mag2);
+                    const float zd = (float)a.z * delta;
+                    if (!(fabsf(zd) < 1.0e8f)) {
+                        code = -2;
+                    } else {
+                        int l;
+                        if (delta <= (float)k)   // kappa = k - delta
+                            l = a.z * (k - a.k1) + (int)floorf(0.5f - zd);
+                        else                     // kappa = delta - k
+                            l = (int)floorf(zd + 0.5f) - a.z * (k + a.k1);
+                        code = (l >= 0 && l < a.n_dst) ? l : -2;
+                    }
+                }
+                if (code >= 0) {
+                    const int d = f * a.n_dst + code - c0;
+                    if (d >= 0 && d < cn) {
+                        atomicAdd(&histf[2 * d], S.x);
+                        atomicAdd(&histf[2 * d + 1], S.y);
+                    }
+                }
+                if (c0 == 0) {
+                    if (a.S)
+                        reinterpret_cast<v2 *>(a.S)[m0 * a.n_src + (unsigned)e] = S;
+                    if (a.Sd)
+                        reinterpret_cast<v2 *>(a.Sd)[m0 * a.n_src + (unsigned)e] =
+                            a.inv_s * cmul(ph, B);
+                    if (a.idx)
+                        a.idx[m0 * a.n_src + (unsigned)e] = code;
+                }
+            }
+            __syncthreads();
+            for (int e = threadIdx.x; e < cn; e += NT) {
+                const v2 v = hist[e];
+                hist[e] = mk(0.f, 0.f);
+                __builtin_nontemporal_store(v, &trow[(unsigned)(c0 + e)]);
+                if (a.colstats) {
+                    const int f = (c0 + e) / a.n_dst;
+                    atomicAdd(&colacc[3 * f], (double)v.x);
+                    atomicAdd(&colacc[3 * f + 1], (double)v.y);
+                    atomicAdd(&colacc[3 * f + 2], (double)v.x * v.x + (double)v.y * v.y);
+                }
+            }
+            if (c0 + CAP < EH)
+                __syncthreads();   // bins zeroed before the next chunk's scatter
+        }
+        if (a.colstats) {
+            __syncthreads();
+            if (threadIdx.x < 3 * nvalid)
+                a.colstats[m0 * 3 + threadIdx.x] = colacc[threadIdx.x];
+            if (threadIdx.x < 3 * F)
+                colacc[threadIdx.x] = 0.0;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Threshold pre-pass: max |S|^2 over all frames, two frames per complex FFT.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ float wave_max(float v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+template <int NF, int NZ>
+__global__ __launch_bounds__(Geo<NF>::NT, (NF == 8192 || NZ == 16) ? 2 : 3) void max_kernel(MaxArgs a)
+{
+    using G = Geo<NF>;
+    constexpr int F = G::F, NT = G::NT;
+    __shared__ v2 lds[G::LDS];
+    __shared__ float red[NT / 64];
+
+    Twiddles<NF> tw;
+    tw.load(reinterpret_cast<const v2 *>(a.twid));
+    const v2 *__restrict__ win = reinterpret_cast<const v2 *>(a.win);
+    const float *__restrict__ x = a.x;
+    const float inv_nsrc = 1.0f / (float)a.n_src;
+    const int64_t n_pairs = (a.n_frames + 1) / 2;
+    const int64_t n_iter = (n_pairs + F - 1) / F;
+    float best = 0.f;
+
+    for (int64_t it = blockIdx.x; it < n_iter; it += gridDim.x) {
+        const int64_t p0 = it * F;
+        const int nvp = (int)((n_pairs - p0) < F ? (n_pairs - p0) : F);
+        __syncthreads();
+        const int cm = (int)(2 * p0 * (int64_t)a.hop - a.M);   // tap 0 of frame 2 p0
+        const int64_t fb_lim = a.n_frames - 2 * p0;   // frames 2 p0 + i exist for i < fb_lim
+        pass1<NF, NZ>(lds, [&](int f, int n) -> v2 {
+            const int sa = cm + 2 * f * a.hop + n;
+            const int sb = sa + a.hop;
+            const bool ok = (f < nvp) & (n < a.L);
+            const bool oka = ok & ((unsigned)sa < (unsigned)a.n);
+            const bool okb = ok & (2 * f + 1 < fb_lim) & ((unsigned)sb < (unsigned)a.n);
+            const float gj = win[n < a.L ? (unsigned)n : 0u].x;
+            const float xa = x[oka ? (unsigned)sa : 0u];
+            const float xb = x[okb ? (unsigned)sb : 0u];
+            return mk(oka ? xa * gj : 0.f, okb ? xb * gj : 0.f);
+        });
+        tw.passes(lds);
+        const int E = nvp * a.n_src;
+        for (int e = threadIdx.x; e < E; e += NT) {
+            int f, ik;
+            split_flat(e, a.n_src, inv_nsrc, f, ik);
+            const int k = a.k1 + ik;
+            const v2 P = lds[pad16(f * NF + k)];
+            const v2 Q = conjv(lds[pad16(f * NF + ((NF - k) & (NF - 1)))]);
+            const v2 Aa = 0.5f * (P + Q);
+            const v2 D = P - Q;   // A_b = -i D / 2
+            const float ma2 = Aa.x * Aa.x + Aa.y * Aa.y;
+            const float mb2 = 0.25f * (D.x * D.x + D.y * D.y);
+            best = fmaxf(best, fmaxf(ma2, mb2));
+        }
+    }
+    best = wave_max(best);
+    if ((threadIdx.x & 63) == 0)
+        red[threadIdx.x >> 6] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float b = red[0];
+        for (int w = 1; w < NT / 64; ++w)
+            b = fmaxf(b, red[w]);
+        a.partial[blockIdx.x] = b;
+    }
+}
+
+// gamma from the pre-pass maxima (relative mode) or from the given value.
+__global__ __launch_bounds__(256) void gamma_kernel(const float *partial, int np, Ctrl *ctrl,
+                                                    int mode, float thr)
+{
+    __shared__ float red[4];
+    float b = 0.f;
+    for (int i = threadIdx.x; i < np; i += 256)
+        b = fmaxf(b, partial[i]);
+    b = wave_max(b);
+    if ((threadIdx.x & 63) == 0)
+        red[threadIdx.x >> 6] = b;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const float m2 = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+        const float g = (mode == 1) ? thr * sqrtf(m2) : thr;
+        ctrl->maxabs2 = m2;
+        ctrl->gamma = g;
+        ctrl->gamma2 = g * g;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Inverse (Eqs. 25-26).  One workgroup per 256 output samples and component.
+// ---------------------------------------------------------------------------
+
+// (b * j) mod G for b, j in [0, G), G <= 65536 (so the product fits 32 bits).
+__device__ __forceinline__ int mulmod(uint32_t b, uint32_t j, int G, int pow2, float invG)
+{
+    const uint32_t p = b * j;
+    if (pow2)
+        return (int)(p & (uint32_t)(G - 1));
+    const uint32_t q = (uint32_t)((float)p * invG);
+    int r = (int)(p - q * (uint32_t)G);
+    while (r < 0)
+        r += G;
+    while (r >= G)
+        r -= G;
+    return r;
+}
+
+__device__ __forceinline__ v2 phasor(const v2 *tlo, const v2 *thi, int idx, int lo_bits)
+{
+    return cmul(thi[idx >> lo_bits], tlo[idx & ((1 << lo_bits) - 1)]);
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ void err_reduce(double d2, double r2, double *err, int q)
+{
+    __shared__ double red[2][4];
+    d2 = wave_sum(d2);
+    r2 = wave_sum(r2);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[0][w] = d2;
+        red[1][w] = r2;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        atomicAdd(&err[2 * q], red[0][0] + red[0][1] + red[0][2] + red[0][3]);
+        atomicAdd(&err[2 * q + 1], red[1][0] + red[1][1] + red[1][2] + red[1][3]);
+    }
+}
+
+__global__ __launch_bounds__(256) void inv_kernel(InvArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int nlo = 1 << a.lo_bits;
+    const int nhi = (a.G + nlo - 1) >> a.lo_bits;
+    const int W = 2 * a.hw + 1;
+    v2 *tlo = reinterpret_cast<v2 *>(smem);
+    v2 *thi = tlo + nlo;
+    v2 *coef = thi + nhi;
+    int *rbase = reinterpret_cast<int *>(coef + a.fb * W);
+
+    const int q = blockIdx.y;
+    const int64_t tile_lo = a.span_lo + (int64_t)blockIdx.x * 256;
+    const int64_t tile_hi = (tile_lo + 255 < a.span_lo + a.span_len - 1) ? tile_lo + 255
+                                                                          : a.span_lo + a.span_len - 1;
+    const int64_t n = tile_lo + threadIdx.x;
+    const bool nvalid = n <= tile_hi;
+    const v2 *__restrict__ win = reinterpret_cast<const v2 *>(a.win);
+
+    for (int e = threadIdx.x; e < nlo; e += 256)
+        tlo[e] = reinterpret_cast<const v2 *>(a.ph_lo)[e];
+    for (int e = threadIdx.x; e < nhi; e += 256)
+        thi[e] = reinterpret_cast<const v2 *>(a.ph_hi)[e];
+
+    // Denominator sum_m g[0] g[n - mH] over every frame of the signal.
+    float den = 0.f;
+    if (nvalid) {
+        const int64_t lo = n - a.M > 0 ? (n - a.M + a.hop - 1) / a.hop : 0;
+        int64_t hi = (n + a.M) / a.hop;
+        if (hi > a.n_frames - 1)
+            hi = a.n_frames - 1;
+        for (int64_t m = lo; m <= hi; ++m)
+            den += win[n - m * a.hop + a.M].x;
+        den *= win[a.M].x;
+    }
+
+    // Frames of this call whose window reaches the tile.
+    int64_t mlo = tile_lo - a.M > 0 ? (tile_lo - a.M + a.hop - 1) / a.hop : 0;
+    int64_t mhi = (tile_hi + a.M) / a.hop;
+    if (mlo < a.frame0)
+        mlo = a.frame0;
+    if (mhi > a.frame0 + a.nframes - 1)
+        mhi = a.frame0 + a.nframes - 1;
+
+    const v2 *__restrict__ T = reinterpret_cast<const v2 *>(a.T);
+    const int32_t *__restrict__ ridge = a.ridge + (int64_t)q * a.nframes;
+    const int zk1 = a.z * a.k1;
+    float acc = 0.f;
+    for (int64_t mb = mlo; mb <= mhi; mb += a.fb) {
+        const int cnt = (int)((mhi - mb + 1) < a.fb ? (mhi - mb + 1) : a.fb);
+        __syncthreads();
+        for (int e = threadIdx.x; e < cnt * W; e += 256) {
+            const int mi = e / W, d = e - mi * W;
+            const int64_t mloc = mb + mi - a.frame0;
+            const int r = ridge[mloc];
+            const int l = r - a.hw + d;
+            v2 c = mk(0.f, 0.f);
+            if (r >= 0 && l >= 0 && l < a.n_dst) {
+                const int b = zk1 + l;
+                const float wgt = (b == 0 || 2 * b == a.G) ? 1.f : 2.f;
+                c = (wgt * a.inv_nfft) * T[mloc * a.n_dst + l];
+            }
+            coef[e] = c;
+            if (d == 0) {
+                int rb = -1;
+                if (r >= 0) {
+                    rb = (zk1 + r - a.hw) % a.G;
+                    if (rb < 0)
+                        rb += a.G;
+                }
+                rbase[mi] = rb;
+            }
+        }
+        __syncthreads();
+        if (!nvalid)
+            continue;
+        for (int mi = 0; mi < cnt; ++mi) {
+            const int64_t j64 = n - (mb + mi) * a.hop;
+            if (j64 < -a.M || j64 > a.M)
+                continue;
+            const int rb = rbase[mi];
+            if (rb < 0)
+                continue;
+            const int j = (int)j64;
+            const int jm = j < 0 ? j + a.G : j;
+            const v2 pw = phasor(tlo, thi, jm, a.lo_bits);
+            const v2 pb = phasor(tlo, thi, mulmod((uint32_t)rb, (uint32_t)jm, a.G, a.g_pow2, a.inv_G),
+                                 a.lo_bits);
+            const v2 *c = coef + mi * W;
+            v2 P = c[W - 1];
+            for (int d = W - 2; d >= 0; --d)
+                P = cmul(P, pw) + c[d];
+            acc += win[j + a.M].x * (pb.x * P.x - pb.y * P.y);
+        }
+    }
+
+    float xv = 0.f;
+    if (nvalid) {
+        xv = den > 0.f ? acc / den : 0.f;
+        float *out = a.xhat + (int64_t)q * a.n + n;
+        if (a.accumulate)
+            xv += *out;
+        *out = xv;
+    }
+    if (a.err) {
+        double d2 = 0.0, r2 = 0.0;
+        if (nvalid && n >= a.M && n < a.n - a.M) {
+            const double rv = a.xref[(int64_t)q * a.n + n];
+            d2 = (rv - (double)xv) * (rv - (double)xv);
+            r2 = rv * rv;
+        }
+        err_reduce(d2, r2, a.err, q);
+    }
+}
+
+// Eq. 15 (hop 1): xhat[m] = (1/(N_f g[0])) sum_zone a_l Re T[m,l].
+__global__ __launch_bounds__(256) void eq15_kernel(InvArgs a, float scale)
+{
+    const int q = blockIdx.y;
+    const int64_t mloc = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const bool valid = mloc < a.nframes;
+    const v2 *__restrict__ T = reinterpret_cast<const v2 *>(a.T);
+    float xv = 0.f;
+    int64_t n = a.frame0 + mloc;
+    if (valid) {
+        const int r = a.ridge[(int64_t)q * a.nframes + mloc];
+        float acc = 0.f;
+        if (r >= 0) {
+            const int la = r - a.hw < 0 ? 0 : r - a.hw;
+            const int lb = r + a.hw > a.n_dst - 1 ? a.n_dst - 1 : r + a.hw;
+            for (int l = la; l <= lb; ++l) {
+                const int b = a.z * a.k1 + l;
+                acc += ((b == 0 || 2 * b == a.G) ? 1.f : 2.f) * T[mloc * a.n_dst + l].x;
+            }
+        }
+        xv = acc * scale;
+        float *out = a.xhat + (int64_t)q * a.n + n;
+        if (a.accumulate)
+            xv += *out;
+        *out = xv;
+    }
+    if (a.err) {
+        double d2 = 0.0, r2 = 0.0;
+        if (valid && n >= a.M && n < a.n - a.M) {
+            const double rv = a.xref[(int64_t)q * a.n + n];
+            d2 = (rv - (double)xv) * (rv - (double)xv);
+            r2 = rv * rv;
+        }
+        err_reduce(d2, r2, a.err, q);
+    }
+}
+
+__global__ void zero_f64(double *p, int count)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count)
+        p[i] = 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Ridge: one wave per (frame, component).
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void ridge_kernel(RidgeArgs a)
+{
+    const int q = blockIdx.y;
+    const int64_t m = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (m >= a.nframes)
+        return;
+    int lo = a.band[2 * q], hi = a.band[2 * q + 1];
+    if (lo < 0)
+        lo = 0;
+    if (hi > a.n_dst - 1)
+        hi = a.n_dst - 1;
+    const v2 *__restrict__ row = reinterpret_cast<const v2 *>(a.T) + m * a.n_dst;
+    float best = 0.f;
+    int arg = 0x7fffffff;
+    for (int l = lo + lane; l <= hi; l += 64) {
+        const v2 v = row[l];
+        const float m2 = v.x * v.x + v.y * v.y;
+        if (m2 > best) {
+            best = m2;
+            arg = l;
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const float ob = __shfl_xor(best, o, 64);
+        const int oa = __shfl_xor(arg, o, 64);
+        if (ob > best || (ob == best && oa < arg)) {
+            best = ob;
+            arg = oa;
+        }
+    }
+    if (lane == 0)
+        a.ridge[(int64_t)q * a.nframes + m] = best > 0.f ? arg : -1;
+}
+
+// Non-zero input rows of pass 1 for window length L: 4, 8 or 16.
+template <int NF>
+int nz_rows(int L)
+{
+    const int rows = (L + NF / 16 - 1) / (NF / 16);
+    return rows <= 4 ? 4 : (rows <= 8 ? 8 : 16);
+}
+
+template <int NF>
+hipError_t launch_fwd_t(const FwdArgs &a, int grid, hipStream_t s)
+{
+    switch (nz_rows<NF>(a.L)) {
+    case 4: hipLaunchKernelGGL((fwd_kernel<NF, 4>), dim3(grid), dim3(Geo<NF>::NT), 0, s, a); break;
+    case 8: hipLaunchKernelGGL((fwd_kernel<NF, 8>), dim3(grid), dim3(Geo<NF>::NT), 0, s, a); break;
+    default: hipLaunchKernelGGL((fwd_kernel<NF, 16>), dim3(grid), dim3(Geo<NF>::NT), 0, s, a); break;
+    }
+    return hipGetLastError();
+}
+
+template <int NF>
+hipError_t launch_max_t(const MaxArgs &a, int grid, hipStream_t s)
+{
+    switch (nz_rows<NF>(a.L)) {
+    case 4: hipLaunchKernelGGL((max_kernel<NF, 4>), dim3(grid), dim3(Geo<NF>::NT), 0, s, a); break;
+    case 8: hipLaunchKernelGGL((max_kernel<NF, 8>), dim3(grid), dim3(Geo<NF>::NT), 0, s, a); break;
+    default: hipLaunchKernelGGL((max_kernel<NF, 16>), dim3(grid), dim3(Geo<NF>::NT), 0, s, a); break;
+    }
+    return hipGetLastError();
+}
+
+template <typename K>
+int occ_of(K kernel, int threads)
+{
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, threads, 0) != hipSuccess)
+        return 1;
+    return nb > 0 ? nb : 1;
+}
+
+template <int NF>
+int occ_fwd_t(int L)
+{
+    switch (nz_rows<NF>(L)) {
+    case 4: return occ_of(fwd_kernel<NF, 4>, Geo<NF>::NT);
+    case 8: return occ_of(fwd_kernel<NF, 8>, Geo<NF>::NT);
+    default: return occ_of(fwd_kernel<NF, 16>, Geo<NF>::NT);
+    }
+}
+
+template <int NF>
+int occ_max_t(int L)
+{
+    switch (nz_rows<NF>(L)) {
+    case 4: return occ_of(max_kernel<NF, 4>, Geo<NF>::NT);
+    case 8: return occ_of(max_kernel<NF, 8>, Geo<NF>::NT);
+    default: return occ_of(max_kernel<NF, 16>, Geo<NF>::NT);
+    }
+}
+
+}  // namespace
+
+#define SST_DISPATCH_NF(nfft, EXPR)                 \
+    switch (nfft) {                                 \
+    case 512: { constexpr int NFv = 512; EXPR; }    \
+    case 1024: { constexpr int NFv = 1024; EXPR; }  \
+    case 2048: { constexpr int NFv = 2048; EXPR; }  \
+    case 4096: { constexpr int NFv = 4096; EXPR; }  \
+    case 8192: { constexpr int NFv = 8192; EXPR; }  \
+    default: break;                                 \
+    }
+
+hipError_t launch_threshold(int nfft, const MaxArgs &a, Ctrl *ctrl, int mode, float thr,
+                            int grid, hipStream_t s)
+{
+    if (mode == 1) {
+        hipError_t e = hipErrorInvalidValue;
+        SST_DISPATCH_NF(nfft, e = launch_max_t<NFv>(a, grid, s); break)
+        if (e != hipSuccess)
+            return e;
+    }
+    hipLaunchKernelGGL(gamma_kernel, dim3(1), dim3(256), 0, s, a.partial, mode == 1 ? grid : 0,
+                       ctrl, mode, thr);
+    return hipGetLastError();
+}
+
+hipError_t launch_forward(int nfft, const FwdArgs &a, int grid, hipStream_t s)
+{
+    SST_DISPATCH_NF(nfft, return launch_fwd_t<NFv>(a, grid, s))
+    return hipErrorInvalidValue;
+}
+
+size_t inv_lds_bytes(const InvArgs &a)
+{
+    const int nlo = 1 << a.lo_bits;
+    const int nhi = (a.G + nlo - 1) >> a.lo_bits;
+    const int W = 2 * a.hw + 1;
+    return sizeof(float2) * (size_t)(nlo + nhi + a.fb * W) + sizeof(int) * (size_t)a.fb;
+}
+
+hipError_t launch_inverse(const InvArgs &a, hipStream_t s)
+{
+    if (a.err) {
+        hipLaunchKernelGGL(zero_f64, dim3((2 * a.n_comp + 63) / 64), dim3(64), 0, s, a.err,
+                           2 * a.n_comp);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
+    const int64_t blocks = (a.span_len + 255) / 256;
+    hipLaunchKernelGGL(inv_kernel, dim3((unsigned)blocks, a.n_comp), dim3(256), inv_lds_bytes(a),
+                       s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_inverse_eq15(const InvArgs &a, float scale, hipStream_t s)
+{
+    if (a.err) {
+        hipLaunchKernelGGL(zero_f64, dim3((2 * a.n_comp + 63) / 64), dim3(64), 0, s, a.err,
+                           2 * a.n_comp);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
+    const int64_t blocks = (a.nframes + 255) / 256;
+    hipLaunchKernelGGL(eq15_kernel, dim3((unsigned)blocks, a.n_comp), dim3(256), 0, s, a, scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_ridge(const RidgeArgs &a, hipStream_t s)
+{
+    const int64_t blocks = (a.nframes + 3) / 4;
+    hipLaunchKernelGGL(ridge_kernel, dim3((unsigned)blocks, a.n_comp), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+int fwd_frames_per_iter(int nfft)
+{
+    SST_DISPATCH_NF(nfft, return Geo<NFv>::F)
+    return 0;
+}
+int fwd_threads(int nfft)
+{
+    SST_DISPATCH_NF(nfft, return Geo<NFv>::NT)
+    return 0;
+}
+int fwd_lds_elems(int nfft)
+{
+    SST_DISPATCH_NF(nfft, return Geo<NFv>::LDS)
+    return 0;
+}
+int fwd_occupancy(int nfft, int L)
+{
+    SST_DISPATCH_NF(nfft, return occ_fwd_t<NFv>(L))
+    return 1;
+}
+int max_occupancy(int nfft, int L)
+{
+    SST_DISPATCH_NF(nfft, return occ_max_t<NFv>(L))
+    return 1;
+}
+
+}  // namespace sst

@@ -1,0 +1,313 @@
+"""GPU parity: the HIP library (through its C ABI) against the float64 oracle on
+identical seeded float32 inputs.  Sizes keep the oracle to seconds while still
+spanning many workgroup iterations and a ragged tail.  Rules: tests/parity.py."""
+import math
+import sys
+import zlib
+
+import numpy as np
+import pytest
+
+import oracle
+from tests.parity import classify_indices, packed_norms, reconciled_T, relf, snr_db
+from workloads import SSTConfig, make_c1, make_c2, make_tone
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def sst():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_2003_07065_amd as m
+    m.lib()
+    return m
+
+
+def _run_forward(sst, x, cfg, frame0=0, nframes=None, debug=True):
+    plan = sst.Plan.from_config(x.shape[0], cfg, device="cuda")
+    xg = torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).cuda()
+    if nframes is None:
+        nframes = plan.n_frames - frame0
+    out = dict(plan=plan, xg=xg)
+    if debug:
+        out["S"] = torch.empty((nframes, plan.n_src), dtype=torch.complex64, device="cuda")
+        out["Sd"] = torch.empty_like(out["S"])
+        out["idx"] = torch.empty((nframes, plan.n_src), dtype=torch.int32, device="cuda")
+        out["col"] = torch.empty((nframes, 3), dtype=torch.float64, device="cuda")
+    out["gamma"] = torch.empty(1, dtype=torch.float32, device="cuda")
+    out["T"] = plan.forward(xg, None, frame0, nframes, S=out.get("S"), Sd=out.get("Sd"),
+                            idx=out.get("idx"), colstats=out.get("col"), gamma=out["gamma"])
+    torch.cuda.synchronize()
+    return out
+
+
+def _forward_parity(sst, x, cfg, frame0=0, nframes=None, label=""):
+    _say(f"[parity] {label} N={x.shape[0]} nfft={cfg.nfft} L={cfg.win_len} hop={cfg.hop} "
+         f"z={cfg.subdiv} band=[{cfg.f_lo},{cfg.f_hi}] frames={frame0}+{nframes}")
+    g = _run_forward(sst, x, cfg, frame0, nframes)
+    plan = g["plan"]
+    nfr = g["T"].shape[0]
+    o = oracle.forward(x.astype(np.float64), cfg, frame0, nfr)
+    assert (o.band.k1, o.band.n_src, o.band.n_dst) == (plan.k1, plan.n_src, plan.n_dst)
+    S_g = g["S"].cpu().numpy()
+    Sd_g = g["Sd"].cpu().numpy()
+    idx_g = g["idx"].cpu().numpy()
+    T_g = g["T"].cpu().numpy()
+    gam_g = float(g["gamma"].cpu().numpy()[0])
+    # gamma (Eq. 13 threshold)
+    assert abs(gam_g - o.gamma) <= 1e-5 * max(o.gamma, 1e-30) + 1e-30, (gam_g, o.gamma)
+    # STFT pair (Eq. 9 and its g' version)
+    e_s, e_sd = relf(S_g, o.S), relf(Sd_g, o.Sd)
+    _say(f"  relF S={e_s:.2e} S'={e_sd:.2e}")
+    assert e_s <= 1e-5 and e_sd <= 1e-5
+    # destination indices
+    s_pack = math.sqrt(np.sum(o.g ** 2) / max(np.sum(o.gd ** 2), 1e-300))
+    ny = packed_norms(x, o.g, o.gd, s_pack, cfg.hop, np.arange(frame0, frame0 + nfr))
+    rep, _ = classify_indices(idx_g, o.idx, o.frac, o.S, o.Sd, o.gamma, cfg.nfft, cfg.subdiv,
+                              s_pack, ny, plan.n_dst)
+    _say(f"  indices: {rep}")
+    assert rep.ok(), (rep, rep.details)
+    # T after reconciling index decisions (Eq. 28 with the GPU's rounding decisions)
+    T_rec = reconciled_T(o.S, idx_g, plan.n_dst)
+    e_t = relf(T_g, T_rec)
+    _say(f"  relF T reconciled={e_t:.2e} raw={relf(T_g, o.T):.2e}")
+    assert e_t <= 1e-5
+    # FP64 column sums of T (conservation of every retained coefficient)
+    col = g["col"].cpu().numpy()
+    ref = T_rec.sum(axis=1)
+    scale = np.abs(o.S).sum(axis=1) + 1e-30
+    assert np.all(np.abs(col[:, 0] + 1j * col[:, 1] - ref) <= 1e-5 * scale)
+    assert np.allclose(col[:, 2], (np.abs(T_g.astype(np.complex128)) ** 2).sum(axis=1),
+                       rtol=1e-9, atol=1e-30)
+    return g, o
+
+
+# (name, N, SSTConfig) -- every DFT size, every pass-1 pruning (4, 8, 16 rows),
+# bands with k1 > 0, non power-of-two z, hops from 1 to 32, histogram chunking
+CASES = [
+    ("c2-shape", 1 << 15, SSTConfig(25600.0, 1023, 128.0, 16, 4096, 0.0, 6400.0, 4, "rel", 1e-3, 6)),
+    ("c3-shape", 1 << 16, SSTConfig(25600.0, 2047, 256.0, 32, 8192, 0.0, 5000.0, 8, "rel", 1e-3, 26)),
+    ("nf1024-F4", 10007, SSTConfig(25600.0, 255, 32.0, 8, 1024, 0.0, 6400.0, 2, "rel", 1e-3, 2)),
+    ("nf512-F8-nz16", 20011, SSTConfig(25600.0, 511, 64.0, 8, 512, 0.0, 6400.0, 1, "rel", 1e-3, 1)),
+    ("nf2048-z3-k1", 12345, SSTConfig(25600.0, 1023, 100.0, 5, 2048, 300.0, 5000.0, 3, "rel", 1e-3, 4)),
+    ("nf4096-nz8-abs", 9001, SSTConfig(8000.0, 1801, 200.0, 7, 4096, 100.0, 4000.0, 2, "abs", 1e-2, 3)),
+    ("nf8192-nz16", 30000, SSTConfig(25600.0, 8191, 900.0, 64, 8192, 1000.0, 3000.0, 5, "rel", 1e-4, 8)),
+]
+
+
+def _signal(name, n, fs, seed=0):
+    rng = np.random.default_rng(zlib.crc32(name.encode()))
+    t = np.arange(n) / fs
+    x = (np.cos(2 * np.pi * (0.11 * fs * t + 0.02 * fs * t * t / max(t[-1], 1e-9)))
+         + 0.5 * np.cos(2 * np.pi * 0.05 * fs * t) + 0.3 * rng.standard_normal(n))
+    return x.astype(np.float32)
+
+
+@pytest.mark.parametrize("name,n,cfg", CASES, ids=[c[0] for c in CASES])
+def test_forward_parity(sst, name, n, cfg):
+    x = _signal(name, n, cfg.fs)
+    _forward_parity(sst, x, cfg, label=name)
+
+
+def test_forward_c1_workload(sst):
+    """The plain standard SST workload (hop 1, full band, N_f = N = 4096)."""
+    w = make_c1()
+    _forward_parity(sst, w.x, w.cfg, label="c1")
+
+
+def test_forward_partial_frames(sst):
+    """A chunk in the middle of the signal: gamma still comes from every frame."""
+    w = make_c2(n=1 << 15)
+    _forward_parity(sst, w.x, w.cfg, frame0=777, nframes=301, label="c2-chunk")
+
+
+def test_forward_chunks_equal_whole(sst):
+    w = make_c2(n=1 << 14)
+    plan = sst.Plan.from_config(w.n, w.cfg, device="cuda")
+    xg = torch.from_numpy(w.x).cuda()
+    T = plan.forward(xg)
+    parts = []
+    f0 = 0
+    for cnt in (100, 257, plan.n_frames - 357):
+        parts.append(plan.forward(xg, None, f0, cnt, reuse_gamma=f0 > 0))
+        f0 += cnt
+    T2 = torch.cat(parts)
+    torch.cuda.synchronize()
+    assert relf(T2.cpu().numpy(), T.cpu().numpy()) < 1e-6
+
+
+@pytest.mark.parametrize("n", [1, 100, 300])
+def test_forward_tiny_signals(sst, n):
+    """Signals shorter than the window: every frame is mostly zero padding."""
+    cfg = SSTConfig(1000.0, 511, 40.0, 7, 512, 0.0, 500.0, 2, "rel", 1e-3, 2)
+    x = _signal(f"tiny{n}", n, cfg.fs)
+    _forward_parity(sst, x, cfg, label=f"tiny{n}")
+
+
+def test_forward_zero_signal(sst):
+    """All-zero input: gamma = 0, nothing is retained, T is all zeros."""
+    cfg = SSTConfig(1000.0, 255, 20.0, 4, 1024, 0.0, 500.0, 2, "rel", 1e-3, 2)
+    g = _run_forward(sst, np.zeros(5000, np.float32), cfg)
+    assert float(g["gamma"].cpu()[0]) == 0.0
+    assert torch.count_nonzero(g["T"]).item() == 0
+    assert bool((g["idx"] == -1).all())
+
+
+# ---------------------------------------------------------------------------
+# Inverse
+# ---------------------------------------------------------------------------
+
+def _ridges_from_if(w, plan):
+    from workloads import ridge_bins
+    f = w.inst_freq(w.frame_times())
+    return ridge_bins(f, w.cfg.fs, w.cfg.nfft, plan.k1, w.cfg.subdiv, plan.n_dst)
+
+
+@pytest.mark.parametrize("which", ["c2-small", "c1"])
+def test_inverse_on_identical_T(sst, which):
+    """Eqs. 25-26 on the same T (oracle T rounded to complex64): elementwise parity."""
+    w = make_c2(n=1 << 15) if which == "c2-small" else make_c1()
+    c = w.cfg
+    _say(f"[inverse] {which}")
+    o = oracle.forward(w.x.astype(np.float64), c)
+    plan = sst.Plan.from_config(w.n, c, device="cuda")
+    T32 = o.T.astype(np.complex64)
+    ridge = _ridges_from_if(w, plan)
+    xh_g = plan.inverse(torch.from_numpy(T32).cuda(), torch.from_numpy(ridge).cuda(), c.hw)
+    xh_g = xh_g.cpu().numpy()
+    for q in range(ridge.shape[0]):
+        xo = oracle.inverse(T32.astype(np.complex128), ridge[q], c.hw, o.g, c.hop, c.nfft,
+                            o.band.k1, c.subdiv, w.n)
+        e = relf(xh_g[q], xo)
+        _say(f"  comp {q}: relF xhat = {e:.2e}")
+        assert e <= 1e-5
+
+
+def test_inverse_pipeline_snr(sst):
+    """GPU pipeline vs oracle pipeline: output SNR (Eq. 33) within 0.1 dB per component,
+    and the GPU's FP64 error reduction equals the host sum."""
+    w = make_c2(n=1 << 15)
+    c = w.cfg
+    o = oracle.forward(w.x.astype(np.float64), c)
+    plan = sst.Plan.from_config(w.n, c, device="cuda")
+    xg = torch.from_numpy(w.x).cuda()
+    T = plan.forward(xg)
+    ridge = _ridges_from_if(w, plan)
+    rg = torch.from_numpy(ridge).cuda()
+    xref = torch.from_numpy(w.comps.astype(np.float32)).cuda()
+    err = torch.zeros((ridge.shape[0], 2), dtype=torch.float64, device="cuda")
+    xh = plan.inverse(T, rg, c.hw, xref=xref, err=err).cpu().numpy()
+    err = err.cpu().numpy()
+    M = (c.win_len - 1) // 2
+    for q in range(ridge.shape[0]):
+        xo = oracle.inverse(o.T, ridge[q], c.hw, o.g, c.hop, c.nfft, o.band.k1, c.subdiv, w.n)
+        ref = w.comps[q].astype(np.float32).astype(np.float64)
+        s_g = snr_db(ref, xh[q], M, w.n - M)
+        s_o = snr_db(ref, xo, M, w.n - M)
+        _say(f"  comp {q}: SNR gpu {s_g:.3f} dB oracle {s_o:.3f} dB")
+        assert abs(s_g - s_o) <= 0.1
+        d = ref[M:w.n - M] - xh[q][M:w.n - M].astype(np.float64)
+        assert abs(err[q, 0] - np.sum(d * d)) <= 1e-9 * np.sum(d * d)
+        assert abs(err[q, 1] - np.sum(ref[M:w.n - M] ** 2)) <= 1e-9 * np.sum(ref[M:w.n - M] ** 2)
+
+
+@pytest.mark.parametrize("name,n,cfg", [CASES[2], CASES[4], CASES[1]],
+                         ids=["nf1024", "nf2048-z3-k1", "c3-shape"])
+def test_inverse_configs(sst, name, n, cfg):
+    """Inverse parity on identical T across DFT sizes, non power-of-two z, k1 > 0."""
+    x = _signal(name, n, cfg.fs)
+    o = oracle.forward(x.astype(np.float64), cfg)
+    plan = sst.Plan.from_config(n, cfg, device="cuda")
+    T32 = o.T.astype(np.complex64)
+    rng = np.random.default_rng(1)
+    nfr = plan.n_frames
+    # a wandering ridge, some frames without a ridge, one ridge at the band edge
+    base = rng.integers(0, plan.n_dst, size=3)
+    ridge = np.stack([(base[q] + (np.arange(nfr) // 17) % 5) % plan.n_dst for q in range(3)])
+    ridge[1, ::7] = -1
+    ridge[2, :] = plan.n_dst - 1
+    ridge = ridge.astype(np.int32)
+    xh = plan.inverse(torch.from_numpy(T32).cuda(), torch.from_numpy(ridge).cuda(),
+                      cfg.hw).cpu().numpy()
+    for q in range(3):
+        xo = oracle.inverse(T32.astype(np.complex128), ridge[q], cfg.hw, o.g, cfg.hop, cfg.nfft,
+                            o.band.k1, cfg.subdiv, n)
+        e = relf(xh[q], xo)
+        _say(f"  {name} comp {q}: relF xhat = {e:.2e}")
+        assert e <= 1e-5
+
+
+def test_inverse_chunks_accumulate(sst):
+    w = make_c2(n=1 << 14)
+    c = w.cfg
+    plan = sst.Plan.from_config(w.n, c, device="cuda")
+    xg = torch.from_numpy(w.x).cuda()
+    T = plan.forward(xg)
+    ridge = torch.from_numpy(_ridges_from_if(w, plan)).cuda()
+    whole = plan.inverse(T, ridge, c.hw)
+    acc = torch.zeros_like(whole)
+    f0 = 0
+    for cnt in (311, 200, plan.n_frames - 511):
+        plan.inverse(T[f0:f0 + cnt].contiguous(), ridge[:, f0:f0 + cnt].contiguous(), c.hw,
+                     xhat=acc, frame0=f0, nframes=cnt, accumulate=True)
+        f0 += cnt
+    torch.cuda.synchronize()
+    assert relf(acc.cpu().numpy(), whole.cpu().numpy()) < 1e-6
+
+
+def test_inverse_eq15_matches_oracle(sst):
+    """Eq. 15 (hop 1) on identical T."""
+    w = make_c1()
+    c = w.cfg
+    o = oracle.forward(w.x.astype(np.float64), c)
+    plan = sst.Plan.from_config(w.n, c, device="cuda")
+    T32 = o.T.astype(np.complex64)
+    ridge = _ridges_from_if(w, plan)
+    xh = plan.inverse(torch.from_numpy(T32).cuda(), torch.from_numpy(ridge).cuda(), c.hw,
+                      eq15=True).cpu().numpy()
+    for q in range(ridge.shape[0]):
+        xo = oracle.inverse_eq15(T32.astype(np.complex128), ridge[q], c.hw, o.g[(c.win_len - 1) // 2],
+                                 c.nfft, o.band.k1, c.subdiv)
+        assert relf(xh[q], xo) <= 1e-6
+
+
+def test_inverse_tone_unit_gain(sst):
+    """Clean tone at a destination-bin centre: the GPU pipeline returns it at >= 60 dB."""
+    cfg = SSTConfig(25600.0, 1023, 128.0, 16, 4096, 0.0, 6400.0, 4, "rel", 1e-3, 6)
+    n = 1 << 15
+    l0 = 4 * 19 + 1
+    x = make_tone(n, (l0 / 4) * cfg.fs / cfg.nfft, cfg.fs, amp=0.8, phase=0.3)
+    plan = sst.Plan.from_config(n, cfg, device="cuda")
+    T = plan.forward(torch.from_numpy(x.astype(np.float32)).cuda())
+    ridge = torch.full((1, plan.n_frames), l0, dtype=torch.int32, device="cuda")
+    xh = plan.inverse(T, ridge, cfg.hw).cpu().numpy()[0]
+    M = (cfg.win_len - 1) // 2
+    assert snr_db(x, xh, M, n - M) > 60.0
+
+
+# ---------------------------------------------------------------------------
+# Ridge
+# ---------------------------------------------------------------------------
+
+def test_ridge_matches_oracle(sst):
+    w = make_c2(n=1 << 15)
+    o = oracle.forward(w.x.astype(np.float64), w.cfg)
+    plan = sst.Plan.from_config(w.n, w.cfg, device="cuda")
+    T32 = o.T.astype(np.complex64)
+    bands = [(60, 100), (140, 170), (370, 400), (0, plan.n_dst - 1)]
+    r_g = plan.ridge(torch.from_numpy(T32).cuda(), bands).cpu().numpy()
+    mag = np.abs(T32.astype(np.complex128)) ** 2
+    for q, (la, lb) in enumerate(bands):
+        r_o = oracle.ridge(T32.astype(np.complex128), la, lb)
+        diff = np.nonzero(r_g[q] != r_o)[0]
+        for m in diff:   # only near-ties may differ (FP32 vs FP64 |T|^2)
+            a, b = mag[m, r_g[q][m]], mag[m, r_o[m]]
+            assert abs(a - b) <= 1e-6 * max(a, b)
+        assert len(diff) <= 2
