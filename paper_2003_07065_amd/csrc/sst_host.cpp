@@ -282,10 +282,19 @@ sst_status sst_plan_bind(sst_plan_t pl, void *workspace, size_t bytes, void *str
                        hipMemcpyHostToDevice, s);
     if (e != hipSuccess)
         return hip_fail(e, "hipMemcpyAsync(tables)");
+    int max_lds = 0;
+    e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    if (e != hipSuccess)
+        return hip_fail(e, "hipDeviceGetAttribute(shared memory)");
+    const size_t need = sst::fwd_lds_bytes(pl->p.nfft, pl->n_src);
+    if (need == 0 || need > (size_t)max_lds)
+        return fail(SST_E_UNSUPPORTED, "forward kernel needs " + std::to_string(need) +
+                                           " bytes of LDS, the device offers " +
+                                           std::to_string(max_lds));
     pl->ws = ws;
     pl->device = dev;
     pl->cus = cus;
-    pl->fwd_grid_cap = cus * sst::fwd_occupancy(pl->p.nfft, pl->p.win_len);
+    pl->fwd_grid_cap = cus * sst::fwd_occupancy(pl->p.nfft, pl->p.win_len, pl->n_src);
     int mg = cus * sst::max_occupancy(pl->p.nfft, pl->p.win_len);
     pl->max_grid_cap = mg < kMaxPartials ? mg : kMaxPartials;
     return SST_OK;
@@ -363,6 +372,11 @@ sst_status sst_forward(sst_plan_t pl, const float *x, int64_t frame0, int64_t nf
     a.n_src = pl->n_src;
     a.n_dst = pl->n_dst;
     a.z = pl->p.subdiv;
+    {
+        const int nt = sst::fwd_threads(NF);
+        const double ang = kTwoPi * (double)mod_exact((int64_t)nt * pl->M, NF) / NF;
+        a.cph_step = make_float2((float)std::cos(ang), (float)std::sin(ang));
+    }
     a.inv_s = (float)(1.0 / pl->s_pack);
     a.cdelta = (float)(NF / (kTwoPi * pl->s_pack));
     const int F = sst::fwd_frames_per_iter(NF);

@@ -33,6 +33,7 @@ struct FwdArgs {
     int32_t *idx;           // optional [nframes][n_src]
     double *colstats;       // optional [nframes][3]
     int L, M, hop, k1, n_src, n_dst, z;
+    float2 cph_step;        // exp(+i 2 pi ((NT M) mod N_f) / N_f), NT = threads per workgroup
     float inv_s;            // 1/s: S' = B / s
     float cdelta;           // N_f / (2 pi s): delta (bins) = cdelta Im(B conj A) / |A|^2
 };
@@ -95,8 +96,10 @@ hipError_t launch_ridge(const RidgeArgs &a, hipStream_t s);
 int fwd_frames_per_iter(int nfft);   // F
 int fwd_threads(int nfft);           // threads per workgroup
 int fwd_lds_elems(int nfft);         // float2 capacity of the LDS buffer
-int fwd_occupancy(int nfft, int L);  // resident workgroups per CU (forward kernel)
+int fwd_occupancy(int nfft, int L, int n_src);  // resident workgroups per CU (forward)
 int max_occupancy(int nfft, int L);  // resident workgroups per CU (threshold pre-pass)
 size_t inv_lds_bytes(const InvArgs &a);
+size_t fwd_dyn_lds(int nfft, int n_src);      // dynamic LDS of the forward kernel
+size_t fwd_lds_bytes(int nfft, int n_src);    // static + dynamic LDS of the forward kernel
 
 }  // namespace sst

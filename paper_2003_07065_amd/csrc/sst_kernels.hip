@@ -40,6 +40,13 @@ namespace sst {
 namespace {
 
 typedef float v2 __attribute__((ext_vector_type(2)));
+typedef unsigned u2 __attribute__((ext_vector_type(2)));
+
+// Word 3 of a raw (untyped, stride 0) buffer resource on the gfx9 family:
+// 32-bit data format, everything else zero.
+constexpr int kBufferWord3 = 0x00020000;
+// Cache policy of the T stream-out: non-temporal.
+constexpr int kNonTemporal = 2;
 
 __device__ __forceinline__ v2 mk(float a, float b)
 {
@@ -187,8 +194,7 @@ struct Geo {
     static constexpr int F = V / NF;                  // frames per iteration
     static constexpr int NT = V / 16;                 // threads per workgroup
     static constexpr int LDS = V + V / 16;            // padded float2 capacity
-    // separate LDS histogram (float2 entries): F * n_dst bins in one chunk for
-    // every configuration with F * n_dst <= HIST; larger rows are chunked
+    // LDS bytes of the destination histogram, in units of 8 bytes
     static constexpr int HIST = NF == 8192 ? 10240 : 4608;
     static constexpr int R3 = NF >= 4096 ? 16 : NF / 256;  // radix of pass 3
     static constexpr bool P4 = NF == 8192;            // radix-2 pass 4
@@ -315,130 +321,306 @@ __device__ __forceinline__ void split_flat(int e, int n_src, float inv_nsrc, int
 // ---------------------------------------------------------------------------
 // Forward kernel: framing, FFT pair, IF, threshold, reassignment, T rows.
 //
-// LDS: the FFT buffer and a separate destination histogram.  The IF stage
-// scatters straight into the histogram; the store phase reads each bin, writes
-// it to HBM and zeroes it for the next iteration, so the histogram needs no
-// separate clearing pass.
+// Histogram.  The reassignment sums (Eq. 28) are accumulated in LDS as 64-bit
+// fixed-point integers: every coefficient is scaled by a power of two 2^K,
+// rounded to a 32-bit integer and added with a 64-bit integer atomic, so each
+// bin holds the exact sum of its rounded terms whatever the order of the
+// atomics, and is rounded to FP32 once when the row is written.  K is chosen
+// per frame from B1 = sum_j |x[c+j] g[j]| >= |S[m,k]| for every k, so each
+// term is below 2^30 and a bin of at most n_src <= 4097 terms below 2^43;
+// the rounding error of a term is at most 2^-(K+1), about 2^-31 B1.  (LDS
+// floating-point atomics are an order of magnitude slower than integer ones
+// on this GPU.)
+//
+// The histogram covers HBINS bins; a row of F n_dst bins is produced in
+// ceil(F n_dst / HBINS) chunks, each re-running the cheap IF stage and
+// scattering only the coefficients that land in the chunk.  The store phase
+// reads each bin, zeroes it and streams the row to HBM, so the histogram needs
+// no separate clearing pass.
+//
+// Pipelining.  On gfx9 one counter tracks outstanding vector-memory loads and
+// stores together, so a load issued after an iteration's T stores would wait
+// for those stores to drain.  Each thread therefore fetches its pass-1 samples
+// of the NEXT iteration right after pass 1, before this iteration's stores,
+// and every store instruction is unconditional (a buffer resource bounded to
+// the valid bins drops the excess), so the wait for the prefetched samples
+// covers only the loads.
+//
+// DEBUG adds the per-coefficient outputs (S, S', destination index) and the
+// FP64 column sums.
 // ---------------------------------------------------------------------------
 
-template <int NF, int NZ>
+// Power-of-two scale 2^K with B 2^K < 2^30 (B >= 0), clamped to [2^-100, 2^100].
+__device__ __forceinline__ float fixed_scale(float B)
+{
+    int e = 0;
+    frexpf(B, &e);   // B < 2^e
+    int K = B > 0.f ? 30 - e : 0;
+    K = K > 100 ? 100 : (K < -100 ? -100 : K);
+    return ldexpf(1.0f, K);
+}
+
+// A term below 2^30 in magnitude as a sign-extended 64-bit integer.
+__device__ __forceinline__ unsigned long long to_fixed(float t)
+{
+    return (unsigned long long)(long long)(int)rintf(t);
+}
+
+// FP32 value of a fixed-point sum |v| < 2^43: v = hi 2^21 + lo with
+// |hi| < 2^22 and 0 <= lo < 2^21 both exact in FP32, so one FMA rounds once.
+__device__ __forceinline__ float from_fixed(unsigned long long v)
+{
+    const int hi = (int)((long long)v >> 21);
+    const unsigned lo = (unsigned)v & 0x1fffffu;
+    return fmaf((float)hi, 2097152.0f, (float)lo);
+}
+
+template <int NF, int NZ, bool DEBUG>
 __global__ __launch_bounds__(Geo<NF>::NT, 2) void fwd_kernel(FwdArgs a)
 {
     using G = Geo<NF>;
-    constexpr int F = G::F, NT = G::NT, CAP = G::HIST;
+    constexpr int F = G::F, NT = G::NT, Q = NF / 16;
+    constexpr int HB = G::HIST / 2;   // 64-bit (re, im) bins that fit the histogram LDS
+    constexpr int NST = HB / NT;      // store instructions per thread and chunk
+    static_assert(HB % NT == 0, "histogram is a whole number of store rounds");
+    constexpr int SEG = Q < 64 ? Q : 64;   // lanes of one frame within a wave in pass 1
     __shared__ v2 lds[G::LDS];
-    __shared__ v2 hist[G::HIST];
-    __shared__ double colacc[3 * F];
-    float *histf = reinterpret_cast<float *>(hist);
+    __shared__ unsigned long long hacc[2 * HB];   // re bins, then im bins
+    __shared__ float bsum[2][F];                  // per-frame sum |x g|, double-buffered
+    __shared__ double colacc[DEBUG ? 3 * F : 1];
 
     Twiddles<NF> tw;
     tw.load(reinterpret_cast<const v2 *>(a.twid));
 
-    const v2 *__restrict__ win = reinterpret_cast<const v2 *>(a.win);
     const v2 *__restrict__ cph = reinterpret_cast<const v2 *>(a.cphase);
     const float *__restrict__ x = a.x;
     const float gamma2 = a.ctrl->gamma2;
     const float inv_nsrc = 1.0f / (float)a.n_src;
+    const float inv_ndst = 1.0f / (float)a.n_dst;
+    const float bmargin = 1.001f;   // margin for the FP32 sum of the bound
     const int64_t n_iter = (a.nframes + F - 1) / F;
 
-    for (int e = threadIdx.x; e < CAP; e += NT)
-        hist[e] = mk(0.f, 0.f);
-    if (threadIdx.x < 3 * F)
-        colacc[threadIdx.x] = 0.0;
-    // (the barriers of the first FFT order these stores before any use)
+    // Centre phase of Eq. 9 for bin k1 + ik.  With one frame per iteration a
+    // thread visits ik = tid + i NT, whose phases differ by the constant
+    // factor exp(i 2 pi ((NT M) mod N_f) / N_f), so they are generated by
+    // rotation; with several frames per iteration the table is staged in LDS.
+    extern __shared__ __align__(16) unsigned char dyn_lds[];
+    v2 *cphl = reinterpret_cast<v2 *>(dyn_lds);
+    v2 ph0 = mk(1.f, 0.f);
+    const v2 ph_step = mk(a.cph_step.x, a.cph_step.y);
+    if constexpr (F == 1) {
+        if (threadIdx.x < a.n_src)
+            ph0 = cph[(unsigned)threadIdx.x];
+    } else {
+        for (int e = threadIdx.x; e < a.n_src; e += NT)
+            cphl[e] = cph[(unsigned)e];
+    }
 
-    for (int64_t it = blockIdx.x; it < n_iter; it += gridDim.x) {
+    // Pass-1 role of this thread: frame f1 of the iteration, taps jj + r Q.
+    const int f1 = threadIdx.x / Q, jj = threadIdx.x % Q;
+    v2 w[NZ];   // (g, s g') of the thread's taps; zero beyond the window
+#pragma unroll
+    for (int r = 0; r < NZ; ++r) {
+        const int n = jj + r * Q;
+        w[r] = n < a.L ? reinterpret_cast<const v2 *>(a.win)[(unsigned)n] : mk(0.f, 0.f);
+    }
+    // Eq. 8: frame m covers samples mH - M .. mH + M.  Signals are limited to
+    // 2^30 samples so sample indices fit 32 bits.
+    float xv[NZ];
+    int okb = 0;
+    auto fetch = [&](int64_t it) {
+        const int64_t m = it * F + f1;   // frame of this thread, relative to frame0
+        const bool fv = (it < n_iter) & (m < a.nframes);
+        const int cm = (int)((a.frame0 + (fv ? m : 0)) * (int64_t)a.hop - a.M) + jj;
+        okb = 0;
+#pragma unroll
+        for (int r = 0; r < NZ; ++r) {
+            const int s = cm + r * Q;
+            const bool ok = fv & ((unsigned)s < (unsigned)a.n);
+            xv[r] = x[ok ? (unsigned)s : 0u];
+            okb |= (int)ok << r;
+        }
+    };
+
+    for (int e = threadIdx.x; e < 2 * HB; e += NT)
+        hacc[e] = 0ull;
+    if (threadIdx.x < 2 * F)
+        bsum[threadIdx.x / F][threadIdx.x % F] = 0.f;
+    if (DEBUG && threadIdx.x < 3 * F)
+        colacc[threadIdx.x] = 0.0;
+    fetch(blockIdx.x);
+    // Wait here for every load issued so far (tables, first samples), so that
+    // inside the loop the samples prefetched by the previous iteration are the
+    // only loads the first use has to wait for (vmcnt(0), expcnt and lgkmcnt
+    // left unconstrained).
+    __builtin_amdgcn_s_waitcnt(0x0f70);
+    __syncthreads();
+
+    int par = 0;   // parity of the bsum buffer used by this iteration
+    for (int64_t it = blockIdx.x; it < n_iter; it += gridDim.x, par ^= 1) {
         const int64_t m0 = it * F;   // first frame of the iteration, relative to frame0
         const int nvalid = (int)((a.nframes - m0) < F ? (a.nframes - m0) : F);
 
-        // Eq. 8: frame m covers samples mH - M .. mH + M; tap n = j + M.
-        // Tap 0 of frame m0; signals are limited to 2^30 samples so sample
-        // indices fit 32 bits.
-        const int cm = (int)((a.frame0 + m0) * (int64_t)a.hop - a.M);
-        pass1<NF, NZ>(lds, [&](int f, int n) -> v2 {
-            // branch-free: clamp the addresses, zero the value when out of range
-            const int s = cm + f * a.hop + n;
-            const bool ok = (f < nvalid) & (n < a.L) & ((unsigned)s < (unsigned)a.n);
-            const float xv = x[ok ? (unsigned)s : 0u];
-            const v2 w = win[n < a.L ? (unsigned)n : 0u];
-            return (ok ? xv : 0.f) * w;
-        });
+        {   // pass 1 from the prefetched samples; partial bound sum |x g|
+            v2 v[16];
+            float part = 0.f;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                if (r < NZ) {
+                    const float xr = ((okb >> r) & 1) ? xv[r] : 0.f;
+                    v[r] = xr * w[r];
+                    part += fabsf(xr * w[r].x);
+                } else {
+                    v[r] = mk(0.f, 0.f);
+                }
+            }
+            if constexpr (NZ == 4)
+                dft16_nz4(v);
+            else if constexpr (NZ == 8)
+                dft16_nz8(v);
+            else
+                dft16(v);
+            const int base = f1 * NF + jj * 16;
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                lds[pad16(base + r)] = v[r];
+#pragma unroll
+            for (int o = SEG / 2; o > 0; o >>= 1)
+                part += __shfl_xor(part, o, 64);
+            if ((threadIdx.x % SEG) == 0)
+                atomicAdd(&bsum[par][f1], part);
+        }
+        fetch(it + gridDim.x);   // next iteration's samples, issued before this one's stores
+        __syncthreads();
         tw.passes(lds);
+        // (the pass barriers order the bsum sums before their use, and the
+        //  other buffer's last use before it is cleared here)
+        if (threadIdx.x < F)
+            bsum[par ^ 1][threadIdx.x] = 0.f;
 
         // Eqs. 12-13 and 27-29 for every in-band coefficient of the F frames,
-        // scattered into the destination bins [c0, c0 + CAP) of the flat
-        // (frame, l) index; one chunk unless F n_dst exceeds the histogram.
+        // scattered into the bins [c0, c0 + HB) of the flat (frame, l) index.
         const int E = nvalid * a.n_src;
         const int EH = nvalid * a.n_dst;
         v2 *__restrict__ trow = reinterpret_cast<v2 *>(a.T) + m0 * (int64_t)a.n_dst;
-        for (int c0 = 0; c0 < EH; c0 += CAP) {
-            const int cn = (EH - c0) < CAP ? (EH - c0) : CAP;
-            for (int e = threadIdx.x; e < E; e += NT) {
-                int f, ik;
-                split_flat(e, a.n_src, inv_nsrc, f, ik);
+        const float sc0 = fixed_scale(bsum[par][0] * bmargin);
+        for (int c0 = 0; c0 < EH; c0 += HB) {
+            const int cn = (EH - c0) < HB ? (EH - c0) : HB;
+            // One in-band coefficient (flat index e, centre phase phk).
+            auto coefficient = [&](int e, int f, int ik, v2 phk) {
                 const int k = a.k1 + ik;
                 const v2 P = lds[pad16(f * NF + k)];
-                const v2 Q = conjv(lds[pad16(f * NF + ((NF - k) & (NF - 1)))]);
-                const v2 A = 0.5f * (P + Q);
-                const v2 D = P - Q;
+                const v2 Qc = conjv(lds[pad16(f * NF + ((NF - k) & (NF - 1)))]);
+                const v2 A = 0.5f * (P + Qc);
+                const v2 D = P - Qc;
                 const v2 B = mk(0.5f * D.y, -0.5f * D.x);
                 const float mag2 = A.x * A.x + A.y * A.y;
-                const v2 ph = cph[(unsigned)ik];
-                const v2 S = cmul(ph, A);
+                const v2 S = cmul(phk, A);
                 int code = -1;
                 if (mag2 > gamma2) {
                     const float im = B.y * A.x - B.x * A.y;   // Im(B conj A)
                     const float delta = a.cdelta * im * __builtin_amdgcn_rcpf(mag2);
                     const float zd = (float)a.z * delta;
-                    if (!(fabsf(zd) < 1.0e8f)) {
-                        code = -2;
-                    } else {
-                        int l;
-                        if (delta <= (float)k)   // kappa = k - delta
-                            l = a.z * (k - a.k1) + (int)floorf(0.5f - zd);
-                        else                     // kappa = delta - k
-                            l = (int)floorf(zd + 0.5f) - a.z * (k + a.k1);
-                        code = (l >= 0 && l < a.n_dst) ? l : -2;
-                    }
+                    // kappa = |k - delta|; l = floor(z (kappa - k1) + 1/2) with the
+                    // integer part kept exact
+                    const float hi = delta <= (float)k ? 0.5f - zd : zd + 0.5f;
+                    const int ibase = delta <= (float)k ? a.z * (k - a.k1) : -a.z * (k + a.k1);
+                    const int l = ibase + (int)floorf(fminf(fmaxf(hi, -1.0e8f), 1.0e8f));
+                    code = (fabsf(zd) < 1.0e8f && l >= 0 && l < a.n_dst) ? l : -2;
                 }
                 if (code >= 0) {
                     const int d = f * a.n_dst + code - c0;
                     if (d >= 0 && d < cn) {
-                        atomicAdd(&histf[2 * d], S.x);
-                        atomicAdd(&histf[2 * d + 1], S.y);
+                        const float sc = F == 1 ? sc0 : fixed_scale(bsum[par][f] * bmargin);
+                        atomicAdd(&hacc[d], to_fixed(S.x * sc));
+                        atomicAdd(&hacc[HB + d], to_fixed(S.y * sc));
                     }
                 }
-                if (c0 == 0) {
-                    if (a.S)
-                        reinterpret_cast<v2 *>(a.S)[m0 * a.n_src + (unsigned)e] = S;
-                    if (a.Sd)
-                        reinterpret_cast<v2 *>(a.Sd)[m0 * a.n_src + (unsigned)e] =
-                            a.inv_s * cmul(ph, B);
-                    if (a.idx)
-                        a.idx[m0 * a.n_src + (unsigned)e] = code;
+                if constexpr (DEBUG) {
+                    if (c0 == 0) {
+                        if (a.S)
+                            reinterpret_cast<v2 *>(a.S)[m0 * a.n_src + (unsigned)e] = S;
+                        if (a.Sd)
+                            reinterpret_cast<v2 *>(a.Sd)[m0 * a.n_src + (unsigned)e] =
+                                a.inv_s * cmul(phk, B);
+                        if (a.idx)
+                            a.idx[m0 * a.n_src + (unsigned)e] = code;
+                    }
+                }
+            };
+            // Two coefficients per iteration give the scheduler two independent
+            // dependency chains (LDS read -> IF -> atomic) to interleave.
+            v2 ph_cur = ph0;
+            const v2 ph_step2 = cmul(ph_step, ph_step);
+            for (int e = threadIdx.x; e < E; e += 2 * NT) {
+                const int e2 = e + NT;
+                if constexpr (F == 1) {
+                    const v2 p1 = ph_cur, p2 = cmul(ph_cur, ph_step);
+                    ph_cur = cmul(ph_cur, ph_step2);
+                    coefficient(e, 0, e, p1);
+                    if (e2 < E)
+                        coefficient(e2, 0, e2, p2);
+                } else {
+                    int f, ik;
+                    split_flat(e, a.n_src, inv_nsrc, f, ik);
+                    coefficient(e, f, ik, cphl[ik]);
+                    if (e2 < E) {
+                        split_flat(e2, a.n_src, inv_nsrc, f, ik);
+                        coefficient(e2, f, ik, cphl[ik]);
+                    }
                 }
             }
             __syncthreads();
-            for (int e = threadIdx.x; e < cn; e += NT) {
-                const v2 v = hist[e];
-                hist[e] = mk(0.f, 0.f);
-                __builtin_nontemporal_store(v, &trow[(unsigned)(c0 + e)]);
-                if (a.colstats) {
-                    const int f = (c0 + e) / a.n_dst;
-                    atomicAdd(&colacc[3 * f], (double)v.x);
-                    atomicAdd(&colacc[3 * f + 1], (double)v.y);
-                    atomicAdd(&colacc[3 * f + 2], (double)v.x * v.x + (double)v.y * v.y);
+            // Row stream-out.  A buffer resource bounded to the cn valid bins
+            // makes the hardware drop the stores past the end, so every store
+            // instruction is unconditional and the next iteration waits only
+            // for its prefetched samples, not for these stores.
+            const __amdgpu_buffer_rsrc_t rs =
+                __builtin_amdgcn_make_buffer_rsrc(trow + c0, (short)0, cn * 8, kBufferWord3);
+            unsigned long long hr[NST], hi[NST];   // read every bin first: one LDS round trip
+#pragma unroll
+            for (int i = 0; i < NST; ++i) {
+                hr[i] = hacc[threadIdx.x + i * NT];
+                hi[i] = hacc[HB + threadIdx.x + i * NT];
+            }
+#pragma unroll
+            for (int i = 0; i < NST; ++i) {
+                hacc[threadIdx.x + i * NT] = 0ull;
+                hacc[HB + threadIdx.x + i * NT] = 0ull;
+            }
+            const float isc0 = 1.0f / sc0;   // exact: a power of two
+#pragma unroll
+            for (int i = 0; i < NST; ++i) {
+                const int e = threadIdx.x + i * NT;
+                float isc = isc0;
+                if constexpr (F > 1) {
+                    int f = (int)(((float)(c0 + e) + 0.5f) * inv_ndst);
+                    f = f < nvalid ? f : nvalid - 1;
+                    isc = 1.0f / fixed_scale(bsum[par][f] * bmargin);
+                }
+                const v2 v = mk(from_fixed(hr[i]) * isc, from_fixed(hi[i]) * isc);
+                __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), rs, (unsigned)e * 8u,
+                                                      0, kNonTemporal);
+                if constexpr (DEBUG) {
+                    if (a.colstats && e < cn) {
+                        const int f = (c0 + e) / a.n_dst;
+                        atomicAdd(&colacc[3 * f], (double)v.x);
+                        atomicAdd(&colacc[3 * f + 1], (double)v.y);
+                        atomicAdd(&colacc[3 * f + 2], (double)v.x * v.x + (double)v.y * v.y);
+                    }
                 }
             }
-            if (c0 + CAP < EH)
+            if (c0 + HB < EH)
                 __syncthreads();   // bins zeroed before the next chunk's scatter
         }
-        if (a.colstats) {
-            __syncthreads();
-            if (threadIdx.x < 3 * nvalid)
-                a.colstats[m0 * 3 + threadIdx.x] = colacc[threadIdx.x];
-            if (threadIdx.x < 3 * F)
-                colacc[threadIdx.x] = 0.0;
+        if constexpr (DEBUG) {
+            if (a.colstats) {
+                __syncthreads();
+                if (threadIdx.x < 3 * nvalid)
+                    a.colstats[m0 * 3 + threadIdx.x] = colacc[threadIdx.x];
+                if (threadIdx.x < 3 * F)
+                    colacc[threadIdx.x] = 0.0;
+            }
         }
     }
 }
@@ -459,50 +641,92 @@ template <int NF, int NZ>
 __global__ __launch_bounds__(Geo<NF>::NT, (NF == 8192 || NZ == 16) ? 2 : 3) void max_kernel(MaxArgs a)
 {
     using G = Geo<NF>;
-    constexpr int F = G::F, NT = G::NT;
+    constexpr int F = G::F, NT = G::NT, Q = NF / 16;
     __shared__ v2 lds[G::LDS];
     __shared__ float red[NT / 64];
 
     Twiddles<NF> tw;
     tw.load(reinterpret_cast<const v2 *>(a.twid));
-    const v2 *__restrict__ win = reinterpret_cast<const v2 *>(a.win);
     const float *__restrict__ x = a.x;
     const float inv_nsrc = 1.0f / (float)a.n_src;
     const int64_t n_pairs = (a.n_frames + 1) / 2;
     const int64_t n_iter = (n_pairs + F - 1) / F;
+
+    // Pass-1 role: frame pair f1 of the iteration, taps jj + r Q.  The pair
+    // (2p, 2p+1) is packed as one complex signal g x_2p + i g x_2p+1.
+    const int f1 = threadIdx.x / Q, jj = threadIdx.x % Q;
+    float gw[NZ];
+#pragma unroll
+    for (int r = 0; r < NZ; ++r) {
+        const int n = jj + r * Q;
+        gw[r] = n < a.L ? reinterpret_cast<const v2 *>(a.win)[(unsigned)n].x : 0.f;
+    }
+    float xa[NZ], xb[NZ];
+    int oka = 0, okb = 0;
+    auto fetch = [&](int64_t it) {
+        const int64_t p = it * F + f1;   // pair index
+        const bool pv = (it < n_iter) & (p < n_pairs);
+        const int cm = (int)(2 * (pv ? p : 0) * (int64_t)a.hop - a.M) + jj;
+        const bool bv = pv & (2 * p + 1 < a.n_frames);
+        oka = 0;
+        okb = 0;
+#pragma unroll
+        for (int r = 0; r < NZ; ++r) {
+            const int sa = cm + r * Q, sb = sa + a.hop;
+            const bool ga = pv & ((unsigned)sa < (unsigned)a.n);
+            const bool gb = bv & ((unsigned)sb < (unsigned)a.n);
+            xa[r] = x[ga ? (unsigned)sa : 0u];
+            xb[r] = x[gb ? (unsigned)sb : 0u];
+            oka |= (int)ga << r;
+            okb |= (int)gb << r;
+        }
+    };
+    fetch(blockIdx.x);
     float best = 0.f;
 
     for (int64_t it = blockIdx.x; it < n_iter; it += gridDim.x) {
         const int64_t p0 = it * F;
         const int nvp = (int)((n_pairs - p0) < F ? (n_pairs - p0) : F);
+        {
+            v2 v[16];
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                v[r] = (r < NZ) ? mk((((oka >> r) & 1) ? xa[r] : 0.f) * gw[r],
+                                     (((okb >> r) & 1) ? xb[r] : 0.f) * gw[r])
+                                : mk(0.f, 0.f);
+            if constexpr (NZ == 4)
+                dft16_nz4(v);
+            else if constexpr (NZ == 8)
+                dft16_nz8(v);
+            else
+                dft16(v);
+            const int base = f1 * NF + jj * 16;
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                lds[pad16(base + r)] = v[r];
+        }
+        fetch(it + gridDim.x);
         __syncthreads();
-        const int cm = (int)(2 * p0 * (int64_t)a.hop - a.M);   // tap 0 of frame 2 p0
-        const int64_t fb_lim = a.n_frames - 2 * p0;   // frames 2 p0 + i exist for i < fb_lim
-        pass1<NF, NZ>(lds, [&](int f, int n) -> v2 {
-            const int sa = cm + 2 * f * a.hop + n;
-            const int sb = sa + a.hop;
-            const bool ok = (f < nvp) & (n < a.L);
-            const bool oka = ok & ((unsigned)sa < (unsigned)a.n);
-            const bool okb = ok & (2 * f + 1 < fb_lim) & ((unsigned)sb < (unsigned)a.n);
-            const float gj = win[n < a.L ? (unsigned)n : 0u].x;
-            const float xa = x[oka ? (unsigned)sa : 0u];
-            const float xb = x[okb ? (unsigned)sb : 0u];
-            return mk(oka ? xa * gj : 0.f, okb ? xb * gj : 0.f);
-        });
         tw.passes(lds);
         const int E = nvp * a.n_src;
         for (int e = threadIdx.x; e < E; e += NT) {
             int f, ik;
-            split_flat(e, a.n_src, inv_nsrc, f, ik);
+            if constexpr (F == 1) {
+                f = 0;
+                ik = e;
+            } else {
+                split_flat(e, a.n_src, inv_nsrc, f, ik);
+            }
             const int k = a.k1 + ik;
             const v2 P = lds[pad16(f * NF + k)];
-            const v2 Q = conjv(lds[pad16(f * NF + ((NF - k) & (NF - 1)))]);
-            const v2 Aa = 0.5f * (P + Q);
-            const v2 D = P - Q;   // A_b = -i D / 2
+            const v2 Qc = conjv(lds[pad16(f * NF + ((NF - k) & (NF - 1)))]);
+            const v2 Aa = 0.5f * (P + Qc);
+            const v2 D = P - Qc;   // A_b = -i D / 2
             const float ma2 = Aa.x * Aa.x + Aa.y * Aa.y;
             const float mb2 = 0.25f * (D.x * D.x + D.y * D.y);
             best = fmaxf(best, fmaxf(ma2, mb2));
         }
+        __syncthreads();   // LDS reads done before the next iteration's pass 1
     }
     best = wave_max(best);
     if ((threadIdx.x & 63) == 0)
@@ -793,15 +1017,27 @@ int nz_rows(int L)
     return rows <= 4 ? 4 : (rows <= 8 ? 8 : 16);
 }
 
+template <int NF, int NZ>
+hipError_t launch_fwd_nz(const FwdArgs &a, int grid, hipStream_t s)
+{
+    const bool debug = a.S || a.Sd || a.idx || a.colstats;
+    const dim3 g(grid), b(Geo<NF>::NT);
+    const size_t dyn = fwd_dyn_lds(NF, a.n_src);
+    if (debug)
+        hipLaunchKernelGGL((fwd_kernel<NF, NZ, true>), g, b, dyn, s, a);
+    else
+        hipLaunchKernelGGL((fwd_kernel<NF, NZ, false>), g, b, dyn, s, a);
+    return hipGetLastError();
+}
+
 template <int NF>
 hipError_t launch_fwd_t(const FwdArgs &a, int grid, hipStream_t s)
 {
     switch (nz_rows<NF>(a.L)) {
-    case 4: hipLaunchKernelGGL((fwd_kernel<NF, 4>), dim3(grid), dim3(Geo<NF>::NT), 0, s, a); break;
-    case 8: hipLaunchKernelGGL((fwd_kernel<NF, 8>), dim3(grid), dim3(Geo<NF>::NT), 0, s, a); break;
-    default: hipLaunchKernelGGL((fwd_kernel<NF, 16>), dim3(grid), dim3(Geo<NF>::NT), 0, s, a); break;
+    case 4: return launch_fwd_nz<NF, 4>(a, grid, s);
+    case 8: return launch_fwd_nz<NF, 8>(a, grid, s);
+    default: return launch_fwd_nz<NF, 16>(a, grid, s);
     }
-    return hipGetLastError();
 }
 
 template <int NF>
@@ -816,21 +1052,23 @@ hipError_t launch_max_t(const MaxArgs &a, int grid, hipStream_t s)
 }
 
 template <typename K>
-int occ_of(K kernel, int threads)
+int occ_of(K kernel, int threads, size_t dyn = 0)
 {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, threads, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, threads, dyn) != hipSuccess)
         return 1;
     return nb > 0 ? nb : 1;
 }
 
 template <int NF>
-int occ_fwd_t(int L)
+int occ_fwd_t(int L, int n_src)
 {
+    // every variant of one N_f has the same LDS and launch bounds
+    const size_t dyn = fwd_dyn_lds(NF, n_src);
     switch (nz_rows<NF>(L)) {
-    case 4: return occ_of(fwd_kernel<NF, 4>, Geo<NF>::NT);
-    case 8: return occ_of(fwd_kernel<NF, 8>, Geo<NF>::NT);
-    default: return occ_of(fwd_kernel<NF, 16>, Geo<NF>::NT);
+    case 4: return occ_of(fwd_kernel<NF, 4, false>, Geo<NF>::NT, dyn);
+    case 8: return occ_of(fwd_kernel<NF, 8, false>, Geo<NF>::NT, dyn);
+    default: return occ_of(fwd_kernel<NF, 16, false>, Geo<NF>::NT, dyn);
     }
 }
 
@@ -845,6 +1083,13 @@ int occ_max_t(int L)
 }
 
 }  // namespace
+
+// Dynamic LDS of the forward kernel: the centre-phase table when several
+// frames share an iteration (N_f < 4096), nothing otherwise.
+size_t fwd_dyn_lds(int nfft, int n_src)
+{
+    return nfft < 4096 ? sizeof(float2) * (size_t)n_src : 0;
+}
 
 #define SST_DISPATCH_NF(nfft, EXPR)                 \
     switch (nfft) {                                 \
@@ -935,9 +1180,25 @@ int fwd_lds_elems(int nfft)
     SST_DISPATCH_NF(nfft, return Geo<NFv>::LDS)
     return 0;
 }
-int fwd_occupancy(int nfft, int L)
+template <int NF>
+size_t fwd_static_lds_t()
 {
-    SST_DISPATCH_NF(nfft, return occ_fwd_t<NFv>(L))
+    hipFuncAttributes at{};
+    if (hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&fwd_kernel<NF, 16, true>)) !=
+        hipSuccess)
+        return 0;
+    return at.sharedSizeBytes;
+}
+
+size_t fwd_lds_bytes(int nfft, int n_src)
+{
+    SST_DISPATCH_NF(nfft, return fwd_static_lds_t<NFv>() + fwd_dyn_lds(NFv, n_src))
+    return 0;
+}
+
+int fwd_occupancy(int nfft, int L, int n_src)
+{
+    SST_DISPATCH_NF(nfft, return occ_fwd_t<NFv>(L, n_src))
     return 1;
 }
 int max_occupancy(int nfft, int L)
