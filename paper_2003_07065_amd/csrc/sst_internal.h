@@ -100,6 +100,7 @@ int fwd_occupancy(int nfft, int L, int n_src);  // resident workgroups per CU (f
 int max_occupancy(int nfft, int L);  // resident workgroups per CU (threshold pre-pass)
 size_t inv_lds_bytes(const InvArgs &a);
 size_t fwd_dyn_lds(int nfft, int n_src);      // dynamic LDS of the forward kernel
+int fwd_rounds(int nfft, int n_src);          // coefficient rounds per thread: 3, 5 or 9
 size_t fwd_lds_bytes(int nfft, int n_src);    // static + dynamic LDS of the forward kernel
 
 }  // namespace sst

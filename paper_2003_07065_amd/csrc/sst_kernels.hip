@@ -194,90 +194,155 @@ struct Geo {
     static constexpr int F = V / NF;                  // frames per iteration
     static constexpr int NT = V / 16;                 // threads per workgroup
     static constexpr int LDS = V + V / 16;            // padded float2 capacity
-    // LDS bytes of the destination histogram, in units of 8 bytes
-    static constexpr int HIST = NF == 8192 ? 10240 : 4608;
     static constexpr int R3 = NF >= 4096 ? 16 : NF / 256;  // radix of pass 3
     static constexpr bool P4 = NF == 8192;            // radix-2 pass 4
 };
 
-// One Stockham pass of radix R and stride NS over the F frames in LDS.
+// w^r for r = 0 .. R-1 from the bases B_b = w^(2^b) (b < log2 R, each the
+// correctly rounded value of a double-precision table): w^r is the product of
+// the bases of the set bits of r, formed as w^(2^p) w^(r - 2^p) with 2^p the
+// top bit of r, so each power is at most log2(R) - 1 products deep and its
+// error does not grow with r (powering a single rounded base would multiply
+// that base's rounding error by r).
+template <int R>
+__device__ __forceinline__ void powers(const v2 *bases, int stride, v2 (&p)[R])
+{
+    p[0] = mk(1.f, 0.f);
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+        const int lb = 31 - __builtin_clz(r);
+        const int hb = 1 << lb;
+        p[r] = hb == r ? bases[lb * stride] : cmul(p[hb], p[r - hb]);
+    }
+}
+
+template <int R>
+constexpr int log2i() { return R <= 1 ? 0 : 1 + log2i<R / 2>(); }
+
+// One Stockham pass of radix R and stride NS over the F frames in LDS.  The
+// twiddles W_{NS R}^{k r} with k = (j mod N_f/R) mod NS = tid mod NS (every
+// butterfly of a thread has the same k, as NS divides both N_f/R and the
+// thread count) are formed from the log2(R) bases W_{NS R}^{k 2^b}, staged
+// once in LDS as [b][k] (TW entries) so that they hold no registers between
+// passes.
 template <int NF, int R, int NS>
 struct Pass {
     using G = Geo<NF>;
     static constexpr int NR = NF / R;
     static constexpr int NB = (NF * G::F / R) / G::NT;   // butterflies per thread
-    static constexpr int NTW = NS > 1 ? NB * (R - 1) : 1;
+    static constexpr int NBITS = log2i<R>();
+    static constexpr int TW = NS > 1 ? NS * NBITS : 0;    // LDS table entries
+    static_assert(NS == 1 || (G::NT % NS == 0 && NR % NS == 0), "one twiddle set per thread");
 
-    static __device__ __forceinline__ void load_tw(v2 *tw, const v2 *__restrict__ twid)
+    // tbl[b NS + k] = W_{NS R}^{k 2^b} = W_{N_f}^{(N_f / (NS R)) k 2^b}; the
+    // exponent stays below N_f / 2.
+    static __device__ __forceinline__ void stage(v2 *tbl, const v2 *__restrict__ twid)
     {
-        if (NS == 1)
-            return;
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            const int j = threadIdx.x + b * G::NT;
-            const int k = (j % NR) % NS;
-#pragma unroll
-            for (int r = 1; r < R; ++r)
-                tw[b * (R - 1) + r - 1] = twid[(unsigned)((NF / (NS * R)) * k * r)];
+        for (int e = threadIdx.x; e < TW; e += G::NT) {
+            const int b = e / NS, k = e % NS;
+            tbl[e] = twid[(unsigned)((NF / (NS * R)) * (k << b))];
         }
     }
 
-    static __device__ __forceinline__ void run(v2 *lds, const v2 *tw)
+    static __device__ __forceinline__ void run(v2 *lds, const v2 *tbl)
     {
+        // LDS addresses depend only on the thread index; an opaque copy per
+        // call keeps them from being hoisted out of the frame loop and spilled
+        int tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
         v2 v[NB][R];
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-            const int j = threadIdx.x + b * G::NT;
+            const int j = tid + b * G::NT;
             const int f = j / NR, jj = j % NR;
 #pragma unroll
             for (int r = 0; r < R; ++r)
                 v[b][r] = lds[pad16(f * NF + jj + r * NR)];
-            if (NS > 1) {
+        }
+        if constexpr (NS > 1) {
+            v2 p[R];
+            powers<R>(tbl + tid % NS, NS, p);
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
 #pragma unroll
                 for (int r = 1; r < R; ++r)
-                    v[b][r] = cmul(v[b][r], tw[b * (R - 1) + r - 1]);
-            }
-            dftR<R>(v[b]);
+                    v[b][r] = cmul(v[b][r], p[r]);
         }
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+            dftR<R>(v[b]);
         __syncthreads();
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-            const int j = threadIdx.x + b * G::NT;
+            const int j = tid + b * G::NT;
             const int f = j / NR, jj = j % NR;
             const int k = jj % NS;
-            const int base = f * NF + (jj / NS) * NS * R + k;
+            const int base_i = f * NF + (jj / NS) * NS * R + k;
 #pragma unroll
             for (int r = 0; r < R; ++r)
-                lds[pad16(base + r * NS)] = v[b][r];
+                lds[pad16(base_i + r * NS)] = v[b][r];
         }
         __syncthreads();
     }
 };
 
-// Twiddles of passes 2..4 held in registers for the kernel's lifetime.
+// Twiddles of passes 2 and 3 come from bases staged in LDS (TW entries);
+// the radix-2 pass 4 of N_f = 8192 needs only w itself, which each thread
+// keeps in registers for its butterflies.
 template <int NF>
 struct Twiddles {
     using G = Geo<NF>;
     using P2 = Pass<NF, 16, 16>;
     using P3 = Pass<NF, G::R3, 256>;
-    using P4 = Pass<NF, 2, 4096>;
-    v2 t2[P2::NTW];
-    v2 t3[P3::NTW];
-    v2 t4[G::P4 ? P4::NTW : 1];
+    static constexpr int TW = P2::TW + P3::TW;
+    static constexpr int NB4 = G::P4 ? (NF / 2) / G::NT : 1;   // pass-4 butterflies per thread
+    v2 t4[NB4];
 
-    __device__ __forceinline__ void load(const v2 *twid)
+    // Stage the pass 2/3 bases into tbl (TW entries, visible after the next
+    // barrier) and load the pass-4 twiddles.
+    __device__ __forceinline__ void load(v2 *tbl, const v2 *__restrict__ twid)
     {
-        P2::load_tw(t2, twid);
-        P3::load_tw(t3, twid);
-        if constexpr (G::P4)
-            P4::load_tw(t4, twid);
+        P2::stage(tbl, twid);
+        P3::stage(tbl + P2::TW, twid);
+        if constexpr (G::P4) {
+#pragma unroll
+            for (int b = 0; b < NB4; ++b) {
+                const int j = threadIdx.x + b * G::NT;
+                t4[b] = twid[(unsigned)j];
+            }
+        }
     }
-    __device__ __forceinline__ void passes(v2 *lds) const
+    __device__ __forceinline__ void passes(v2 *lds, const v2 *tbl) const
     {
-        P2::run(lds, t2);
-        P3::run(lds, t3);
+        P2::run(lds, tbl);
+        P3::run(lds, tbl + P2::TW);
         if constexpr (G::P4)
-            P4::run(lds, t4);
+            pass4(lds);
+    }
+    // Radix-2 pass of stride 4096 (N_f = 8192, one frame): butterfly j pairs
+    // elements j and j + 4096 with twiddle W_8192^j.
+    __device__ __forceinline__ void pass4(v2 *lds) const
+    {
+        int tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        v2 v[NB4][2];
+#pragma unroll
+        for (int b = 0; b < NB4; ++b) {
+            const int j = tid + b * G::NT;
+            v[b][0] = lds[pad16(j)];
+            v[b][1] = cmul(lds[pad16(j + 4096)], t4[b]);
+            const v2 u = v[b][0];
+            v[b][0] = u + v[b][1];
+            v[b][1] = u - v[b][1];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int b = 0; b < NB4; ++b) {
+            const int j = tid + b * G::NT;
+            lds[pad16(j)] = v[b][0];
+            lds[pad16(j + 4096)] = v[b][1];
+        }
+        __syncthreads();
     }
 };
 
@@ -321,22 +386,29 @@ __device__ __forceinline__ void split_flat(int e, int n_src, float inv_nsrc, int
 // ---------------------------------------------------------------------------
 // Forward kernel: framing, FFT pair, IF, threshold, reassignment, T rows.
 //
-// Histogram.  The reassignment sums (Eq. 28) are accumulated in LDS as 64-bit
-// fixed-point integers: every coefficient is scaled by a power of two 2^K,
-// rounded to a 32-bit integer and added with a 64-bit integer atomic, so each
-// bin holds the exact sum of its rounded terms whatever the order of the
-// atomics, and is rounded to FP32 once when the row is written.  K is chosen
-// per frame from B1 = sum_j |x[c+j] g[j]| >= |S[m,k]| for every k, so each
-// term is below 2^30 and a bin of at most n_src <= 4097 terms below 2^43;
-// the rounding error of a term is at most 2^-(K+1), about 2^-31 B1.  (LDS
+// Phases of one iteration (F frames):
+//   pass 1 .. pass s  Stockham FFT of the packed pair in the LDS buffer;
+//   IF phase          every thread evaluates its in-band coefficients
+//                     (Eqs. 12-13, 27-29) and keeps (destination, S) in
+//                     registers; per-frame sums sum_k (|Re S| + |Im S|) are
+//                     reduced in LDS;
+//   scatter phase     the LDS buffer, no longer needed by the FFT, becomes
+//                     the destination histogram: zeroed, then every kept
+//                     coefficient is added to its bin;
+//   store phase       each bin is read, converted and streamed to HBM as T.
+// Reusing the FFT buffer for the histogram halves the LDS of a workgroup and
+// raises the number of resident workgroups per CU.  Rows longer than the
+// buffer (F n_dst > HBINS) are scattered and stored in several chunks.
+//
+// Histogram arithmetic.  The sums of Eq. 28 are accumulated as 32-bit
+// fixed-point integers with a per-frame power-of-two scale 2^K chosen from
+// B = sum_k (|Re S| + |Im S|) over the frame's kept coefficients, which bounds
+// the real and the imaginary sum of every bin: B 2^K < 2^31, so no bin
+// overflows.  Each term is rounded to an integer (error <= 2^-(K+1), about
+// 2^-32 B) and the integer sums are exact, hence independent of the order of
+// the atomics; each bin is rounded to FP32 once when it is written.  (LDS
 // floating-point atomics are an order of magnitude slower than integer ones
 // on this GPU.)
-//
-// The histogram covers HBINS bins; a row of F n_dst bins is produced in
-// ceil(F n_dst / HBINS) chunks, each re-running the cheap IF stage and
-// scattering only the coefficients that land in the chunk.  The store phase
-// reads each bin, zeroes it and streams the row to HBM, so the histogram needs
-// no separate clearing pass.
 //
 // Pipelining.  On gfx9 one counter tracks outstanding vector-memory loads and
 // stores together, so a load issued after an iteration's T stores would wait
@@ -346,58 +418,46 @@ __device__ __forceinline__ void split_flat(int e, int n_src, float inv_nsrc, int
 // the valid bins drops the excess), so the wait for the prefetched samples
 // covers only the loads.
 //
-// DEBUG adds the per-coefficient outputs (S, S', destination index) and the
-// FP64 column sums.
+// R bounds the in-band coefficients per thread (ceil(F n_src / NT) <= R).
+// CHUNKED allows rows longer than the buffer; without it the row is a single
+// chunk whose store count is known at compile time.  DEBUG adds the
+// per-coefficient outputs (S, S', destination index) and the FP64 column sums.
 // ---------------------------------------------------------------------------
 
-// Power-of-two scale 2^K with B 2^K < 2^30 (B >= 0), clamped to [2^-100, 2^100].
+// Power-of-two scale 2^K with B 2^K < 2^31 (B >= 0), clamped to [2^-100, 2^100].
 __device__ __forceinline__ float fixed_scale(float B)
 {
     int e = 0;
     frexpf(B, &e);   // B < 2^e
-    int K = B > 0.f ? 30 - e : 0;
+    int K = B > 0.f ? 31 - e : 0;
     K = K > 100 ? 100 : (K < -100 ? -100 : K);
     return ldexpf(1.0f, K);
 }
 
-// A term below 2^30 in magnitude as a sign-extended 64-bit integer.
-__device__ __forceinline__ unsigned long long to_fixed(float t)
-{
-    return (unsigned long long)(long long)(int)rintf(t);
-}
-
-// FP32 value of a fixed-point sum |v| < 2^43: v = hi 2^21 + lo with
-// |hi| < 2^22 and 0 <= lo < 2^21 both exact in FP32, so one FMA rounds once.
-__device__ __forceinline__ float from_fixed(unsigned long long v)
-{
-    const int hi = (int)((long long)v >> 21);
-    const unsigned lo = (unsigned)v & 0x1fffffu;
-    return fmaf((float)hi, 2097152.0f, (float)lo);
-}
-
-template <int NF, int NZ, bool DEBUG>
-__global__ __launch_bounds__(Geo<NF>::NT, 2) void fwd_kernel(FwdArgs a)
+template <int NF, int NZ, int R, bool DEBUG, bool CHUNKED>
+// Waves per SIMD: 4 for N_f = 8192 (two 8-wave workgroups fill a CU's LDS), 3 otherwise.
+__global__ __launch_bounds__(Geo<NF>::NT, DEBUG ? 2 : (NF == 8192 ? 4 : 3)) void fwd_kernel(FwdArgs a)
 {
     using G = Geo<NF>;
     constexpr int F = G::F, NT = G::NT, Q = NF / 16;
-    constexpr int HB = G::HIST / 2;   // 64-bit (re, im) bins that fit the histogram LDS
+    constexpr int HB = G::LDS;        // histogram bins (two 32-bit integers each)
     constexpr int NST = HB / NT;      // store instructions per thread and chunk
     static_assert(HB % NT == 0, "histogram is a whole number of store rounds");
-    constexpr int SEG = Q < 64 ? Q : 64;   // lanes of one frame within a wave in pass 1
+    constexpr int SEGF = 24;          // key = (frame << SEGF) | flat destination
     __shared__ v2 lds[G::LDS];
-    __shared__ unsigned long long hacc[2 * HB];   // re bins, then im bins
-    __shared__ float bsum[2][F];                  // per-frame sum |x g|, double-buffered
+    __shared__ float bsum[F];
     __shared__ double colacc[DEBUG ? 3 * F : 1];
+    int *hq = reinterpret_cast<int *>(lds);   // bin b: hq[2b] = re, hq[2b + 1] = im
 
+    __shared__ v2 twl[Twiddles<NF>::TW];
     Twiddles<NF> tw;
-    tw.load(reinterpret_cast<const v2 *>(a.twid));
+    tw.load(twl, reinterpret_cast<const v2 *>(a.twid));
 
     const v2 *__restrict__ cph = reinterpret_cast<const v2 *>(a.cphase);
     const float *__restrict__ x = a.x;
     const float gamma2 = a.ctrl->gamma2;
     const float inv_nsrc = 1.0f / (float)a.n_src;
     const float inv_ndst = 1.0f / (float)a.n_dst;
-    const float bmargin = 1.001f;   // margin for the FP32 sum of the bound
     const int64_t n_iter = (a.nframes + F - 1) / F;
 
     // Centre phase of Eq. 9 for bin k1 + ik.  With one frame per iteration a
@@ -442,10 +502,6 @@ __global__ __launch_bounds__(Geo<NF>::NT, 2) void fwd_kernel(FwdArgs a)
         }
     };
 
-    for (int e = threadIdx.x; e < 2 * HB; e += NT)
-        hacc[e] = 0ull;
-    if (threadIdx.x < 2 * F)
-        bsum[threadIdx.x / F][threadIdx.x % F] = 0.f;
     if (DEBUG && threadIdx.x < 3 * F)
         colacc[threadIdx.x] = 0.0;
     fetch(blockIdx.x);
@@ -454,26 +510,17 @@ __global__ __launch_bounds__(Geo<NF>::NT, 2) void fwd_kernel(FwdArgs a)
     // only loads the first use has to wait for (vmcnt(0), expcnt and lgkmcnt
     // left unconstrained).
     __builtin_amdgcn_s_waitcnt(0x0f70);
-    __syncthreads();
 
-    int par = 0;   // parity of the bsum buffer used by this iteration
-    for (int64_t it = blockIdx.x; it < n_iter; it += gridDim.x, par ^= 1) {
+    for (int64_t it = blockIdx.x; it < n_iter; it += gridDim.x) {
         const int64_t m0 = it * F;   // first frame of the iteration, relative to frame0
         const int nvalid = (int)((a.nframes - m0) < F ? (a.nframes - m0) : F);
+        __syncthreads();   // the previous iteration's store phase is done with the buffer
 
-        {   // pass 1 from the prefetched samples; partial bound sum |x g|
+        {   // pass 1 from the prefetched samples
             v2 v[16];
-            float part = 0.f;
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                if (r < NZ) {
-                    const float xr = ((okb >> r) & 1) ? xv[r] : 0.f;
-                    v[r] = xr * w[r];
-                    part += fabsf(xr * w[r].x);
-                } else {
-                    v[r] = mk(0.f, 0.f);
-                }
-            }
+            for (int r = 0; r < 16; ++r)
+                v[r] = (r < NZ) ? (((okb >> r) & 1) ? xv[r] : 0.f) * w[r] : mk(0.f, 0.f);
             if constexpr (NZ == 4)
                 dft16_nz4(v);
             else if constexpr (NZ == 8)
@@ -484,134 +531,173 @@ __global__ __launch_bounds__(Geo<NF>::NT, 2) void fwd_kernel(FwdArgs a)
 #pragma unroll
             for (int r = 0; r < 16; ++r)
                 lds[pad16(base + r)] = v[r];
-#pragma unroll
-            for (int o = SEG / 2; o > 0; o >>= 1)
-                part += __shfl_xor(part, o, 64);
-            if ((threadIdx.x % SEG) == 0)
-                atomicAdd(&bsum[par][f1], part);
         }
+        if (threadIdx.x < F)
+            bsum[threadIdx.x] = 0.f;
         fetch(it + gridDim.x);   // next iteration's samples, issued before this one's stores
         __syncthreads();
-        tw.passes(lds);
-        // (the pass barriers order the bsum sums before their use, and the
-        //  other buffer's last use before it is cleared here)
-        if (threadIdx.x < F)
-            bsum[par ^ 1][threadIdx.x] = 0.f;
+        tw.passes(lds, twl);
 
-        // Eqs. 12-13 and 27-29 for every in-band coefficient of the F frames,
-        // scattered into the bins [c0, c0 + HB) of the flat (frame, l) index.
+        // IF phase: Eqs. 12-13 and 27-29 for every in-band coefficient of the
+        // F frames; kept coefficients stay in registers as (key, S).
         const int E = nvalid * a.n_src;
         const int EH = nvalid * a.n_dst;
+        // Per-round quantities (bins, LDS addresses) depend only on the thread
+        // index; an opaque copy per iteration keeps the compiler from hoisting
+        // them out of the frame loop and spilling them.
+        int tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        int key[R];
+        v2 sv[R];
+        float part[F];
+#pragma unroll
+        for (int f = 0; f < F; ++f)
+            part[f] = 0.f;
+        v2 ph_cur = ph0;
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            // rounds are independent; keeping the scheduler from interleaving
+            // them bounds the live registers to one round's temporaries
+            __builtin_amdgcn_sched_barrier(0);
+            const int e = tid + i * NT;
+            key[i] = -1;
+            sv[i] = mk(0.f, 0.f);
+            int f, ik;
+            v2 phk;
+            if constexpr (F == 1) {
+                f = 0;
+                ik = e;
+                phk = ph_cur;
+                ph_cur = cmul(ph_cur, ph_step);
+            } else {
+                split_flat(e < E ? e : 0, a.n_src, inv_nsrc, f, ik);
+                phk = cphl[ik];
+            }
+            if (e >= E)
+                continue;
+            const int k = a.k1 + ik;
+            const v2 P = lds[pad16(f * NF + k)];
+            const v2 Qc = conjv(lds[pad16(f * NF + ((NF - k) & (NF - 1)))]);
+            const v2 A = 0.5f * (P + Qc);
+            const v2 D = P - Qc;
+            const v2 B = mk(0.5f * D.y, -0.5f * D.x);
+            const float mag2 = A.x * A.x + A.y * A.y;
+            const v2 S = cmul(phk, A);
+            int code = -1;
+            if (mag2 > gamma2) {
+                const float im = B.y * A.x - B.x * A.y;   // Im(B conj A)
+                const float delta = a.cdelta * im * __builtin_amdgcn_rcpf(mag2);
+                const float zd = (float)a.z * delta;
+                // kappa = |k - delta|; l = floor(z (kappa - k1) + 1/2) with the
+                // integer part kept exact
+                const float hi = delta <= (float)k ? 0.5f - zd : zd + 0.5f;
+                const int ibase = delta <= (float)k ? a.z * (k - a.k1) : -a.z * (k + a.k1);
+                const int l = ibase + (int)floorf(fminf(fmaxf(hi, -1.0e8f), 1.0e8f));
+                code = (fabsf(zd) < 1.0e8f && l >= 0 && l < a.n_dst) ? l : -2;
+            }
+            if (code >= 0) {
+                key[i] = (f << SEGF) | (f * a.n_dst + code);
+                sv[i] = S;
+                const float mag1 = fabsf(S.x) + fabsf(S.y);
+#pragma unroll
+                for (int ff = 0; ff < F; ++ff)
+                    part[ff] += ff == f ? mag1 : 0.f;
+            }
+            if constexpr (DEBUG) {
+                if (a.S)
+                    reinterpret_cast<v2 *>(a.S)[m0 * a.n_src + (unsigned)e] = S;
+                if (a.Sd)
+                    reinterpret_cast<v2 *>(a.Sd)[m0 * a.n_src + (unsigned)e] = a.inv_s * cmul(phk, B);
+                if (a.idx)
+                    a.idx[m0 * a.n_src + (unsigned)e] = code;
+            }
+        }
+#pragma unroll
+        for (int ff = 0; ff < F; ++ff) {
+            float p = part[ff];
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1)
+                p += __shfl_xor(p, o, 64);
+            if ((threadIdx.x & 63) == 0 && p > 0.f)
+                atomicAdd(&bsum[ff], p);
+        }
+        __syncthreads();   // FFT buffer free, frame bounds complete
+
         v2 *__restrict__ trow = reinterpret_cast<v2 *>(a.T) + m0 * (int64_t)a.n_dst;
-        const float sc0 = fixed_scale(bsum[par][0] * bmargin);
-        for (int c0 = 0; c0 < EH; c0 += HB) {
-            const int cn = (EH - c0) < HB ? (EH - c0) : HB;
-            // One in-band coefficient (flat index e, centre phase phk).
-            auto coefficient = [&](int e, int f, int ik, v2 phk) {
-                const int k = a.k1 + ik;
-                const v2 P = lds[pad16(f * NF + k)];
-                const v2 Qc = conjv(lds[pad16(f * NF + ((NF - k) & (NF - 1)))]);
-                const v2 A = 0.5f * (P + Qc);
-                const v2 D = P - Qc;
-                const v2 B = mk(0.5f * D.y, -0.5f * D.x);
-                const float mag2 = A.x * A.x + A.y * A.y;
-                const v2 S = cmul(phk, A);
-                int code = -1;
-                if (mag2 > gamma2) {
-                    const float im = B.y * A.x - B.x * A.y;   // Im(B conj A)
-                    const float delta = a.cdelta * im * __builtin_amdgcn_rcpf(mag2);
-                    const float zd = (float)a.z * delta;
-                    // kappa = |k - delta|; l = floor(z (kappa - k1) + 1/2) with the
-                    // integer part kept exact
-                    const float hi = delta <= (float)k ? 0.5f - zd : zd + 0.5f;
-                    const int ibase = delta <= (float)k ? a.z * (k - a.k1) : -a.z * (k + a.k1);
-                    const int l = ibase + (int)floorf(fminf(fmaxf(hi, -1.0e8f), 1.0e8f));
-                    code = (fabsf(zd) < 1.0e8f && l >= 0 && l < a.n_dst) ? l : -2;
-                }
-                if (code >= 0) {
-                    const int d = f * a.n_dst + code - c0;
-                    if (d >= 0 && d < cn) {
-                        const float sc = F == 1 ? sc0 : fixed_scale(bsum[par][f] * bmargin);
-                        atomicAdd(&hacc[d], to_fixed(S.x * sc));
-                        atomicAdd(&hacc[HB + d], to_fixed(S.y * sc));
-                    }
-                }
-                if constexpr (DEBUG) {
-                    if (c0 == 0) {
-                        if (a.S)
-                            reinterpret_cast<v2 *>(a.S)[m0 * a.n_src + (unsigned)e] = S;
-                        if (a.Sd)
-                            reinterpret_cast<v2 *>(a.Sd)[m0 * a.n_src + (unsigned)e] =
-                                a.inv_s * cmul(phk, B);
-                        if (a.idx)
-                            a.idx[m0 * a.n_src + (unsigned)e] = code;
-                    }
-                }
-            };
-            // Two coefficients per iteration give the scheduler two independent
-            // dependency chains (LDS read -> IF -> atomic) to interleave.
-            v2 ph_cur = ph0;
-            const v2 ph_step2 = cmul(ph_step, ph_step);
-            for (int e = threadIdx.x; e < E; e += 2 * NT) {
-                const int e2 = e + NT;
-                if constexpr (F == 1) {
-                    const v2 p1 = ph_cur, p2 = cmul(ph_cur, ph_step);
-                    ph_cur = cmul(ph_cur, ph_step2);
-                    coefficient(e, 0, e, p1);
-                    if (e2 < E)
-                        coefficient(e2, 0, e2, p2);
-                } else {
-                    int f, ik;
-                    split_flat(e, a.n_src, inv_nsrc, f, ik);
-                    coefficient(e, f, ik, cphl[ik]);
-                    if (e2 < E) {
-                        split_flat(e2, a.n_src, inv_nsrc, f, ik);
-                        coefficient(e2, f, ik, cphl[ik]);
-                    }
-                }
+        float scf[F];
+#pragma unroll
+        for (int ff = 0; ff < F; ++ff)
+            scf[ff] = fixed_scale(bsum[ff] * 1.001f);
+        for (int c0 = 0; c0 < (CHUNKED ? EH : 1); c0 += HB) {
+            const int cn = CHUNKED ? ((EH - c0) < HB ? (EH - c0) : HB) : EH;
+#pragma unroll
+            for (int i = 0; i < NST; ++i)
+                reinterpret_cast<unsigned long long *>(hq)[threadIdx.x + i * NT] = 0ull;
+            __syncthreads();
+            // scatter phase (Eq. 28)
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                if (key[i] < 0)
+                    continue;
+                const int f = key[i] >> SEGF;
+                const int d = (key[i] & ((1 << SEGF) - 1)) - c0;
+                if (d < 0 || d >= cn)
+                    continue;
+                float sc = scf[0];
+#pragma unroll
+                for (int ff = 1; ff < F; ++ff)
+                    sc = ff == f ? scf[ff] : sc;
+                atomicAdd(&hq[2 * d], (int)rintf(sv[i].x * sc));
+                atomicAdd(&hq[2 * d + 1], (int)rintf(sv[i].y * sc));
             }
             __syncthreads();
-            // Row stream-out.  A buffer resource bounded to the cn valid bins
+            // store phase.  A buffer resource bounded to the cn valid bins
             // makes the hardware drop the stores past the end, so every store
-            // instruction is unconditional and the next iteration waits only
-            // for its prefetched samples, not for these stores.
+            // instruction is unconditional.
             const __amdgpu_buffer_rsrc_t rs =
                 __builtin_amdgcn_make_buffer_rsrc(trow + c0, (short)0, cn * 8, kBufferWord3);
-            unsigned long long hr[NST], hi[NST];   // read every bin first: one LDS round trip
+            // bins are read in groups of SG: one LDS round trip per group
+            constexpr int SG = 6;
 #pragma unroll
-            for (int i = 0; i < NST; ++i) {
-                hr[i] = hacc[threadIdx.x + i * NT];
-                hi[i] = hacc[HB + threadIdx.x + i * NT];
-            }
+            for (int g0 = 0; g0 < NST; g0 += SG) {
+                __builtin_amdgcn_sched_barrier(0);
+                unsigned long long hv[SG];
 #pragma unroll
-            for (int i = 0; i < NST; ++i) {
-                hacc[threadIdx.x + i * NT] = 0ull;
-                hacc[HB + threadIdx.x + i * NT] = 0ull;
-            }
-            const float isc0 = 1.0f / sc0;   // exact: a power of two
+                for (int i = 0; i < SG; ++i)
+                    if (g0 + i < NST)
+                        hv[i] = reinterpret_cast<const unsigned long long *>(hq)[threadIdx.x + (g0 + i) * NT];
 #pragma unroll
-            for (int i = 0; i < NST; ++i) {
-                const int e = threadIdx.x + i * NT;
-                float isc = isc0;
-                if constexpr (F > 1) {
-                    int f = (int)(((float)(c0 + e) + 0.5f) * inv_ndst);
-                    f = f < nvalid ? f : nvalid - 1;
-                    isc = 1.0f / fixed_scale(bsum[par][f] * bmargin);
-                }
-                const v2 v = mk(from_fixed(hr[i]) * isc, from_fixed(hi[i]) * isc);
-                __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), rs, (unsigned)e * 8u,
-                                                      0, kNonTemporal);
-                if constexpr (DEBUG) {
-                    if (a.colstats && e < cn) {
-                        const int f = (c0 + e) / a.n_dst;
-                        atomicAdd(&colacc[3 * f], (double)v.x);
-                        atomicAdd(&colacc[3 * f + 1], (double)v.y);
-                        atomicAdd(&colacc[3 * f + 2], (double)v.x * v.x + (double)v.y * v.y);
+                for (int i = 0; i < SG; ++i) {
+                    if (g0 + i >= NST)
+                        continue;
+                    const int e = threadIdx.x + (g0 + i) * NT;
+                    float isc = 1.0f / scf[0];   // exact: a power of two
+                    if constexpr (F > 1) {
+                        int f = (int)(((float)(c0 + e) + 0.5f) * inv_ndst);
+                        f = f < nvalid ? f : nvalid - 1;
+                        float sc = scf[0];
+#pragma unroll
+                        for (int ff = 1; ff < F; ++ff)
+                            sc = ff == f ? scf[ff] : sc;
+                        isc = 1.0f / sc;
+                    }
+                    const int re = (int)(unsigned)hv[i];
+                    const int im = (int)(unsigned)(hv[i] >> 32);
+                    const v2 v = mk((float)re * isc, (float)im * isc);
+                    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), rs,
+                                                          (unsigned)e * 8u, 0, kNonTemporal);
+                    if constexpr (DEBUG) {
+                        if (a.colstats && e < cn) {
+                            const int f = (c0 + e) / a.n_dst;
+                            atomicAdd(&colacc[3 * f], (double)v.x);
+                            atomicAdd(&colacc[3 * f + 1], (double)v.y);
+                            atomicAdd(&colacc[3 * f + 2], (double)v.x * v.x + (double)v.y * v.y);
+                        }
                     }
                 }
             }
-            if (c0 + HB < EH)
-                __syncthreads();   // bins zeroed before the next chunk's scatter
+            if (CHUNKED && c0 + HB < EH)
+                __syncthreads();   // store reads done before the next chunk is cleared
         }
         if constexpr (DEBUG) {
             if (a.colstats) {
@@ -638,15 +724,16 @@ __device__ __forceinline__ float wave_max(float v)
 }
 
 template <int NF, int NZ>
-__global__ __launch_bounds__(Geo<NF>::NT, (NF == 8192 || NZ == 16) ? 2 : 3) void max_kernel(MaxArgs a)
+__global__ __launch_bounds__(Geo<NF>::NT, NF == 8192 ? 4 : 3) void max_kernel(MaxArgs a)
 {
     using G = Geo<NF>;
     constexpr int F = G::F, NT = G::NT, Q = NF / 16;
     __shared__ v2 lds[G::LDS];
     __shared__ float red[NT / 64];
 
+    __shared__ v2 twl[Twiddles<NF>::TW];
     Twiddles<NF> tw;
-    tw.load(reinterpret_cast<const v2 *>(a.twid));
+    tw.load(twl, reinterpret_cast<const v2 *>(a.twid));
     const float *__restrict__ x = a.x;
     const float inv_nsrc = 1.0f / (float)a.n_src;
     const int64_t n_pairs = (a.n_frames + 1) / 2;
@@ -707,7 +794,7 @@ __global__ __launch_bounds__(Geo<NF>::NT, (NF == 8192 || NZ == 16) ? 2 : 3) void
         }
         fetch(it + gridDim.x);
         __syncthreads();
-        tw.passes(lds);
+        tw.passes(lds, twl);
         const int E = nvp * a.n_src;
         for (int e = threadIdx.x; e < E; e += NT) {
             int f, ik;
@@ -1023,10 +1110,18 @@ hipError_t launch_fwd_nz(const FwdArgs &a, int grid, hipStream_t s)
     const bool debug = a.S || a.Sd || a.idx || a.colstats;
     const dim3 g(grid), b(Geo<NF>::NT);
     const size_t dyn = fwd_dyn_lds(NF, a.n_src);
-    if (debug)
-        hipLaunchKernelGGL((fwd_kernel<NF, NZ, true>), g, b, dyn, s, a);
-    else
-        hipLaunchKernelGGL((fwd_kernel<NF, NZ, false>), g, b, dyn, s, a);
+    const bool chunked = (int64_t)Geo<NF>::F * a.n_dst > Geo<NF>::LDS;
+    if (debug) {
+        hipLaunchKernelGGL((fwd_kernel<NF, NZ, 9, true, true>), g, b, dyn, s, a);
+    } else if (chunked) {
+        hipLaunchKernelGGL((fwd_kernel<NF, NZ, 9, false, true>), g, b, dyn, s, a);
+    } else {
+        switch (fwd_rounds(NF, a.n_src)) {
+        case 3: hipLaunchKernelGGL((fwd_kernel<NF, NZ, 3, false, false>), g, b, dyn, s, a); break;
+        case 5: hipLaunchKernelGGL((fwd_kernel<NF, NZ, 5, false, false>), g, b, dyn, s, a); break;
+        default: hipLaunchKernelGGL((fwd_kernel<NF, NZ, 9, false, false>), g, b, dyn, s, a); break;
+        }
+    }
     return hipGetLastError();
 }
 
@@ -1066,9 +1161,9 @@ int occ_fwd_t(int L, int n_src)
     // every variant of one N_f has the same LDS and launch bounds
     const size_t dyn = fwd_dyn_lds(NF, n_src);
     switch (nz_rows<NF>(L)) {
-    case 4: return occ_of(fwd_kernel<NF, 4, false>, Geo<NF>::NT, dyn);
-    case 8: return occ_of(fwd_kernel<NF, 8, false>, Geo<NF>::NT, dyn);
-    default: return occ_of(fwd_kernel<NF, 16, false>, Geo<NF>::NT, dyn);
+    case 4: return occ_of(fwd_kernel<NF, 4, 9, false, true>, Geo<NF>::NT, dyn);
+    case 8: return occ_of(fwd_kernel<NF, 8, 9, false, true>, Geo<NF>::NT, dyn);
+    default: return occ_of(fwd_kernel<NF, 16, 9, false, true>, Geo<NF>::NT, dyn);
     }
 }
 
@@ -1089,6 +1184,14 @@ int occ_max_t(int L)
 size_t fwd_dyn_lds(int nfft, int n_src)
 {
     return nfft < 4096 ? sizeof(float2) * (size_t)n_src : 0;
+}
+
+int fwd_rounds(int nfft, int n_src)
+{
+    const int F = nfft >= 4096 ? 1 : 4096 / nfft;
+    const int NT = nfft > 4096 ? nfft / 16 : 256;
+    const int need = (F * n_src + NT - 1) / NT;
+    return need <= 3 ? 3 : (need <= 5 ? 5 : 9);
 }
 
 #define SST_DISPATCH_NF(nfft, EXPR)                 \
@@ -1184,7 +1287,7 @@ template <int NF>
 size_t fwd_static_lds_t()
 {
     hipFuncAttributes at{};
-    if (hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&fwd_kernel<NF, 16, true>)) !=
+    if (hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&fwd_kernel<NF, 16, 9, true, true>)) !=
         hipSuccess)
         return 0;
     return at.sharedSizeBytes;

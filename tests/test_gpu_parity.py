@@ -73,6 +73,10 @@ def _forward_parity(sst, x, cfg, frame0=0, nframes=None, label=""):
     rep, _ = classify_indices(idx_g, o.idx, o.frac, o.S, o.Sd, o.gamma, cfg.nfft, cfg.subdiv,
                               s_pack, ny, plan.n_dst)
     _say(f"  indices: {rep}")
+    # per-coefficient STFT error in units of 2^-24 ||y_m|| (the index rule's error model)
+    eun = np.abs(S_g - o.S) / (2.0 ** -24 * ny[:, None] + 1e-300)
+    _say(f"  |dS|/(2^-24 |y|): rms {np.sqrt(np.mean(eun ** 2)):.2f} "
+         f"p99.99 {np.quantile(eun, 0.9999):.2f} max {eun.max():.2f}")
     assert rep.ok(), (rep, rep.details)
     # T after reconciling index decisions (Eq. 28 with the GPU's rounding decisions)
     T_rec = reconciled_T(o.S, idx_g, plan.n_dst)
