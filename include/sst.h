@@ -215,6 +215,79 @@ sst_status sst_inverse(sst_plan_t plan, const float *T, int64_t frame0, int64_t 
                        const int32_t *ridge, int32_t n_comp, int32_t hw, float *xhat,
                        const float *xref, double *err, uint32_t flags, void *stream);
 
+/*
+ * Batched form: many channels, each with its own parameters (length, hop,
+ * N_f, window, band, subdivision, threshold), processed by one persistent
+ * launch per group of channels that share N_f and the pass-1 tap-row count
+ * (so a mixed batch of three DFT sizes is three launches, which a caller
+ * may capture in one hipGraph).  Work items are (channel, group of frames);
+ * every item computes exactly what sst_forward computes for that channel,
+ * with the same kernels, so a channel's T is bit-identical to a
+ * single-channel sst_forward of it.  Calls follow the single-channel rules:
+ * asynchronous on `stream`, caller-owned device memory, no device allocation.
+ */
+typedef struct sst_batch_s *sst_batch_t;
+
+/*
+ * sst_batch_plan -- validate and plan n_channels channels (params[c] as for
+ * sst_plan).  Host only.  Errors as sst_plan (the message names the channel).
+ */
+sst_status sst_batch_plan(const sst_params *params, int32_t n_channels, sst_batch_t *out);
+
+/*
+ * sst_batch_query -- shape of channel c (as sst_plan_query; its
+ * workspace_bytes is the whole batch's workspace).
+ */
+sst_status sst_batch_query(sst_batch_t batch, int32_t c, sst_shape *out);
+
+/*
+ * sst_batch_bind -- attach one caller-owned workspace (256-byte aligned, at
+ * least workspace_bytes) and upload every channel's tables on `stream`.
+ */
+sst_status sst_batch_bind(sst_batch_t batch, void *workspace_dev, size_t bytes, void *stream);
+
+/*
+ * sst_batch_set_io -- record channel c's device buffers (host only):
+ *   x      float [n_samples of c]
+ *   T      complex float [n_frames of c][n_dst of c], whole signal; channels
+ *          processed by different forward calls may share T memory
+ *   ridge  int32 [n_comp][n_frames] (inverse; may be NULL for forward-only use)
+ *   n_comp components, hw zone half-width (inverse)
+ *   xhat   float [n_comp][n_samples] (inverse)
+ *   xref, err  optional, as for sst_inverse
+ * Takes effect at the next sst_batch_commit.
+ */
+sst_status sst_batch_set_io(sst_batch_t batch, int32_t c, const float *x, float *T,
+                            const int32_t *ridge, int32_t n_comp, int32_t hw, float *xhat,
+                            const float *xref, double *err);
+
+/*
+ * sst_batch_commit -- upload the per-channel descriptors built from the
+ * recorded buffers.  Blocks until the upload is done (setup call; not for
+ * graph capture).  Errors: SST_E_STATE (not bound), SST_E_DEVICE.
+ */
+sst_status sst_batch_commit(sst_batch_t batch, void *stream);
+
+/*
+ * sst_batch_forward -- forward SST (as sst_forward over every frame) of
+ * channels [c_begin, c_end): relative thresholds are computed per channel
+ * unless SST_FWD_REUSE_GAMMA.  Kernel launches only, so it can be captured.
+ * Errors: SST_E_ARG (range, a channel without x or T), SST_E_STATE, SST_E_DEVICE.
+ */
+sst_status sst_batch_forward(sst_batch_t batch, int32_t c_begin, int32_t c_end, uint32_t flags,
+                             void *stream);
+
+/*
+ * sst_batch_inverse -- direct inverse (as sst_inverse over every frame, no
+ * flags) of every component of channels [c_begin, c_end) in one launch.
+ * Kernel launches only.  Errors: SST_E_ARG (a channel without ridge/xhat),
+ * SST_E_STATE, SST_E_UNSUPPORTED (z N_f > 65536), SST_E_DEVICE.
+ */
+sst_status sst_batch_inverse(sst_batch_t batch, int32_t c_begin, int32_t c_end, void *stream);
+
+/* sst_batch_destroy -- release the batch's host memory. */
+void sst_batch_destroy(sst_batch_t batch);
+
 /* sst_destroy -- release the plan's host memory (the workspace stays the caller's). */
 void sst_destroy(sst_plan_t plan);
 

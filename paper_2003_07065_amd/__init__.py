@@ -8,7 +8,8 @@ device, and raises otherwise.
 
 Names mirror the C ABI: ``Plan`` wraps sst_plan / sst_plan_query /
 sst_plan_bind / sst_destroy, and its methods ``forward``, ``ridge`` and
-``inverse`` wrap sst_forward, sst_ridge and sst_inverse.
+``inverse`` wrap sst_forward, sst_ridge and sst_inverse.  ``Batch`` wraps the
+sst_batch_* calls (many channels, one persistent launch per DFT-size group).
 """
 from __future__ import annotations
 
@@ -36,7 +37,9 @@ SST_INV_EQ15 = 2
 
 EXPORTED = ("sst_plan", "sst_plan_query", "sst_plan_bind", "sst_forward", "sst_ridge",
             "sst_inverse", "sst_destroy", "sst_status_string", "sst_last_error",
-            "sst_critical_hf")
+            "sst_critical_hf", "sst_batch_plan", "sst_batch_query", "sst_batch_bind",
+            "sst_batch_set_io", "sst_batch_commit", "sst_batch_forward", "sst_batch_inverse",
+            "sst_batch_destroy")
 
 
 class SSTError(RuntimeError):
@@ -121,8 +124,19 @@ def lib():
     L.sst_critical_hf.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                   ctypes.POINTER(ctypes.c_double),
                                   ctypes.POINTER(ctypes.c_double)]
+    L.sst_batch_plan.argtypes = [ctypes.POINTER(Params), i32, ctypes.POINTER(vp)]
+    L.sst_batch_query.argtypes = [vp, i32, ctypes.POINTER(Shape)]
+    L.sst_batch_bind.argtypes = [vp, vp, ctypes.c_size_t, vp]
+    L.sst_batch_set_io.argtypes = [vp, i32, vp, vp, vp, i32, i32, vp, vp, vp]
+    L.sst_batch_commit.argtypes = [vp, vp]
+    L.sst_batch_forward.argtypes = [vp, i32, i32, u32, vp]
+    L.sst_batch_inverse.argtypes = [vp, i32, i32, vp]
+    L.sst_batch_destroy.argtypes = [vp]
+    L.sst_batch_destroy.restype = None
     for name in ("sst_plan", "sst_plan_query", "sst_plan_bind", "sst_forward", "sst_ridge",
-                 "sst_inverse", "sst_critical_hf"):
+                 "sst_inverse", "sst_critical_hf", "sst_batch_plan", "sst_batch_query",
+                 "sst_batch_bind", "sst_batch_set_io", "sst_batch_commit", "sst_batch_forward",
+                 "sst_batch_inverse"):
         getattr(L, name).restype = i32
     _lib = L
     return L
@@ -155,6 +169,34 @@ def _stream_handle(device) -> int:
     return int(torch.cuda.current_stream(device).cuda_stream)
 
 
+def _params(n_samples: int, fs: float, win_len: int, sigma: float, hop: int, nfft: int,
+            f_lo: float, f_hi: float, subdiv: int, thr_mode: str, thr: float, window, dwindow,
+            keep: list) -> Params:
+    p = Params()
+    p.struct_size = ctypes.sizeof(Params)
+    p.n_samples = int(n_samples)
+    p.fs = float(fs)
+    p.win_len = int(win_len)
+    p.sigma = float(sigma)
+    if window is not None:
+        import numpy as np
+        w = np.ascontiguousarray(np.asarray(window, dtype=np.float64))
+        dw = np.ascontiguousarray(np.asarray(dwindow, dtype=np.float64))
+        keep += [w, dw]
+        p.window = w.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        p.dwindow = dw.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    p.hop = int(hop)
+    p.nfft = int(nfft)
+    p.f_lo = float(f_lo)
+    p.f_hi = float(f_hi)
+    p.subdiv = int(subdiv)
+    p.thr_mode = SST_THR_ABS if thr_mode == "abs" else SST_THR_REL_MAX
+    p.thr = float(thr)
+    p.precision = SST_PREC_FP32_FFT
+    p.flags = 0
+    return p
+
+
 class Plan:
     """A transform plan (host tables) bound to a torch-allocated device workspace."""
 
@@ -162,29 +204,9 @@ class Plan:
                  nfft: int, f_lo: float, f_hi: float, subdiv: int = 1, thr_mode: str = "rel",
                  thr: float = 1e-3, window=None, dwindow=None, device=None):
         self._h = None
-        p = Params()
-        p.struct_size = ctypes.sizeof(Params)
-        p.n_samples = int(n_samples)
-        p.fs = float(fs)
-        p.win_len = int(win_len)
-        p.sigma = float(sigma)
         keep = []
-        if window is not None:
-            import numpy as np
-            w = np.ascontiguousarray(np.asarray(window, dtype=np.float64))
-            dw = np.ascontiguousarray(np.asarray(dwindow, dtype=np.float64))
-            keep += [w, dw]
-            p.window = w.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-            p.dwindow = dw.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-        p.hop = int(hop)
-        p.nfft = int(nfft)
-        p.f_lo = float(f_lo)
-        p.f_hi = float(f_hi)
-        p.subdiv = int(subdiv)
-        p.thr_mode = SST_THR_ABS if thr_mode == "abs" else SST_THR_REL_MAX
-        p.thr = float(thr)
-        p.precision = SST_PREC_FP32_FFT
-        p.flags = 0
+        p = _params(n_samples, fs, win_len, sigma, hop, nfft, f_lo, f_hi, subdiv, thr_mode, thr,
+                    window, dwindow, keep)
         h = ctypes.c_void_p()
         _check(lib().sst_plan(ctypes.byref(p), ctypes.byref(h)), "sst_plan")
         self._h = h
@@ -309,6 +331,96 @@ class Plan:
     def close(self):
         if self._h is not None and _lib is not None:
             _lib.sst_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many channels with their own parameters (sst_batch_*).
+
+    ``configs`` is a list of (n_samples, cfg) pairs (cfg as for Plan.from_config).
+    Buffers are recorded with ``set_io`` and uploaded with ``commit``; ``forward``
+    and ``inverse`` then launch kernels only (capturable in a HIP graph).
+    """
+
+    def __init__(self, configs, device="cuda"):
+        import torch
+        self._h = None
+        n = len(configs)
+        arr = (Params * n)()
+        keep = []
+        for i, (ns, cfg) in enumerate(configs):
+            arr[i] = _params(ns, cfg.fs, cfg.win_len, cfg.sigma, cfg.hop, cfg.nfft, cfg.f_lo,
+                             cfg.f_hi, cfg.subdiv, cfg.thr_mode, cfg.thr, None, None, keep)
+        h = ctypes.c_void_p()
+        _check(lib().sst_batch_plan(arr, n, ctypes.byref(h)), "sst_batch_plan")
+        self._h = h
+        self.n_channels = n
+        self.shapes = []
+        for c in range(n):
+            sh = Shape()
+            _check(lib().sst_batch_query(self._h, c, ctypes.byref(sh)), "sst_batch_query")
+            self.shapes.append(sh)
+        device = torch.device(device)
+        if device.index is None:
+            device = torch.device("cuda", torch.cuda.current_device())
+        self.device = device
+        nbytes = int(self.shapes[0].workspace_bytes)
+        with torch.cuda.device(device):
+            ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+            base = int(ws.data_ptr()) + ((-int(ws.data_ptr())) % 256)
+            _check(lib().sst_batch_bind(self._h, ctypes.c_void_p(base), ctypes.c_size_t(nbytes),
+                                        ctypes.c_void_p(_stream_handle(device))), "sst_batch_bind")
+        self.workspace = ws
+        self._io = [None] * n
+
+    def set_io(self, c: int, x, T, ridge=None, hw: int = 0, xhat=None, xref=None, err=None):
+        """Record channel c's buffers (kept alive by the batch until replaced)."""
+        import torch
+        sh = self.shapes[c]
+        if x is None or x.dtype != torch.float32 or x.numel() != sh.n_samples:
+            raise ValueError(f"channel {c}: x must be float32 with n_samples elements")
+        if T is None or T.dtype != torch.complex64 or T.numel() < sh.n_frames * sh.n_dst:
+            raise ValueError(f"channel {c}: T must be complex64 [n_frames, n_dst]")
+        n_comp = 0
+        if ridge is not None:
+            n_comp = ridge.shape[0] if ridge.dim() == 2 else 1
+            if ridge.dtype != torch.int32 or ridge.numel() != n_comp * sh.n_frames:
+                raise ValueError(f"channel {c}: ridge must be int32 [n_comp, n_frames]")
+            if xhat is None or xhat.dtype != torch.float32 or xhat.numel() < n_comp * sh.n_samples:
+                raise ValueError(f"channel {c}: xhat must be float32 [n_comp, n_samples]")
+        _check(lib().sst_batch_set_io(self._h, c, ctypes.c_void_p(x.data_ptr()),
+                                      ctypes.c_void_p(T.data_ptr()), ctypes.c_void_p(_ptr(ridge)),
+                                      int(n_comp), int(hw), ctypes.c_void_p(_ptr(xhat)),
+                                      ctypes.c_void_p(_ptr(xref)), ctypes.c_void_p(_ptr(err))),
+               "sst_batch_set_io")
+        self._io[c] = (x, T, ridge, xhat, xref, err)
+
+    def commit(self):
+        _check(lib().sst_batch_commit(self._h, ctypes.c_void_p(_stream_handle(self.device))),
+               "sst_batch_commit")
+
+    def forward(self, c_begin: int = 0, c_end: Optional[int] = None, reuse_gamma: bool = False):
+        c_end = self.n_channels if c_end is None else c_end
+        _check(lib().sst_batch_forward(self._h, int(c_begin), int(c_end),
+                                       SST_FWD_REUSE_GAMMA if reuse_gamma else 0,
+                                       ctypes.c_void_p(_stream_handle(self.device))),
+               "sst_batch_forward")
+
+    def inverse(self, c_begin: int = 0, c_end: Optional[int] = None):
+        c_end = self.n_channels if c_end is None else c_end
+        _check(lib().sst_batch_inverse(self._h, int(c_begin), int(c_end),
+                                       ctypes.c_void_p(_stream_handle(self.device))),
+               "sst_batch_inverse")
+
+    def close(self):
+        if self._h is not None and _lib is not None:
+            _lib.sst_batch_destroy(self._h)
         self._h = None
 
     def __del__(self):

@@ -15,6 +15,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <algorithm>
 #include <new>
 #include <string>
 #include <vector>
@@ -40,17 +41,10 @@ sst_status hip_fail(hipError_t e, const char *what)
 
 constexpr double kTwoPi = 6.283185307179586476925286766559;
 constexpr size_t kAlign = 256;
-constexpr int kMaxPartials = 8192;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
-
-int64_t mod_exact(int64_t a, int64_t m)
-{
-    int64_t r = a % m;
-    return r < 0 ? r + m : r;
-}
 
 }  // namespace
 
@@ -61,9 +55,9 @@ struct sst_plan_s {
     double s_pack = 1.0;
     double g0 = 0.0;
     int G = 0, lo_bits = 0, n_lo = 0, n_hi = 0;
-    // workspace layout (bytes)
-    size_t off_win = 0, off_cph = 0, off_twid = 0, off_phlo = 0, off_phhi = 0;
-    size_t tables_end = 0, off_part = 0, ws_bytes = 0;
+    // workspace layout (bytes): control block, descriptor slot, tables
+    size_t off_desc = 0, off_idesc = 0, off_win = 0, off_twid = 0, off_phlo = 0, off_phhi = 0;
+    size_t tables_end = 0, ws_bytes = 0;
     std::vector<unsigned char> blob;   // host image of [off_win, tables_end)
     // bound state
     unsigned char *ws = nullptr;
@@ -112,6 +106,105 @@ sst_status validate(const sst_params *p)
     if (p->flags != 0)
         return fail(SST_E_ARG, "params.flags must be 0");
     return SST_OK;
+}
+
+// Descriptor of one channel for a forward call over frames [frame0, frame0 + nframes).
+sst::ChanDesc chan_desc(const sst_plan_s *pl, const float *x, int64_t frame0, int64_t nframes,
+                        float *T, const sst_fwd_aux *aux, sst::Ctrl *ctrl)
+{
+    sst::ChanDesc d{};
+    d.x = x;
+    d.n = pl->p.n_samples;
+    d.n_frames = pl->n_frames;
+    d.frame0 = frame0;
+    d.nframes = nframes;
+    d.win = reinterpret_cast<const float2 *>(pl->ws + pl->off_win);
+    d.ctrl = ctrl;
+    d.T = reinterpret_cast<float2 *>(T);
+    if (aux) {
+        d.S = reinterpret_cast<float2 *>(aux->S);
+        d.Sd = reinterpret_cast<float2 *>(aux->Sd);
+        d.idx = aux->idx;
+        d.colstats = aux->colstats;
+    }
+    d.L = pl->p.win_len;
+    d.M = pl->M;
+    d.hop = pl->p.hop;
+    d.k1 = pl->k1;
+    d.n_src = pl->n_src;
+    d.n_dst = pl->n_dst;
+    d.z = pl->p.subdiv;
+    d.thr_mode = pl->p.thr_mode;
+    d.thr = (float)pl->p.thr;
+    d.inv_s = (float)(1.0 / pl->s_pack);
+    d.cdelta = (float)(pl->p.nfft / (kTwoPi * pl->s_pack));
+    return d;
+}
+
+// Descriptor of one channel's inverse over frames [frame0, frame0 + nframes).
+sst::InvDesc inv_desc(const sst_plan_s *pl, const float *T, int64_t frame0, int64_t nframes,
+                      const int32_t *ridge, int n_comp, int hw, float *xhat, const float *xref,
+                      double *err, bool accumulate)
+{
+    sst::InvDesc a{};
+    a.T = reinterpret_cast<const float2 *>(T);
+    a.ridge = ridge;
+    a.xhat = xhat;
+    a.xref = xref;
+    a.err = err;
+    a.win = reinterpret_cast<const float2 *>(pl->ws + pl->off_win);
+    a.ph_lo = reinterpret_cast<const float2 *>(pl->ws + pl->off_phlo);
+    a.ph_hi = reinterpret_cast<const float2 *>(pl->ws + pl->off_phhi);
+    a.n = pl->p.n_samples;
+    a.n_frames = pl->n_frames;
+    a.frame0 = frame0;
+    a.nframes = nframes;
+    a.L = pl->p.win_len;
+    a.M = pl->M;
+    a.hop = pl->p.hop;
+    a.nfft = pl->p.nfft;
+    a.k1 = pl->k1;
+    a.z = pl->p.subdiv;
+    a.n_dst = pl->n_dst;
+    a.hw = hw;
+    a.n_comp = n_comp;
+    a.G = pl->G;
+    a.lo_bits = pl->lo_bits;
+    a.g_pow2 = is_pow2(pl->G) ? 1 : 0;
+    a.inv_G = (float)(1.0 / pl->G);
+    a.inv_nfft = (float)(1.0 / pl->p.nfft);
+    a.accumulate = accumulate ? 1 : 0;
+    if (frame0 == 0 && nframes == pl->n_frames) {
+        a.span_lo = 0;
+        a.span_len = pl->p.n_samples;
+    } else {
+        int64_t lo = frame0 * pl->p.hop - pl->M;
+        int64_t hi = (frame0 + nframes - 1) * pl->p.hop + pl->M;
+        if (lo < 0)
+            lo = 0;
+        if (hi > pl->p.n_samples - 1)
+            hi = pl->p.n_samples - 1;
+        a.span_lo = lo;
+        a.span_len = hi >= lo ? hi - lo + 1 : 0;
+    }
+    a.tiles = (a.span_len + 255) / 256;
+    a.blk0 = 0;
+    a.blk_end = (int64_t)n_comp * a.tiles;
+    return a;
+}
+
+sst::InvLaunch inv_launch(const sst::InvDesc *dev, int n_ch, int64_t blk_begin, int max_w,
+                          int max_tab)
+{
+    sst::InvLaunch l{};
+    l.ch = dev;
+    l.n_ch = n_ch;
+    l.blk_begin = blk_begin;
+    l.max_w = max_w;
+    l.max_tab = max_tab;
+    const int fb = 2048 / max_w;
+    l.fb = fb < 1 ? 1 : (fb > 128 ? 128 : fb);
+    return l;
 }
 
 }  // namespace
@@ -194,10 +287,12 @@ sst_status sst_plan(const sst_params *params, sst_plan_t *out)
 
     // Workspace layout.
     size_t off = align_up(sizeof(sst::Ctrl));
+    pl->off_desc = off;
+    off = align_up(off + sizeof(sst::ChanDesc));
+    pl->off_idesc = off;
+    off = align_up(off + sizeof(sst::InvDesc));
     pl->off_win = off;
     off = align_up(off + sizeof(float) * 2 * (size_t)L);
-    pl->off_cph = off;
-    off = align_up(off + sizeof(float) * 2 * (size_t)pl->n_src);
     pl->off_twid = off;
     off = align_up(off + sizeof(float) * 2 * (size_t)NF);
     pl->off_phlo = off;
@@ -205,8 +300,6 @@ sst_status sst_plan(const sst_params *params, sst_plan_t *out)
     pl->off_phhi = off;
     off = align_up(off + sizeof(float) * 2 * (size_t)pl->n_hi);
     pl->tables_end = off;
-    pl->off_part = off;
-    off = align_up(off + sizeof(float) * (size_t)kMaxPartials);
     pl->ws_bytes = off;
 
     try {
@@ -222,10 +315,6 @@ sst_status sst_plan(const sst_params *params, sst_plan_t *out)
     };
     for (int i = 0; i < L; ++i)
         put(pl->off_win, i, g[i], pl->s_pack * gd[i]);
-    for (int k = k1; k <= k2; ++k) {
-        const double a = kTwoPi * (double)mod_exact((int64_t)k * pl->M, NF) / NF;
-        put(pl->off_cph, k - k1, std::cos(a), std::sin(a));
-    }
     for (int r = 0; r < NF; ++r) {
         const double a = kTwoPi * (double)r / NF;
         put(pl->off_twid, r, std::cos(a), -std::sin(a));
@@ -286,7 +375,7 @@ sst_status sst_plan_bind(sst_plan_t pl, void *workspace, size_t bytes, void *str
     e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
     if (e != hipSuccess)
         return hip_fail(e, "hipDeviceGetAttribute(shared memory)");
-    const size_t need = sst::fwd_lds_bytes(pl->p.nfft, pl->n_src);
+    const size_t need = sst::fwd_lds_bytes(pl->p.nfft);
     if (need == 0 || need > (size_t)max_lds)
         return fail(SST_E_UNSUPPORTED, "forward kernel needs " + std::to_string(need) +
                                            " bytes of LDS, the device offers " +
@@ -294,9 +383,8 @@ sst_status sst_plan_bind(sst_plan_t pl, void *workspace, size_t bytes, void *str
     pl->ws = ws;
     pl->device = dev;
     pl->cus = cus;
-    pl->fwd_grid_cap = cus * sst::fwd_occupancy(pl->p.nfft, pl->p.win_len, pl->n_src);
-    int mg = cus * sst::max_occupancy(pl->p.nfft, pl->p.win_len);
-    pl->max_grid_cap = mg < kMaxPartials ? mg : kMaxPartials;
+    pl->fwd_grid_cap = cus * sst::fwd_occupancy(pl->p.nfft, pl->p.win_len);
+    pl->max_grid_cap = cus * sst::max_occupancy(pl->p.nfft, pl->p.win_len);
     return SST_OK;
 }
 
@@ -315,74 +403,43 @@ sst_status sst_forward(sst_plan_t pl, const float *x, int64_t frame0, int64_t nf
         return fail(SST_E_ARG, "unknown forward flags");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const int NF = pl->p.nfft;
+    const int F = sst::fwd_frames_per_iter(NF);
     sst::Ctrl *ctrl = reinterpret_cast<sst::Ctrl *>(pl->ws);
-    const float2 *win = reinterpret_cast<const float2 *>(pl->ws + pl->off_win);
-    const float2 *twid = reinterpret_cast<const float2 *>(pl->ws + pl->off_twid);
-
-    if (!(flags & SST_FWD_REUSE_GAMMA)) {
-        sst::MaxArgs m{};
-        m.x = x;
-        m.n = pl->p.n_samples;
-        m.n_frames = pl->n_frames;
-        m.win = win;
-        m.twid = twid;
-        m.partial = reinterpret_cast<float *>(pl->ws + pl->off_part);
-        m.L = pl->p.win_len;
-        m.M = pl->M;
-        m.hop = pl->p.hop;
-        m.k1 = pl->k1;
-        m.n_src = pl->n_src;
-        const int F = sst::fwd_frames_per_iter(NF);
-        const int64_t iters = ((pl->n_frames + 1) / 2 + F - 1) / F;
-        const int grid = (int)(iters < pl->max_grid_cap ? iters : pl->max_grid_cap);
-        hipError_t e = sst::launch_threshold(NF, m, ctrl, pl->p.thr_mode, (float)pl->p.thr,
-                                             grid, s);
+    sst::ChanDesc *slot = reinterpret_cast<sst::ChanDesc *>(pl->ws + pl->off_desc);
+    const bool threshold = !(flags & SST_FWD_REUSE_GAMMA);
+    sst::ChanDesc d = chan_desc(pl, x, frame0, nframes, T, aux, ctrl);
+    d.item0 = 0;
+    d.item_end = (nframes + F - 1) / F;
+    d.mitem0 = 0;
+    d.mitem_end = (threshold && pl->p.thr_mode == SST_THR_REL_MAX)
+                      ? ((pl->n_frames + 1) / 2 + F - 1) / F : 0;
+    hipError_t e = sst::launch_put_desc(d, slot, s);
+    if (e != hipSuccess)
+        return hip_fail(e, "descriptor upload");
+    sst::GroupLaunch g{};
+    g.ch = slot;
+    g.n_ch = 1;
+    g.twid = reinterpret_cast<const float2 *>(pl->ws + pl->off_twid);
+    if (threshold) {
+        g.item_begin = 0;
+        g.item_stop = d.mitem_end;
+        const int grid = (int)(d.mitem_end < pl->max_grid_cap ? d.mitem_end : pl->max_grid_cap);
+        e = sst::launch_threshold(NF, pl->p.win_len, g, grid, s);
         if (e != hipSuccess)
             return hip_fail(e, "threshold launch");
     }
     if (aux && aux->gamma) {
-        hipError_t e = hipMemcpyAsync(aux->gamma, &ctrl->gamma, sizeof(float),
-                                      hipMemcpyDeviceToDevice, s);
+        e = hipMemcpyAsync(aux->gamma, &ctrl->gamma, sizeof(float), hipMemcpyDeviceToDevice, s);
         if (e != hipSuccess)
             return hip_fail(e, "hipMemcpyAsync(gamma)");
     }
     if (nframes == 0)
         return SST_OK;
-
-    sst::FwdArgs a{};
-    a.x = x;
-    a.n = pl->p.n_samples;
-    a.frame0 = frame0;
-    a.nframes = nframes;
-    a.win = win;
-    a.cphase = reinterpret_cast<const float2 *>(pl->ws + pl->off_cph);
-    a.twid = twid;
-    a.ctrl = ctrl;
-    a.T = reinterpret_cast<float2 *>(T);
-    if (aux) {
-        a.S = reinterpret_cast<float2 *>(aux->S);
-        a.Sd = reinterpret_cast<float2 *>(aux->Sd);
-        a.idx = aux->idx;
-        a.colstats = aux->colstats;
-    }
-    a.L = pl->p.win_len;
-    a.M = pl->M;
-    a.hop = pl->p.hop;
-    a.k1 = pl->k1;
-    a.n_src = pl->n_src;
-    a.n_dst = pl->n_dst;
-    a.z = pl->p.subdiv;
-    {
-        const int nt = sst::fwd_threads(NF);
-        const double ang = kTwoPi * (double)mod_exact((int64_t)nt * pl->M, NF) / NF;
-        a.cph_step = make_float2((float)std::cos(ang), (float)std::sin(ang));
-    }
-    a.inv_s = (float)(1.0 / pl->s_pack);
-    a.cdelta = (float)(NF / (kTwoPi * pl->s_pack));
-    const int F = sst::fwd_frames_per_iter(NF);
-    const int64_t iters = (nframes + F - 1) / F;
-    const int grid = (int)(iters < pl->fwd_grid_cap ? iters : pl->fwd_grid_cap);
-    hipError_t e = sst::launch_forward(NF, a, grid, s);
+    g.item_begin = 0;
+    g.item_stop = d.item_end;
+    const bool debug = aux && (aux->S || aux->Sd || aux->idx || aux->colstats);
+    const int grid = (int)(d.item_end < pl->fwd_grid_cap ? d.item_end : pl->fwd_grid_cap);
+    e = sst::launch_forward(NF, pl->p.win_len, pl->n_src, pl->n_dst, debug, g, grid, s);
     if (e != hipSuccess)
         return hip_fail(e, "forward launch");
     return SST_OK;
@@ -443,74 +500,357 @@ sst_status sst_inverse(sst_plan_t pl, const float *T, int64_t frame0, int64_t nf
         return fail(SST_E_ARG, "err needs xref and a whole-signal call without accumulation");
     if (pl->G > 65536)
         return fail(SST_E_UNSUPPORTED, "inverse needs subdiv * nfft <= 65536");
-
-    sst::InvArgs a{};
-    a.T = reinterpret_cast<const float2 *>(T);
-    a.ridge = ridge;
-    a.xhat = xhat;
-    a.xref = xref;
-    a.err = err;
-    a.win = reinterpret_cast<const float2 *>(pl->ws + pl->off_win);
-    a.ph_lo = reinterpret_cast<const float2 *>(pl->ws + pl->off_phlo);
-    a.ph_hi = reinterpret_cast<const float2 *>(pl->ws + pl->off_phhi);
-    a.n = pl->p.n_samples;
-    a.n_frames = pl->n_frames;
-    a.frame0 = frame0;
-    a.nframes = nframes;
-    a.L = pl->p.win_len;
-    a.M = pl->M;
-    a.hop = pl->p.hop;
-    a.nfft = pl->p.nfft;
-    a.k1 = pl->k1;
-    a.z = pl->p.subdiv;
-    a.n_dst = pl->n_dst;
-    a.hw = hw;
-    a.n_comp = n_comp;
-    a.G = pl->G;
-    a.lo_bits = pl->lo_bits;
-    a.g_pow2 = is_pow2(pl->G) ? 1 : 0;
-    a.inv_G = (float)(1.0 / pl->G);
-    a.inv_nfft = (float)(1.0 / pl->p.nfft);
-    a.accumulate = accumulate ? 1 : 0;
-    const int W = 2 * hw + 1;
-    int fb = 2048 / W;
-    a.fb = fb < 1 ? 1 : (fb > 128 ? 128 : fb);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    sst::InvDesc a = inv_desc(pl, T, frame0, nframes, ridge, n_comp, hw, xhat, xref, err,
+                              accumulate);
+    sst::InvDesc *slot = reinterpret_cast<sst::InvDesc *>(pl->ws + pl->off_idesc);
 
     if (flags & SST_INV_EQ15) {
         if (pl->p.hop != 1)
             return fail(SST_E_ARG, "SST_INV_EQ15 needs hop == 1");
         a.span_lo = frame0;
         a.span_len = nframes;
-        hipError_t e = sst::launch_inverse_eq15(a, (float)(1.0 / (pl->p.nfft * pl->g0)), s);
+        hipError_t e = sst::launch_put_inv_desc(a, slot, s);
+        if (e == hipSuccess)
+            e = sst::launch_inverse_eq15(a, slot, (float)(1.0 / (pl->p.nfft * pl->g0)), s);
         if (e != hipSuccess)
             return hip_fail(e, "inverse (Eq. 15) launch");
         return SST_OK;
     }
-    if (whole) {
-        a.span_lo = 0;
-        a.span_len = pl->p.n_samples;
-    } else {
-        int64_t lo = frame0 * pl->p.hop - pl->M;
-        int64_t hi = (frame0 + nframes - 1) * pl->p.hop + pl->M;
-        if (lo < 0)
-            lo = 0;
-        if (hi > pl->p.n_samples - 1)
-            hi = pl->p.n_samples - 1;
-        if (hi < lo)
-            return SST_OK;
-        a.span_lo = lo;
-        a.span_len = hi - lo + 1;
-    }
-    if (sst::inv_lds_bytes(a) > 64 * 1024)
+    if (a.span_len <= 0)
+        return SST_OK;
+    sst::InvLaunch l = inv_launch(slot, 1, a.blk0, 2 * hw + 1, pl->n_lo + pl->n_hi);
+    if (sst::inv_lds_bytes(l) > 64 * 1024)
         return fail(SST_E_UNSUPPORTED, "inverse LDS tables exceed 64 KiB");
-    hipError_t e = sst::launch_inverse(a, s);
+    hipError_t e = sst::launch_put_inv_desc(a, slot, s);
+    if (e == hipSuccess)
+        e = sst::launch_inverse(l, a.blk_end - a.blk0, err != nullptr, s);
     if (e != hipSuccess)
         return hip_fail(e, "inverse launch");
     return SST_OK;
 }
 
 void sst_destroy(sst_plan_t pl) { delete pl; }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batched form.  Every channel keeps its own plan (tables, shapes); the batch
+// workspace holds each channel's plan workspace, then one descriptor array
+// per launch group (channels sharing N_f and the pass-1 tap-row count) for
+// the forward and threshold kernels and one InvDesc array for the inverse.
+// ---------------------------------------------------------------------------
+
+struct sst_batch_s {
+    struct Io {
+        const float *x = nullptr;
+        float *T = nullptr;
+        const int32_t *ridge = nullptr;
+        int n_comp = 0, hw = 0;
+        float *xhat = nullptr;
+        const float *xref = nullptr;
+        double *err = nullptr;
+    };
+    struct Group {
+        int nfft = 0, nz = 0;
+        std::vector<int> chans;     // ascending channel indices
+        int max_L = 0, max_n_src = 0, max_n_dst = 0;
+        size_t off_desc = 0;        // ChanDesc[chans.size()]
+        std::vector<sst::ChanDesc> desc;
+        int fwd_grid_cap = 0, max_grid_cap = 0;
+    };
+    std::vector<sst_plan_s *> plans;
+    std::vector<Io> io;
+    std::vector<Group> groups;
+    std::vector<size_t> off_chan;
+    size_t off_idesc = 0, ws_bytes = 0;
+    std::vector<sst::InvDesc> idesc;   // one per channel, channel order
+    unsigned char *ws = nullptr;
+    bool committed = false;
+    ~sst_batch_s()
+    {
+        for (sst_plan_s *p : plans)
+            delete p;
+    }
+};
+
+namespace {
+
+int nz_rows_host(int nfft, int L)
+{
+    const int q = nfft / 16;
+    const int rows = (L + q - 1) / q;
+    return rows <= 4 ? 4 : (rows <= 8 ? 8 : 16);
+}
+
+}  // namespace
+
+extern "C" {
+
+sst_status sst_batch_plan(const sst_params *params, int32_t n_channels, sst_batch_t *out)
+{
+    if (!out)
+        return fail(SST_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (!params || n_channels < 1)
+        return fail(SST_E_ARG, "params NULL or n_channels < 1");
+    sst_batch_s *b = new (std::nothrow) sst_batch_s();
+    if (!b)
+        return fail(SST_E_NOMEM, "batch allocation failed");
+    try {
+        b->plans.assign((size_t)n_channels, nullptr);
+        b->io.assign((size_t)n_channels, sst_batch_s::Io{});
+        b->off_chan.assign((size_t)n_channels, 0);
+    } catch (...) {
+        delete b;
+        return fail(SST_E_NOMEM, "batch allocation failed");
+    }
+    size_t off = 0;
+    for (int c = 0; c < n_channels; ++c) {
+        sst_status st = sst_plan(&params[c], &b->plans[(size_t)c]);
+        if (st != SST_OK) {
+            g_err = "channel " + std::to_string(c) + ": " + g_err;
+            delete b;
+            return st;
+        }
+        b->off_chan[(size_t)c] = off;
+        off = align_up(off + b->plans[(size_t)c]->ws_bytes);
+    }
+    for (int c = 0; c < n_channels; ++c) {
+        const sst_plan_s *pl = b->plans[(size_t)c];
+        const int nz = nz_rows_host(pl->p.nfft, pl->p.win_len);
+        sst_batch_s::Group *grp = nullptr;
+        for (auto &gr : b->groups)
+            if (gr.nfft == pl->p.nfft && gr.nz == nz)
+                grp = &gr;
+        if (!grp) {
+            b->groups.emplace_back();
+            grp = &b->groups.back();
+            grp->nfft = pl->p.nfft;
+            grp->nz = nz;
+        }
+        grp->chans.push_back(c);
+        grp->max_L = std::max(grp->max_L, pl->p.win_len);
+        grp->max_n_src = std::max(grp->max_n_src, pl->n_src);
+        grp->max_n_dst = std::max(grp->max_n_dst, pl->n_dst);
+    }
+    for (auto &gr : b->groups) {
+        gr.off_desc = off;
+        off = align_up(off + sizeof(sst::ChanDesc) * gr.chans.size());
+    }
+    b->off_idesc = off;
+    off = align_up(off + sizeof(sst::InvDesc) * (size_t)n_channels);
+    b->ws_bytes = off;
+    *out = b;
+    return SST_OK;
+}
+
+sst_status sst_batch_query(sst_batch_t b, int32_t c, sst_shape *out)
+{
+    if (!b || !out)
+        return fail(SST_E_ARG, "batch or out is NULL");
+    if (c < 0 || c >= (int32_t)b->plans.size())
+        return fail(SST_E_ARG, "channel out of range");
+    sst_status st = sst_plan_query(b->plans[(size_t)c], out);
+    out->workspace_bytes = b->ws_bytes;
+    return st;
+}
+
+sst_status sst_batch_bind(sst_batch_t b, void *workspace, size_t bytes, void *stream)
+{
+    if (!b)
+        return fail(SST_E_ARG, "batch is NULL");
+    if (!workspace || bytes < b->ws_bytes || (reinterpret_cast<uintptr_t>(workspace) % kAlign))
+        return fail(SST_E_WORKSPACE, "workspace NULL, not 256-byte aligned, or smaller than "
+                                     "sst_shape.workspace_bytes");
+    unsigned char *ws = static_cast<unsigned char *>(workspace);
+    for (size_t c = 0; c < b->plans.size(); ++c) {
+        sst_plan_s *pl = b->plans[c];
+        sst_status st = sst_plan_bind(pl, ws + b->off_chan[c], pl->ws_bytes, stream);
+        if (st != SST_OK)
+            return st;
+    }
+    for (auto &gr : b->groups) {
+        const sst_plan_s *p0 = b->plans[(size_t)gr.chans[0]];
+        gr.fwd_grid_cap = p0->fwd_grid_cap;
+        gr.max_grid_cap = p0->max_grid_cap;
+        for (int c : gr.chans) {
+            gr.fwd_grid_cap = std::max(gr.fwd_grid_cap, b->plans[(size_t)c]->fwd_grid_cap);
+            gr.max_grid_cap = std::max(gr.max_grid_cap, b->plans[(size_t)c]->max_grid_cap);
+        }
+    }
+    b->ws = ws;
+    b->committed = false;
+    return SST_OK;
+}
+
+sst_status sst_batch_set_io(sst_batch_t b, int32_t c, const float *x, float *T,
+                            const int32_t *ridge, int32_t n_comp, int32_t hw, float *xhat,
+                            const float *xref, double *err)
+{
+    if (!b)
+        return fail(SST_E_ARG, "batch is NULL");
+    if (c < 0 || c >= (int32_t)b->plans.size())
+        return fail(SST_E_ARG, "channel out of range");
+    if (ridge && (n_comp < 1 || n_comp > 65535 || hw < 0 || hw > 512 || !xhat))
+        return fail(SST_E_ARG, "inverse buffers need 1 <= n_comp <= 65535, 0 <= hw <= 512 and xhat");
+    if (err && !xref)
+        return fail(SST_E_ARG, "err needs xref");
+    sst_batch_s::Io &o = b->io[(size_t)c];
+    o.x = x;
+    o.T = T;
+    o.ridge = ridge;
+    o.n_comp = ridge ? n_comp : 0;
+    o.hw = hw;
+    o.xhat = xhat;
+    o.xref = xref;
+    o.err = err;
+    b->committed = false;
+    return SST_OK;
+}
+
+sst_status sst_batch_commit(sst_batch_t b, void *stream)
+{
+    if (!b)
+        return fail(SST_E_ARG, "batch is NULL");
+    if (!b->ws)
+        return fail(SST_E_STATE, "batch is not bound to a workspace");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    for (auto &gr : b->groups) {
+        gr.desc.assign(gr.chans.size(), sst::ChanDesc{});
+        int64_t items = 0, mitems = 0;
+        for (size_t i = 0; i < gr.chans.size(); ++i) {
+            const int c = gr.chans[i];
+            const sst_plan_s *pl = b->plans[(size_t)c];
+            const sst_batch_s::Io &o = b->io[(size_t)c];
+            const int F = sst::fwd_frames_per_iter(pl->p.nfft);
+            sst::ChanDesc d = chan_desc(pl, o.x, 0, pl->n_frames, o.T, nullptr,
+                                        reinterpret_cast<sst::Ctrl *>(pl->ws));
+            d.item0 = items;
+            items += (pl->n_frames + F - 1) / F;
+            d.item_end = items;
+            d.mitem0 = mitems;
+            if (pl->p.thr_mode == SST_THR_REL_MAX)
+                mitems += ((pl->n_frames + 1) / 2 + F - 1) / F;
+            d.mitem_end = mitems;
+            gr.desc[i] = d;
+        }
+        hipError_t e = hipMemcpyAsync(b->ws + gr.off_desc, gr.desc.data(),
+                                      sizeof(sst::ChanDesc) * gr.desc.size(),
+                                      hipMemcpyHostToDevice, s);
+        if (e != hipSuccess)
+            return hip_fail(e, "hipMemcpyAsync(descriptors)");
+    }
+    b->idesc.assign(b->plans.size(), sst::InvDesc{});
+    int64_t blk = 0;
+    for (size_t c = 0; c < b->plans.size(); ++c) {
+        const sst_plan_s *pl = b->plans[c];
+        const sst_batch_s::Io &o = b->io[c];
+        sst::InvDesc a = inv_desc(pl, o.T, 0, pl->n_frames, o.ridge, o.ridge ? o.n_comp : 0, o.hw,
+                                  o.xhat, o.xref, o.err, false);
+        a.blk0 = blk;
+        blk += o.ridge ? (int64_t)o.n_comp * a.tiles : 0;
+        a.blk_end = blk;
+        b->idesc[c] = a;
+    }
+    hipError_t e = hipMemcpyAsync(b->ws + b->off_idesc, b->idesc.data(),
+                                  sizeof(sst::InvDesc) * b->idesc.size(), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess)
+        return hip_fail(e, "hipMemcpyAsync(inverse descriptors)");
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        return hip_fail(e, "hipStreamSynchronize");
+    b->committed = true;
+    return SST_OK;
+}
+
+sst_status sst_batch_forward(sst_batch_t b, int32_t c_begin, int32_t c_end, uint32_t flags,
+                             void *stream)
+{
+    if (!b)
+        return fail(SST_E_ARG, "batch is NULL");
+    if (!b->ws || !b->committed)
+        return fail(SST_E_STATE, "batch not bound or buffers not committed");
+    if (c_begin < 0 || c_end > (int32_t)b->plans.size() || c_begin >= c_end)
+        return fail(SST_E_ARG, "channel range empty or outside [0, n_channels)");
+    if (flags & ~SST_FWD_REUSE_GAMMA)
+        return fail(SST_E_ARG, "unknown forward flags");
+    for (int c = c_begin; c < c_end; ++c)
+        if (!b->io[(size_t)c].x || !b->io[(size_t)c].T)
+            return fail(SST_E_ARG, "channel " + std::to_string(c) + " has no x or T");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    for (const auto &gr : b->groups) {
+        size_t i0 = 0, i1 = 0;
+        while (i0 < gr.chans.size() && gr.chans[i0] < c_begin)
+            ++i0;
+        i1 = i0;
+        while (i1 < gr.chans.size() && gr.chans[i1] < c_end)
+            ++i1;
+        if (i1 == i0)
+            continue;
+        const sst_plan_s *p0 = b->plans[(size_t)gr.chans[i0]];
+        sst::GroupLaunch g{};
+        g.ch = reinterpret_cast<const sst::ChanDesc *>(b->ws + gr.off_desc) + i0;
+        g.n_ch = (int)(i1 - i0);
+        g.twid = reinterpret_cast<const float2 *>(p0->ws + p0->off_twid);
+        if (!(flags & SST_FWD_REUSE_GAMMA)) {
+            g.item_begin = gr.desc[i0].mitem0;
+            g.item_stop = gr.desc[i1 - 1].mitem_end;
+            const int64_t items = g.item_stop - g.item_begin;
+            const int grid = (int)(items < gr.max_grid_cap ? items : gr.max_grid_cap);
+            hipError_t e = sst::launch_threshold(gr.nfft, gr.max_L, g, grid, s);
+            if (e != hipSuccess)
+                return hip_fail(e, "batched threshold launch");
+        }
+        g.item_begin = gr.desc[i0].item0;
+        g.item_stop = gr.desc[i1 - 1].item_end;
+        const int64_t items = g.item_stop - g.item_begin;
+        const int grid = (int)(items < gr.fwd_grid_cap ? items : gr.fwd_grid_cap);
+        if (grid > 0) {
+            hipError_t e = sst::launch_forward(gr.nfft, gr.max_L, gr.max_n_src, gr.max_n_dst,
+                                               false, g, grid, s);
+            if (e != hipSuccess)
+                return hip_fail(e, "batched forward launch");
+        }
+    }
+    return SST_OK;
+}
+
+sst_status sst_batch_inverse(sst_batch_t b, int32_t c_begin, int32_t c_end, void *stream)
+{
+    if (!b)
+        return fail(SST_E_ARG, "batch is NULL");
+    if (!b->ws || !b->committed)
+        return fail(SST_E_STATE, "batch not bound or buffers not committed");
+    if (c_begin < 0 || c_end > (int32_t)b->plans.size() || c_begin >= c_end)
+        return fail(SST_E_ARG, "channel range empty or outside [0, n_channels)");
+    int max_w = 1, max_tab = 1;
+    bool any_err = false;
+    for (int c = c_begin; c < c_end; ++c) {
+        const sst_batch_s::Io &o = b->io[(size_t)c];
+        const sst_plan_s *pl = b->plans[(size_t)c];
+        if (!o.T || !o.ridge || !o.xhat)
+            return fail(SST_E_ARG, "channel " + std::to_string(c) + " has no T, ridge or xhat");
+        if (pl->G > 65536)
+            return fail(SST_E_UNSUPPORTED, "inverse needs subdiv * nfft <= 65536");
+        max_w = std::max(max_w, 2 * o.hw + 1);
+        max_tab = std::max(max_tab, pl->n_lo + pl->n_hi);
+        any_err = any_err || o.err;
+    }
+    const sst::InvDesc *dev = reinterpret_cast<const sst::InvDesc *>(b->ws + b->off_idesc);
+    sst::InvLaunch l = inv_launch(dev + c_begin, c_end - c_begin, b->idesc[(size_t)c_begin].blk0,
+                                  max_w, max_tab);
+    if (sst::inv_lds_bytes(l) > 64 * 1024)
+        return fail(SST_E_UNSUPPORTED, "inverse LDS tables exceed 64 KiB");
+    const int64_t blocks = b->idesc[(size_t)c_end - 1].blk_end - l.blk_begin;
+    hipError_t e = sst::launch_inverse(l, blocks, any_err, reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess)
+        return hip_fail(e, "batched inverse launch");
+    return SST_OK;
+}
+
+void sst_batch_destroy(sst_batch_t b) { delete b; }
+
 
 const char *sst_status_string(sst_status s)
 {

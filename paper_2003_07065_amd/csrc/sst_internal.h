@@ -10,48 +10,54 @@ namespace sst {
 
 // Device-side control block at the start of the workspace.
 struct Ctrl {
-    float gamma;    // threshold |S| > gamma
-    float gamma2;   // gamma^2 (the kernels compare |A|^2 > gamma^2)
-    float maxabs2;  // max |S|^2 found by the threshold pre-pass
-    float pad[61];
+    float gamma;        // threshold |S| > gamma
+    float gamma2;       // gamma^2 (the kernels compare |A|^2 > gamma^2)
+    float maxabs2;      // max |S|^2 found by the threshold pre-pass
+    unsigned maxbits;   // running max |S|^2 as float bits (atomicMax on non-negative floats)
+    float pad[60];
 };
 static_assert(sizeof(Ctrl) == 256, "control block is one 256-byte slot");
 
-// Arguments of the fused forward kernel (framing, FFT pair, IF, reassignment).
-struct FwdArgs {
-    const float *x;         // [n]
+// Per-channel descriptor read (through the scalar cache) by the threshold
+// and forward kernels.  A launch processes a contiguous list of descriptors
+// whose channels share N_f; single-channel calls use a list of one.
+struct ChanDesc {
+    const float *x;         // [n] signal
     int64_t n;              // signal length
-    int64_t frame0;         // first frame of the call
-    int64_t nframes;        // frames in the call
+    int64_t n_frames;       // frames of the whole signal: ceil(n / hop)
+    int64_t frame0;         // first frame of the forward call
+    int64_t nframes;        // frames of the forward call
+    int64_t item0;          // forward items (F frames each) of the launch list before this channel
+    int64_t item_end;       // item0 + ceil(nframes / F)
+    int64_t mitem0;         // threshold items (F frame pairs each) before this channel
+    int64_t mitem_end;      // mitem0 + ceil(ceil(n_frames / 2) / F) (relative threshold), else mitem0
     const float2 *win;      // [L]: (g[j], s * g'[j]), j = -M..M
-    const float2 *cphase;   // [n_src]: exp(+i 2 pi ((k M) mod N_f) / N_f)
-    const float2 *twid;     // [N_f]: exp(-i 2 pi r / N_f)
-    const Ctrl *ctrl;       // gamma2
+    Ctrl *ctrl;             // threshold of this channel
     float2 *T;              // [nframes][n_dst]
     float2 *S;              // optional [nframes][n_src]
     float2 *Sd;             // optional [nframes][n_src]
     int32_t *idx;           // optional [nframes][n_src]
     double *colstats;       // optional [nframes][3]
-    int L, M, hop, k1, n_src, n_dst, z;
-    float2 cph_step;        // exp(+i 2 pi ((NT M) mod N_f) / N_f), NT = threads per workgroup
+    int L, M, hop, k1, n_src, n_dst, z, thr_mode;
+    float thr;              // gamma (absolute) or rho (relative)
     float inv_s;            // 1/s: S' = B / s
     float cdelta;           // N_f / (2 pi s): delta (bins) = cdelta Im(B conj A) / |A|^2
+    float pad_;
 };
 
-// Arguments of the threshold pre-pass (max |S|^2 over every frame and in-band bin).
-struct MaxArgs {
-    const float *x;
-    int64_t n;
-    int64_t n_frames;       // all frames of the signal
-    const float2 *win;
-    const float2 *twid;
-    float *partial;         // [gridDim.x]
-    int L, M, hop, k1, n_src;
+// One launch of the threshold or forward kernel over descriptors ch[0 .. n_ch).
+struct GroupLaunch {
+    const ChanDesc *ch;     // device array
+    int n_ch;
+    int64_t item_begin;     // first item: ch[0].item0 (forward) or ch[0].mitem0 (threshold)
+    int64_t item_stop;      // ch[n_ch-1].item_end or .mitem_end
+    const float2 *twid;     // [N_f]: exp(-i 2 pi r / N_f), shared by the launch
 };
 
-// Arguments of the direct inverse kernel.
-struct InvArgs {
-    const float2 *T;        // [nframes][n_dst] rows of the chunk
+// Per-channel descriptor of the direct inverse (one call's frames of one
+// channel, every component).  Launches cover a contiguous list of them.
+struct InvDesc {
+    const float2 *T;        // [nframes][n_dst] rows of the call
     const int32_t *ridge;   // [n_comp][nframes]
     float *xhat;            // [n_comp][n]
     const float *xref;      // optional [n_comp][n]
@@ -62,8 +68,11 @@ struct InvArgs {
     int64_t n;              // signal length
     int64_t n_frames;       // all frames of the signal
     int64_t frame0, nframes;
-    int64_t span_lo;        // first output sample the chunk reaches
-    int64_t span_len;       // number of output samples the chunk reaches
+    int64_t span_lo;        // first output sample the call reaches
+    int64_t span_len;       // number of output samples the call reaches
+    int64_t blk0;           // workgroups of the launch list before this channel
+    int64_t blk_end;        // blk0 + n_comp * tiles
+    int64_t tiles;          // ceil(span_len / 256)
     int L, M, hop, nfft, k1, z, n_dst, hw, n_comp;
     int G;                  // z * N_f (phase grid of the inverse)
     int lo_bits;            // split of the phase-table index
@@ -71,7 +80,17 @@ struct InvArgs {
     float inv_G;            // 1/G
     float inv_nfft;
     int accumulate;         // add into xhat
-    int fb;                 // frames staged per LDS block
+    int pad_;
+};
+
+// One inverse launch over descriptors ch[0 .. n_ch).
+struct InvLaunch {
+    const InvDesc *ch;      // device array
+    int n_ch;
+    int fb;                 // frames staged per LDS block (same for the launch)
+    int64_t blk_begin;      // ch[0].blk0
+    int max_tab;            // LDS float2 entries of the largest phase tables in the list
+    int max_w;              // largest 2 hw + 1 in the list
 };
 
 // Arguments of the ridge kernel.
@@ -85,22 +104,32 @@ struct RidgeArgs {
 };
 
 // Launchers (sst_kernels.hip).  Each returns the hipError_t of its launch.
-hipError_t launch_threshold(int nfft, const MaxArgs &a, Ctrl *ctrl, int mode, float thr,
-                            int grid, hipStream_t s);
-hipError_t launch_forward(int nfft, const FwdArgs &a, int grid, hipStream_t s);
-hipError_t launch_inverse(const InvArgs &a, hipStream_t s);
-hipError_t launch_inverse_eq15(const InvArgs &a, float inv_nfft_g0, hipStream_t s);
+// Threshold: clears maxbits of the launch's channels, runs the pre-pass when
+// `rel_items` > 0 and sets gamma of every channel of the list.
+hipError_t launch_threshold(int nfft, int L, const GroupLaunch &g, int grid, hipStream_t s);
+// Forward: `debug` selects the variant that writes S, S', idx and colstats;
+// max_n_src / max_n_dst / max_L bound the launch's channels.
+hipError_t launch_forward(int nfft, int max_L, int max_n_src, int max_n_dst, bool debug,
+                          const GroupLaunch &g, int grid, hipStream_t s);
+// Copy one descriptor into device memory (a kernel, so it can be captured).
+hipError_t launch_put_desc(const ChanDesc &d, ChanDesc *dst, hipStream_t s);
+// Inverse of the launch list (blocks = ch[n_ch-1].blk_end - blk_begin).
+// Clears err first when `clear_err`.
+hipError_t launch_inverse(const InvLaunch &l, int64_t blocks, bool clear_err, hipStream_t s);
+// Eq. 15 for one descriptor (host copy `a`, device copy `dev`).
+hipError_t launch_inverse_eq15(const InvDesc &a, const InvDesc *dev, float inv_nfft_g0,
+                               hipStream_t s);
+hipError_t launch_put_inv_desc(const InvDesc &d, InvDesc *dst, hipStream_t s);
+size_t inv_lds_bytes(const InvLaunch &l);
 hipError_t launch_ridge(const RidgeArgs &a, hipStream_t s);
 
 // Kernel geometry, shared so the host can size grids and workspaces.
 int fwd_frames_per_iter(int nfft);   // F
 int fwd_threads(int nfft);           // threads per workgroup
 int fwd_lds_elems(int nfft);         // float2 capacity of the LDS buffer
-int fwd_occupancy(int nfft, int L, int n_src);  // resident workgroups per CU (forward)
+int fwd_occupancy(int nfft, int L);  // resident workgroups per CU (forward)
 int max_occupancy(int nfft, int L);  // resident workgroups per CU (threshold pre-pass)
-size_t inv_lds_bytes(const InvArgs &a);
-size_t fwd_dyn_lds(int nfft, int n_src);      // dynamic LDS of the forward kernel
 int fwd_rounds(int nfft, int n_src);          // coefficient rounds per thread: 3, 5 or 9
-size_t fwd_lds_bytes(int nfft, int n_src);    // static + dynamic LDS of the forward kernel
+size_t fwd_lds_bytes(int nfft);               // LDS of the forward kernel
 
 }  // namespace sst

@@ -184,6 +184,10 @@ __device__ __forceinline__ void dftR<8>(v2 *a) { dft8(a); }
 template <>
 __device__ __forceinline__ void dftR<16>(v2 *a) { dft16(a); }
 
+// Pointer to memory the kernels only read and index uniformly (descriptors,
+// control blocks): loads through it use the scalar unit.
+#define CA __attribute__((address_space(4)))
+
 // ---------------------------------------------------------------------------
 // Geometry per DFT size.
 // ---------------------------------------------------------------------------
@@ -391,7 +395,7 @@ __device__ __forceinline__ void split_flat(int e, int n_src, float inv_nsrc, int
 //   IF phase          every thread evaluates its in-band coefficients
 //                     (Eqs. 12-13, 27-29) and keeps (destination, S) in
 //                     registers; per-frame sums sum_k (|Re S| + |Im S|) are
-//                     reduced in LDS;
+//                     reduced per wave, then summed in a fixed order;
 //   scatter phase     the LDS buffer, no longer needed by the FFT, becomes
 //                     the destination histogram: zeroed, then every kept
 //                     coefficient is added to its bin;
@@ -434,9 +438,78 @@ __device__ __forceinline__ float fixed_scale(float B)
     return ldexpf(1.0f, K);
 }
 
-template <int NF, int NZ, int R, bool DEBUG, bool CHUNKED>
+// Channel of item `it` for a launch whose items ascend with the channel
+// index: advance c while `it` lies past channel c's items (end[] cumulative).
+template <bool THRESHOLD>
+__device__ __forceinline__ int chan_of(const CA ChanDesc *ch, int n_ch, int c, int64_t it)
+{
+    while (c < n_ch - 1 && it >= (THRESHOLD ? ch[c].mitem_end : ch[c].item_end))
+        ++c;
+    return c;
+}
+
+// Per-channel values a workgroup keeps in scalar registers while it works
+// on that channel's items; reloaded only when the channel changes.
+struct Chan {
+    const float *x;
+    const float2 *win;
+    float2 *T;
+    float2 *S;
+    float2 *Sd;
+    int32_t *idx;
+    double *colstats;
+    Ctrl *ctrl;
+    int64_t n, n_frames, frame0, nframes, item0, item_end;
+    int L, M, hop, k1, n_src, n_dst, z;
+    float gamma2, inv_s, cdelta, inv_nsrc, inv_ndst;
+};
+
+template <bool THRESHOLD>
+__device__ __forceinline__ Chan load_chan(const CA ChanDesc *ch, int c)
+{
+    const CA ChanDesc &d = ch[c];
+    Chan r;
+    r.x = d.x;
+    r.win = d.win;
+    r.T = d.T;
+    r.S = d.S;
+    r.Sd = d.Sd;
+    r.idx = d.idx;
+    r.colstats = d.colstats;
+    r.ctrl = d.ctrl;
+    r.n = d.n;
+    r.n_frames = d.n_frames;
+    r.frame0 = d.frame0;
+    r.nframes = d.nframes;
+    r.item0 = THRESHOLD ? d.mitem0 : d.item0;
+    r.item_end = THRESHOLD ? d.mitem_end : d.item_end;
+    r.L = d.L;
+    r.M = d.M;
+    r.hop = d.hop;
+    r.k1 = d.k1;
+    r.n_src = d.n_src;
+    r.n_dst = d.n_dst;
+    r.z = d.z;
+    r.gamma2 = THRESHOLD ? 0.f : ((const CA Ctrl *)d.ctrl)->gamma2;
+    r.inv_s = d.inv_s;
+    r.cdelta = d.cdelta;
+    r.inv_nsrc = 1.0f / (float)d.n_src;
+    r.inv_ndst = 1.0f / (float)d.n_dst;
+    return r;
+}
+
+// exp(+i 2 pi t / N_f) for 0 <= t < N_f from two LDS copies of the twiddle
+// table (lo[r] = W^r, r < 64; hi[h] = W^(64 h)): the conjugate of
+// W^t = hi[t / 64] lo[t mod 64].
+__device__ __forceinline__ v2 cphase_of(const v2 *lo, const v2 *hi, int t)
+{
+    return conjv(cmul(hi[t >> 6], lo[t & 63]));
+}
+
+template <int NF, int NZ, int R, bool DEBUG, bool CHUNKED, bool MULTI>
 // Waves per SIMD: 4 for N_f = 8192 (two 8-wave workgroups fill a CU's LDS), 3 otherwise.
-__global__ __launch_bounds__(Geo<NF>::NT, DEBUG ? 2 : (NF == 8192 ? 4 : 3)) void fwd_kernel(FwdArgs a)
+// MULTI: the launch may hold several channels (else exactly one).
+__global__ __launch_bounds__(Geo<NF>::NT, DEBUG ? 2 : (NF == 8192 ? 4 : 3)) void fwd_kernel(GroupLaunch g)
 {
     using G = Geo<NF>;
     constexpr int F = G::F, NT = G::NT, Q = NF / 16;
@@ -444,77 +517,87 @@ __global__ __launch_bounds__(Geo<NF>::NT, DEBUG ? 2 : (NF == 8192 ? 4 : 3)) void
     constexpr int NST = HB / NT;      // store instructions per thread and chunk
     static_assert(HB % NT == 0, "histogram is a whole number of store rounds");
     constexpr int SEGF = 24;          // key = (frame << SEGF) | flat destination
+    constexpr int NHI = NF / 64;
     __shared__ v2 lds[G::LDS];
-    __shared__ float bsum[F];
+    __shared__ float bpart[NT / 64][F];   // per-wave partial bounds, summed in fixed order
     __shared__ double colacc[DEBUG ? 3 * F : 1];
+    __shared__ v2 twl[Twiddles<NF>::TW];
+    __shared__ v2 clo[64], chi[NHI];   // centre-phase tables (Eq. 9)
     int *hq = reinterpret_cast<int *>(lds);   // bin b: hq[2b] = re, hq[2b + 1] = im
 
-    __shared__ v2 twl[Twiddles<NF>::TW];
+    const v2 *__restrict__ twid = reinterpret_cast<const v2 *>(g.twid);
     Twiddles<NF> tw;
-    tw.load(twl, reinterpret_cast<const v2 *>(a.twid));
-
-    const v2 *__restrict__ cph = reinterpret_cast<const v2 *>(a.cphase);
-    const float *__restrict__ x = a.x;
-    const float gamma2 = a.ctrl->gamma2;
-    const float inv_nsrc = 1.0f / (float)a.n_src;
-    const float inv_ndst = 1.0f / (float)a.n_dst;
-    const int64_t n_iter = (a.nframes + F - 1) / F;
-
-    // Centre phase of Eq. 9 for bin k1 + ik.  With one frame per iteration a
-    // thread visits ik = tid + i NT, whose phases differ by the constant
-    // factor exp(i 2 pi ((NT M) mod N_f) / N_f), so they are generated by
-    // rotation; with several frames per iteration the table is staged in LDS.
-    extern __shared__ __align__(16) unsigned char dyn_lds[];
-    v2 *cphl = reinterpret_cast<v2 *>(dyn_lds);
-    v2 ph0 = mk(1.f, 0.f);
-    const v2 ph_step = mk(a.cph_step.x, a.cph_step.y);
-    if constexpr (F == 1) {
-        if (threadIdx.x < a.n_src)
-            ph0 = cph[(unsigned)threadIdx.x];
-    } else {
-        for (int e = threadIdx.x; e < a.n_src; e += NT)
-            cphl[e] = cph[(unsigned)e];
+    tw.load(twl, twid);
+    for (int e = threadIdx.x; e < 64 + NHI; e += NT) {
+        if (e < 64)
+            clo[e] = twid[(unsigned)e];
+        else
+            chi[e - 64] = twid[(unsigned)(e - 64) * 64u];
     }
+    const CA ChanDesc *ch = (const CA ChanDesc *)g.ch;
 
     // Pass-1 role of this thread: frame f1 of the iteration, taps jj + r Q.
     const int f1 = threadIdx.x / Q, jj = threadIdx.x % Q;
     v2 w[NZ];   // (g, s g') of the thread's taps; zero beyond the window
-#pragma unroll
-    for (int r = 0; r < NZ; ++r) {
-        const int n = jj + r * Q;
-        w[r] = n < a.L ? reinterpret_cast<const v2 *>(a.win)[(unsigned)n] : mk(0.f, 0.f);
-    }
     // Eq. 8: frame m covers samples mH - M .. mH + M.  Signals are limited to
     // 2^30 samples so sample indices fit 32 bits.
     float xv[NZ];
     int okb = 0;
-    auto fetch = [&](int64_t it) {
-        const int64_t m = it * F + f1;   // frame of this thread, relative to frame0
-        const bool fv = (it < n_iter) & (m < a.nframes);
-        const int cm = (int)((a.frame0 + (fv ? m : 0)) * (int64_t)a.hop - a.M) + jj;
+    // Samples of item `it` of channel d; the taps too when the channel changes
+    // (w is free then: it is read only by pass 1, which precedes the fetch).
+    auto fetch = [&](int64_t it, const Chan &d, bool new_chan) {
+        const bool iv = it < g.item_stop;
+        const int64_t m = (iv ? it - d.item0 : 0) * F + f1;   // frame relative to d.frame0
+        const bool fv = iv & (m < d.nframes);
+        const int cm = (int)((d.frame0 + (fv ? m : 0)) * (int64_t)d.hop - d.M) + jj;
+        const float *__restrict__ x = d.x;
+        const unsigned n = (unsigned)d.n;
         okb = 0;
 #pragma unroll
         for (int r = 0; r < NZ; ++r) {
             const int s = cm + r * Q;
-            const bool ok = fv & ((unsigned)s < (unsigned)a.n);
+            const bool ok = fv & ((unsigned)s < n);
             xv[r] = x[ok ? (unsigned)s : 0u];
             okb |= (int)ok << r;
+        }
+        if (new_chan) {
+            const v2 *__restrict__ win = reinterpret_cast<const v2 *>(d.win);
+#pragma unroll
+            for (int r = 0; r < NZ; ++r) {
+                const int tap = jj + r * Q;
+                w[r] = tap < d.L ? win[(unsigned)tap] : mk(0.f, 0.f);
+            }
         }
     };
 
     if (DEBUG && threadIdx.x < 3 * F)
         colacc[threadIdx.x] = 0.0;
-    fetch(blockIdx.x);
+    int64_t it = g.item_begin + blockIdx.x;
+    int c = chan_of<false>(ch, g.n_ch, 0, it);
+    Chan a = load_chan<false>(ch, c);
+    fetch(it, a, true);
     // Wait here for every load issued so far (tables, first samples), so that
     // inside the loop the samples prefetched by the previous iteration are the
     // only loads the first use has to wait for (vmcnt(0), expcnt and lgkmcnt
     // left unconstrained).
     __builtin_amdgcn_s_waitcnt(0x0f70);
 
-    for (int64_t it = blockIdx.x; it < n_iter; it += gridDim.x) {
-        const int64_t m0 = it * F;   // first frame of the iteration, relative to frame0
+    // centre phase of bin k1 + tid and the rotation step (F == 1), per channel
+    v2 ph0 = mk(1.f, 0.f), ph_step = mk(1.f, 0.f);
+    bool new_chan = true;
+    for (; it < g.item_stop; it += gridDim.x) {
+        const int64_t m0 = (it - a.item0) * F;   // first frame of the item, relative to frame0
         const int nvalid = (int)((a.nframes - m0) < F ? (a.nframes - m0) : F);
-        __syncthreads();   // the previous iteration's store phase is done with the buffer
+        const float gamma2 = a.gamma2;
+        const float inv_nsrc = a.inv_nsrc;
+        const float inv_ndst = a.inv_ndst;
+        // the previous iteration's store phase is done with the buffer (and,
+        // on the first iteration, the staged tables are complete)
+        __syncthreads();
+        if (F == 1 && (MULTI ? new_chan : it == g.item_begin + blockIdx.x)) {
+            ph0 = cphase_of(clo, chi, ((a.k1 + (int)threadIdx.x) * a.M) & (NF - 1));
+            ph_step = cphase_of(clo, chi, (NT * a.M) & (NF - 1));
+        }
 
         {   // pass 1 from the prefetched samples
             v2 v[16];
@@ -532,9 +615,15 @@ __global__ __launch_bounds__(Geo<NF>::NT, DEBUG ? 2 : (NF == 8192 ? 4 : 3)) void
             for (int r = 0; r < 16; ++r)
                 lds[pad16(base + r)] = v[r];
         }
-        if (threadIdx.x < F)
-            bsum[threadIdx.x] = 0.f;
-        fetch(it + gridDim.x);   // next iteration's samples, issued before this one's stores
+        // next iteration's samples, issued before this one's stores
+        const int64_t itn = it + gridDim.x;
+        Chan an = a;
+        const bool chg = MULTI && itn < g.item_stop && itn >= a.item_end;
+        if (chg) {
+            c = chan_of<false>(ch, g.n_ch, c, itn);
+            an = load_chan<false>(ch, c);
+        }
+        fetch(itn, an, chg);
         __syncthreads();
         tw.passes(lds, twl);
 
@@ -553,6 +642,10 @@ __global__ __launch_bounds__(Geo<NF>::NT, DEBUG ? 2 : (NF == 8192 ? 4 : 3)) void
 #pragma unroll
         for (int f = 0; f < F; ++f)
             part[f] = 0.f;
+        // Centre phase of Eq. 9, exp(i 2 pi ((k M) mod N_f) / N_f).  With one
+        // frame per iteration a thread visits k = k1 + tid + i NT, whose phases
+        // differ by the constant factor for (NT M) mod N_f, so they are
+        // generated by rotation; otherwise each is looked up.
         v2 ph_cur = ph0;
 #pragma unroll
         for (int i = 0; i < R; ++i) {
@@ -571,7 +664,7 @@ __global__ __launch_bounds__(Geo<NF>::NT, DEBUG ? 2 : (NF == 8192 ? 4 : 3)) void
                 ph_cur = cmul(ph_cur, ph_step);
             } else {
                 split_flat(e < E ? e : 0, a.n_src, inv_nsrc, f, ik);
-                phk = cphl[ik];
+                phk = cphase_of(clo, chi, ((a.k1 + ik) * a.M) & (NF - 1));
             }
             if (e >= E)
                 continue;
@@ -618,16 +711,23 @@ __global__ __launch_bounds__(Geo<NF>::NT, DEBUG ? 2 : (NF == 8192 ? 4 : 3)) void
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1)
                 p += __shfl_xor(p, o, 64);
-            if ((threadIdx.x & 63) == 0 && p > 0.f)
-                atomicAdd(&bsum[ff], p);
+            if ((threadIdx.x & 63) == 0)
+                bpart[threadIdx.x >> 6][ff] = p;
         }
         __syncthreads();   // FFT buffer free, frame bounds complete
 
         v2 *__restrict__ trow = reinterpret_cast<v2 *>(a.T) + m0 * (int64_t)a.n_dst;
+        // the bound is summed in a fixed order so the scale, hence T, is
+        // reproducible bit for bit
         float scf[F];
 #pragma unroll
-        for (int ff = 0; ff < F; ++ff)
-            scf[ff] = fixed_scale(bsum[ff] * 1.001f);
+        for (int ff = 0; ff < F; ++ff) {
+            float B = 0.f;
+#pragma unroll
+            for (int wv = 0; wv < NT / 64; ++wv)
+                B += bpart[wv][ff];
+            scf[ff] = fixed_scale(B * 1.001f);
+        }
         for (int c0 = 0; c0 < (CHUNKED ? EH : 1); c0 += HB) {
             const int cn = CHUNKED ? ((EH - c0) < HB ? (EH - c0) : HB) : EH;
 #pragma unroll
@@ -708,6 +808,8 @@ __global__ __launch_bounds__(Geo<NF>::NT, DEBUG ? 2 : (NF == 8192 ? 4 : 3)) void
                     colacc[threadIdx.x] = 0.0;
             }
         }
+        a = an;
+        new_chan = chg;
     }
 }
 
@@ -723,57 +825,82 @@ __device__ __forceinline__ float wave_max(float v)
     return v;
 }
 
+// Block-wide max of v, then one atomicMax of its float bits into *dst
+// (non-negative floats order like their bit patterns).  Every thread calls it.
+template <int NT>
+__device__ __forceinline__ void block_max_flush(float v, float *red, unsigned *dst)
+{
+    v = wave_max(v);
+    if ((threadIdx.x & 63) == 0)
+        red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float b = red[0];
+        for (int w = 1; w < NT / 64; ++w)
+            b = fmaxf(b, red[w]);
+        atomicMax(dst, __float_as_uint(b));
+    }
+    __syncthreads();
+}
+
 template <int NF, int NZ>
-__global__ __launch_bounds__(Geo<NF>::NT, NF == 8192 ? 4 : 3) void max_kernel(MaxArgs a)
+__global__ __launch_bounds__(Geo<NF>::NT, NF == 8192 ? 4 : 3) void max_kernel(GroupLaunch g)
 {
     using G = Geo<NF>;
     constexpr int F = G::F, NT = G::NT, Q = NF / 16;
     __shared__ v2 lds[G::LDS];
     __shared__ float red[NT / 64];
-
     __shared__ v2 twl[Twiddles<NF>::TW];
     Twiddles<NF> tw;
-    tw.load(twl, reinterpret_cast<const v2 *>(a.twid));
-    const float *__restrict__ x = a.x;
-    const float inv_nsrc = 1.0f / (float)a.n_src;
-    const int64_t n_pairs = (a.n_frames + 1) / 2;
-    const int64_t n_iter = (n_pairs + F - 1) / F;
+    tw.load(twl, reinterpret_cast<const v2 *>(g.twid));
+    const CA ChanDesc *ch = (const CA ChanDesc *)g.ch;
 
     // Pass-1 role: frame pair f1 of the iteration, taps jj + r Q.  The pair
     // (2p, 2p+1) is packed as one complex signal g x_2p + i g x_2p+1.
     const int f1 = threadIdx.x / Q, jj = threadIdx.x % Q;
     float gw[NZ];
-#pragma unroll
-    for (int r = 0; r < NZ; ++r) {
-        const int n = jj + r * Q;
-        gw[r] = n < a.L ? reinterpret_cast<const v2 *>(a.win)[(unsigned)n].x : 0.f;
-    }
     float xa[NZ], xb[NZ];
     int oka = 0, okb = 0;
-    auto fetch = [&](int64_t it) {
-        const int64_t p = it * F + f1;   // pair index
-        const bool pv = (it < n_iter) & (p < n_pairs);
-        const int cm = (int)(2 * (pv ? p : 0) * (int64_t)a.hop - a.M) + jj;
-        const bool bv = pv & (2 * p + 1 < a.n_frames);
+    auto fetch = [&](int64_t it, const Chan &d, bool new_chan) {
+        const int64_t n_pairs = (d.n_frames + 1) / 2;
+        const bool iv = it < g.item_stop;
+        const int64_t p = (iv ? it - d.item0 : 0) * F + f1;   // pair index
+        const bool pv = iv & (p < n_pairs);
+        const int cm = (int)(2 * (pv ? p : 0) * (int64_t)d.hop - d.M) + jj;
+        const bool bv = pv & (2 * p + 1 < d.n_frames);
+        const float *__restrict__ x = d.x;
+        const unsigned n = (unsigned)d.n;
         oka = 0;
         okb = 0;
 #pragma unroll
         for (int r = 0; r < NZ; ++r) {
-            const int sa = cm + r * Q, sb = sa + a.hop;
-            const bool ga = pv & ((unsigned)sa < (unsigned)a.n);
-            const bool gb = bv & ((unsigned)sb < (unsigned)a.n);
+            const int sa = cm + r * Q, sb = sa + d.hop;
+            const bool ga = pv & ((unsigned)sa < n);
+            const bool gb = bv & ((unsigned)sb < n);
             xa[r] = x[ga ? (unsigned)sa : 0u];
             xb[r] = x[gb ? (unsigned)sb : 0u];
             oka |= (int)ga << r;
             okb |= (int)gb << r;
         }
+        if (new_chan) {
+#pragma unroll
+            for (int r = 0; r < NZ; ++r) {
+                const int tap = jj + r * Q;
+                gw[r] = tap < d.L ? reinterpret_cast<const v2 *>(d.win)[(unsigned)tap].x : 0.f;
+            }
+        }
     };
-    fetch(blockIdx.x);
+    int64_t it = g.item_begin + blockIdx.x;
+    int c = chan_of<true>(ch, g.n_ch, 0, it);
+    Chan a = load_chan<true>(ch, c);
+    fetch(it, a, true);
     float best = 0.f;
 
-    for (int64_t it = blockIdx.x; it < n_iter; it += gridDim.x) {
-        const int64_t p0 = it * F;
+    for (; it < g.item_stop; it += gridDim.x) {
+        const int64_t n_pairs = (a.n_frames + 1) / 2;
+        const int64_t p0 = (it - a.item0) * F;
         const int nvp = (int)((n_pairs - p0) < F ? (n_pairs - p0) : F);
+        const float inv_nsrc = a.inv_nsrc;
         {
             v2 v[16];
 #pragma unroll
@@ -792,7 +919,14 @@ __global__ __launch_bounds__(Geo<NF>::NT, NF == 8192 ? 4 : 3) void max_kernel(Ma
             for (int r = 0; r < 16; ++r)
                 lds[pad16(base + r)] = v[r];
         }
-        fetch(it + gridDim.x);
+        const int64_t itn = it + gridDim.x;
+        Chan an = a;
+        const bool chg = itn < g.item_stop && itn >= a.item_end;
+        if (chg) {
+            c = chan_of<true>(ch, g.n_ch, c, itn);
+            an = load_chan<true>(ch, c);
+        }
+        fetch(itn, an, chg);
         __syncthreads();
         tw.passes(lds, twl);
         const int E = nvp * a.n_src;
@@ -814,38 +948,42 @@ __global__ __launch_bounds__(Geo<NF>::NT, NF == 8192 ? 4 : 3) void max_kernel(Ma
             best = fmaxf(best, fmaxf(ma2, mb2));
         }
         __syncthreads();   // LDS reads done before the next iteration's pass 1
-    }
-    best = wave_max(best);
-    if ((threadIdx.x & 63) == 0)
-        red[threadIdx.x >> 6] = best;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        float b = red[0];
-        for (int w = 1; w < NT / 64; ++w)
-            b = fmaxf(b, red[w]);
-        a.partial[blockIdx.x] = b;
+        if (chg || itn >= g.item_stop) {
+            // leaving this channel: fold the workgroup's maximum into it
+            block_max_flush<NT>(best, red, &a.ctrl->maxbits);
+            best = 0.f;
+        }
+        a = an;
     }
 }
 
-// gamma from the pre-pass maxima (relative mode) or from the given value.
-__global__ __launch_bounds__(256) void gamma_kernel(const float *partial, int np, Ctrl *ctrl,
-                                                    int mode, float thr)
+// Clear the running maxima of the launch's channels.
+__global__ __launch_bounds__(256) void clear_max_kernel(GroupLaunch g)
 {
-    __shared__ float red[4];
-    float b = 0.f;
-    for (int i = threadIdx.x; i < np; i += 256)
-        b = fmaxf(b, partial[i]);
-    b = wave_max(b);
-    if ((threadIdx.x & 63) == 0)
-        red[threadIdx.x >> 6] = b;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const float m2 = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
-        const float g = (mode == 1) ? thr * sqrtf(m2) : thr;
-        ctrl->maxabs2 = m2;
-        ctrl->gamma = g;
-        ctrl->gamma2 = g * g;
-    }
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    if (c < g.n_ch)
+        g.ch[c].ctrl->maxbits = 0u;
+}
+
+// gamma of every channel: rho sqrt(max |S|^2) (relative) or the given value.
+__global__ __launch_bounds__(256) void gamma_kernel(GroupLaunch g)
+{
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    if (c >= g.n_ch)
+        return;
+    Ctrl *ctrl = g.ch[c].ctrl;
+    const float m2 = __uint_as_float(ctrl->maxbits);
+    const float gm = g.ch[c].thr_mode == 1 ? g.ch[c].thr * sqrtf(m2) : g.ch[c].thr;
+    ctrl->maxabs2 = m2;
+    ctrl->gamma = gm;
+    ctrl->gamma2 = gm * gm;
+}
+
+// Write one descriptor into device memory.
+__global__ __launch_bounds__(64) void put_desc_kernel(ChanDesc d, ChanDesc *dst)
+{
+    if (threadIdx.x == 0)
+        *dst = d;
 }
 
 // ---------------------------------------------------------------------------
@@ -897,19 +1035,39 @@ __device__ __forceinline__ void err_reduce(double d2, double r2, double *err, in
     }
 }
 
-__global__ __launch_bounds__(256) void inv_kernel(InvArgs a)
+// Descriptor of workgroup `blk` of an inverse launch: the last channel whose
+// blk0 <= blk (binary search over the list; every thread gets the same c).
+__device__ __forceinline__ int inv_chan_of(const CA InvDesc *ch, int n_ch, int64_t blk)
+{
+    int lo = 0, hi = n_ch - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (ch[mid].blk0 <= blk)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void inv_kernel(InvLaunch l)
 {
     extern __shared__ __align__(16) unsigned char smem[];
+    const int64_t blk = l.blk_begin + (int64_t)blockIdx.x;
+    const CA InvDesc *chs = (const CA InvDesc *)l.ch;
+    const CA InvDesc &a = chs[inv_chan_of(chs, l.n_ch, blk)];
     const int nlo = 1 << a.lo_bits;
     const int nhi = (a.G + nlo - 1) >> a.lo_bits;
     const int W = 2 * a.hw + 1;
+    const int fb = l.fb;
     v2 *tlo = reinterpret_cast<v2 *>(smem);
     v2 *thi = tlo + nlo;
-    v2 *coef = thi + nhi;
-    int *rbase = reinterpret_cast<int *>(coef + a.fb * W);
+    v2 *coef = tlo + l.max_tab;
+    int *rbase = reinterpret_cast<int *>(coef + fb * l.max_w);
 
-    const int q = blockIdx.y;
-    const int64_t tile_lo = a.span_lo + (int64_t)blockIdx.x * 256;
+    const int64_t local = blk - a.blk0;
+    const int q = (int)(local / a.tiles);
+    const int64_t tile_lo = a.span_lo + (local - (int64_t)q * a.tiles) * 256;
     const int64_t tile_hi = (tile_lo + 255 < a.span_lo + a.span_len - 1) ? tile_lo + 255
                                                                           : a.span_lo + a.span_len - 1;
     const int64_t n = tile_lo + threadIdx.x;
@@ -945,19 +1103,19 @@ __global__ __launch_bounds__(256) void inv_kernel(InvArgs a)
     const int32_t *__restrict__ ridge = a.ridge + (int64_t)q * a.nframes;
     const int zk1 = a.z * a.k1;
     float acc = 0.f;
-    for (int64_t mb = mlo; mb <= mhi; mb += a.fb) {
-        const int cnt = (int)((mhi - mb + 1) < a.fb ? (mhi - mb + 1) : a.fb);
+    for (int64_t mb = mlo; mb <= mhi; mb += fb) {
+        const int cnt = (int)((mhi - mb + 1) < fb ? (mhi - mb + 1) : fb);
         __syncthreads();
         for (int e = threadIdx.x; e < cnt * W; e += 256) {
             const int mi = e / W, d = e - mi * W;
             const int64_t mloc = mb + mi - a.frame0;
             const int r = ridge[mloc];
-            const int l = r - a.hw + d;
+            const int lq = r - a.hw + d;
             v2 c = mk(0.f, 0.f);
-            if (r >= 0 && l >= 0 && l < a.n_dst) {
-                const int b = zk1 + l;
+            if (r >= 0 && lq >= 0 && lq < a.n_dst) {
+                const int b = zk1 + lq;
                 const float wgt = (b == 0 || 2 * b == a.G) ? 1.f : 2.f;
-                c = (wgt * a.inv_nfft) * T[mloc * a.n_dst + l];
+                c = (wgt * a.inv_nfft) * T[mloc * a.n_dst + lq];
             }
             coef[e] = c;
             if (d == 0) {
@@ -1012,9 +1170,26 @@ __global__ __launch_bounds__(256) void inv_kernel(InvArgs a)
     }
 }
 
-// Eq. 15 (hop 1): xhat[m] = (1/(N_f g[0])) sum_zone a_l Re T[m,l].
-__global__ __launch_bounds__(256) void eq15_kernel(InvArgs a, float scale)
+// Clear the error sums of every channel of an inverse launch.
+__global__ __launch_bounds__(256) void clear_err_kernel(InvLaunch l)
 {
+    const int c = blockIdx.x;
+    if (c >= l.n_ch || !l.ch[c].err)
+        return;
+    for (int i = threadIdx.x; i < 2 * l.ch[c].n_comp; i += 256)
+        l.ch[c].err[i] = 0.0;
+}
+
+__global__ __launch_bounds__(64) void put_inv_desc_kernel(InvDesc d, InvDesc *dst)
+{
+    if (threadIdx.x == 0)
+        *dst = d;
+}
+
+// Eq. 15 (hop 1): xhat[m] = (1/(N_f g[0])) sum_zone a_l Re T[m,l].
+__global__ __launch_bounds__(256) void eq15_kernel(const InvDesc *dp, float scale)
+{
+    const CA InvDesc &a = *(const CA InvDesc *)dp;
     const int q = blockIdx.y;
     const int64_t mloc = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const bool valid = mloc < a.nframes;
@@ -1104,44 +1279,53 @@ int nz_rows(int L)
     return rows <= 4 ? 4 : (rows <= 8 ? 8 : 16);
 }
 
-template <int NF, int NZ>
-hipError_t launch_fwd_nz(const FwdArgs &a, int grid, hipStream_t s)
+template <int NF, int NZ, bool MULTI>
+hipError_t launch_fwd_nzm(int max_n_src, int max_n_dst, bool debug, const GroupLaunch &gl,
+                          int grid, hipStream_t s)
 {
-    const bool debug = a.S || a.Sd || a.idx || a.colstats;
     const dim3 g(grid), b(Geo<NF>::NT);
-    const size_t dyn = fwd_dyn_lds(NF, a.n_src);
-    const bool chunked = (int64_t)Geo<NF>::F * a.n_dst > Geo<NF>::LDS;
+    const bool chunked = (int64_t)Geo<NF>::F * max_n_dst > Geo<NF>::LDS;
     if (debug) {
-        hipLaunchKernelGGL((fwd_kernel<NF, NZ, 9, true, true>), g, b, dyn, s, a);
+        hipLaunchKernelGGL((fwd_kernel<NF, NZ, 9, true, true, MULTI>), g, b, 0, s, gl);
     } else if (chunked) {
-        hipLaunchKernelGGL((fwd_kernel<NF, NZ, 9, false, true>), g, b, dyn, s, a);
+        hipLaunchKernelGGL((fwd_kernel<NF, NZ, 9, false, true, MULTI>), g, b, 0, s, gl);
     } else {
-        switch (fwd_rounds(NF, a.n_src)) {
-        case 3: hipLaunchKernelGGL((fwd_kernel<NF, NZ, 3, false, false>), g, b, dyn, s, a); break;
-        case 5: hipLaunchKernelGGL((fwd_kernel<NF, NZ, 5, false, false>), g, b, dyn, s, a); break;
-        default: hipLaunchKernelGGL((fwd_kernel<NF, NZ, 9, false, false>), g, b, dyn, s, a); break;
+        switch (fwd_rounds(NF, max_n_src)) {
+        case 3: hipLaunchKernelGGL((fwd_kernel<NF, NZ, 3, false, false, MULTI>), g, b, 0, s, gl); break;
+        case 5: hipLaunchKernelGGL((fwd_kernel<NF, NZ, 5, false, false, MULTI>), g, b, 0, s, gl); break;
+        default: hipLaunchKernelGGL((fwd_kernel<NF, NZ, 9, false, false, MULTI>), g, b, 0, s, gl); break;
         }
     }
     return hipGetLastError();
 }
 
-template <int NF>
-hipError_t launch_fwd_t(const FwdArgs &a, int grid, hipStream_t s)
+template <int NF, int NZ>
+hipError_t launch_fwd_nz(int max_n_src, int max_n_dst, bool debug, const GroupLaunch &gl,
+                         int grid, hipStream_t s)
 {
-    switch (nz_rows<NF>(a.L)) {
-    case 4: return launch_fwd_nz<NF, 4>(a, grid, s);
-    case 8: return launch_fwd_nz<NF, 8>(a, grid, s);
-    default: return launch_fwd_nz<NF, 16>(a, grid, s);
+    return gl.n_ch > 1 ? launch_fwd_nzm<NF, NZ, true>(max_n_src, max_n_dst, debug, gl, grid, s)
+                       : launch_fwd_nzm<NF, NZ, false>(max_n_src, max_n_dst, debug, gl, grid, s);
+}
+
+template <int NF>
+hipError_t launch_fwd_t(int max_L, int max_n_src, int max_n_dst, bool debug, const GroupLaunch &gl,
+                        int grid, hipStream_t s)
+{
+    switch (nz_rows<NF>(max_L)) {
+    case 4: return launch_fwd_nz<NF, 4>(max_n_src, max_n_dst, debug, gl, grid, s);
+    case 8: return launch_fwd_nz<NF, 8>(max_n_src, max_n_dst, debug, gl, grid, s);
+    default: return launch_fwd_nz<NF, 16>(max_n_src, max_n_dst, debug, gl, grid, s);
     }
 }
 
 template <int NF>
-hipError_t launch_max_t(const MaxArgs &a, int grid, hipStream_t s)
+hipError_t launch_max_t(int L, const GroupLaunch &gl, int grid, hipStream_t s)
 {
-    switch (nz_rows<NF>(a.L)) {
-    case 4: hipLaunchKernelGGL((max_kernel<NF, 4>), dim3(grid), dim3(Geo<NF>::NT), 0, s, a); break;
-    case 8: hipLaunchKernelGGL((max_kernel<NF, 8>), dim3(grid), dim3(Geo<NF>::NT), 0, s, a); break;
-    default: hipLaunchKernelGGL((max_kernel<NF, 16>), dim3(grid), dim3(Geo<NF>::NT), 0, s, a); break;
+    const dim3 g(grid), b(Geo<NF>::NT);
+    switch (nz_rows<NF>(L)) {
+    case 4: hipLaunchKernelGGL((max_kernel<NF, 4>), g, b, 0, s, gl); break;
+    case 8: hipLaunchKernelGGL((max_kernel<NF, 8>), g, b, 0, s, gl); break;
+    default: hipLaunchKernelGGL((max_kernel<NF, 16>), g, b, 0, s, gl); break;
     }
     return hipGetLastError();
 }
@@ -1156,14 +1340,13 @@ int occ_of(K kernel, int threads, size_t dyn = 0)
 }
 
 template <int NF>
-int occ_fwd_t(int L, int n_src)
+int occ_fwd_t(int L)
 {
-    // every variant of one N_f has the same LDS and launch bounds
-    const size_t dyn = fwd_dyn_lds(NF, n_src);
+    // every variant of one N_f and NZ has the same LDS and launch bounds
     switch (nz_rows<NF>(L)) {
-    case 4: return occ_of(fwd_kernel<NF, 4, 9, false, true>, Geo<NF>::NT, dyn);
-    case 8: return occ_of(fwd_kernel<NF, 8, 9, false, true>, Geo<NF>::NT, dyn);
-    default: return occ_of(fwd_kernel<NF, 16, 9, false, true>, Geo<NF>::NT, dyn);
+    case 4: return occ_of(fwd_kernel<NF, 4, 9, false, true, true>, Geo<NF>::NT);
+    case 8: return occ_of(fwd_kernel<NF, 8, 9, false, true, true>, Geo<NF>::NT);
+    default: return occ_of(fwd_kernel<NF, 16, 9, false, true, true>, Geo<NF>::NT);
     }
 }
 
@@ -1178,13 +1361,6 @@ int occ_max_t(int L)
 }
 
 }  // namespace
-
-// Dynamic LDS of the forward kernel: the centre-phase table when several
-// frames share an iteration (N_f < 4096), nothing otherwise.
-size_t fwd_dyn_lds(int nfft, int n_src)
-{
-    return nfft < 4096 ? sizeof(float2) * (size_t)n_src : 0;
-}
 
 int fwd_rounds(int nfft, int n_src)
 {
@@ -1204,50 +1380,56 @@ int fwd_rounds(int nfft, int n_src)
     default: break;                                 \
     }
 
-hipError_t launch_threshold(int nfft, const MaxArgs &a, Ctrl *ctrl, int mode, float thr,
-                            int grid, hipStream_t s)
+hipError_t launch_threshold(int nfft, int L, const GroupLaunch &g, int grid, hipStream_t s)
 {
-    if (mode == 1) {
-        hipError_t e = hipErrorInvalidValue;
-        SST_DISPATCH_NF(nfft, e = launch_max_t<NFv>(a, grid, s); break)
+    const unsigned cb = (unsigned)((g.n_ch + 255) / 256);
+    hipLaunchKernelGGL(clear_max_kernel, dim3(cb), dim3(256), 0, s, g);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    if (g.item_stop > g.item_begin && grid > 0) {
+        e = hipErrorInvalidValue;
+        SST_DISPATCH_NF(nfft, e = launch_max_t<NFv>(L, g, grid, s); break)
         if (e != hipSuccess)
             return e;
     }
-    hipLaunchKernelGGL(gamma_kernel, dim3(1), dim3(256), 0, s, a.partial, mode == 1 ? grid : 0,
-                       ctrl, mode, thr);
+    hipLaunchKernelGGL(gamma_kernel, dim3(cb), dim3(256), 0, s, g);
     return hipGetLastError();
 }
 
-hipError_t launch_forward(int nfft, const FwdArgs &a, int grid, hipStream_t s)
+hipError_t launch_forward(int nfft, int max_L, int max_n_src, int max_n_dst, bool debug,
+                          const GroupLaunch &g, int grid, hipStream_t s)
 {
-    SST_DISPATCH_NF(nfft, return launch_fwd_t<NFv>(a, grid, s))
+    SST_DISPATCH_NF(nfft, return launch_fwd_t<NFv>(max_L, max_n_src, max_n_dst, debug, g, grid, s))
     return hipErrorInvalidValue;
 }
 
-size_t inv_lds_bytes(const InvArgs &a)
+hipError_t launch_put_desc(const ChanDesc &d, ChanDesc *dst, hipStream_t s)
 {
-    const int nlo = 1 << a.lo_bits;
-    const int nhi = (a.G + nlo - 1) >> a.lo_bits;
-    const int W = 2 * a.hw + 1;
-    return sizeof(float2) * (size_t)(nlo + nhi + a.fb * W) + sizeof(int) * (size_t)a.fb;
+    hipLaunchKernelGGL(put_desc_kernel, dim3(1), dim3(64), 0, s, d, dst);
+    return hipGetLastError();
 }
 
-hipError_t launch_inverse(const InvArgs &a, hipStream_t s)
+size_t inv_lds_bytes(const InvLaunch &l)
 {
-    if (a.err) {
-        hipLaunchKernelGGL(zero_f64, dim3((2 * a.n_comp + 63) / 64), dim3(64), 0, s, a.err,
-                           2 * a.n_comp);
+    return sizeof(float2) * (size_t)(l.max_tab + l.fb * l.max_w) + sizeof(int) * (size_t)l.fb;
+}
+
+hipError_t launch_inverse(const InvLaunch &l, int64_t blocks, bool clear_err, hipStream_t s)
+{
+    if (clear_err) {
+        hipLaunchKernelGGL(clear_err_kernel, dim3((unsigned)l.n_ch), dim3(256), 0, s, l);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess)
             return e;
     }
-    const int64_t blocks = (a.span_len + 255) / 256;
-    hipLaunchKernelGGL(inv_kernel, dim3((unsigned)blocks, a.n_comp), dim3(256), inv_lds_bytes(a),
-                       s, a);
+    if (blocks <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(inv_kernel, dim3((unsigned)blocks), dim3(256), inv_lds_bytes(l), s, l);
     return hipGetLastError();
 }
 
-hipError_t launch_inverse_eq15(const InvArgs &a, float scale, hipStream_t s)
+hipError_t launch_inverse_eq15(const InvDesc &a, const InvDesc *dev, float scale, hipStream_t s)
 {
     if (a.err) {
         hipLaunchKernelGGL(zero_f64, dim3((2 * a.n_comp + 63) / 64), dim3(64), 0, s, a.err,
@@ -1257,7 +1439,13 @@ hipError_t launch_inverse_eq15(const InvArgs &a, float scale, hipStream_t s)
             return e;
     }
     const int64_t blocks = (a.nframes + 255) / 256;
-    hipLaunchKernelGGL(eq15_kernel, dim3((unsigned)blocks, a.n_comp), dim3(256), 0, s, a, scale);
+    hipLaunchKernelGGL(eq15_kernel, dim3((unsigned)blocks, a.n_comp), dim3(256), 0, s, dev, scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_put_inv_desc(const InvDesc &d, InvDesc *dst, hipStream_t s)
+{
+    hipLaunchKernelGGL(put_inv_desc_kernel, dim3(1), dim3(64), 0, s, d, dst);
     return hipGetLastError();
 }
 
@@ -1287,21 +1475,21 @@ template <int NF>
 size_t fwd_static_lds_t()
 {
     hipFuncAttributes at{};
-    if (hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&fwd_kernel<NF, 16, 9, true, true>)) !=
+    if (hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&fwd_kernel<NF, 16, 9, true, true, true>)) !=
         hipSuccess)
         return 0;
     return at.sharedSizeBytes;
 }
 
-size_t fwd_lds_bytes(int nfft, int n_src)
+size_t fwd_lds_bytes(int nfft)
 {
-    SST_DISPATCH_NF(nfft, return fwd_static_lds_t<NFv>() + fwd_dyn_lds(NFv, n_src))
+    SST_DISPATCH_NF(nfft, return fwd_static_lds_t<NFv>())
     return 0;
 }
 
-int fwd_occupancy(int nfft, int L, int n_src)
+int fwd_occupancy(int nfft, int L)
 {
-    SST_DISPATCH_NF(nfft, return occ_fwd_t<NFv>(L, n_src))
+    SST_DISPATCH_NF(nfft, return occ_fwd_t<NFv>(L))
     return 1;
 }
 int max_occupancy(int nfft, int L)

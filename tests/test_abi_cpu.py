@@ -141,3 +141,71 @@ def test_sigma_f_example(golden):
     sf = 1.0 / (2 * np.pi * 0.03)
     assert abs(sf - golden["sigma_f_sim_hz"]["value"]) < golden["sigma_f_sim_hz"]["tol"]
     assert abs(6 * sf - golden["six_sigma_f_sim_hz"]["value"]) < golden["six_sigma_f_sim_hz"]["tol"]
+
+
+def _batch_params(cfgs):
+    arr = (sst.Params * len(cfgs))()
+    keep = []
+    for i, kw in enumerate(cfgs):
+        d = _params(**kw)
+        arr[i] = sst._params(d["n_samples"], d["fs"], d["win_len"], d["sigma"], d["hop"],
+                             d["nfft"], d["f_lo"], d["f_hi"], d["subdiv"], d["thr_mode"],
+                             d["thr"], None, None, keep)
+    return arr
+
+
+def test_batch_plan_shapes_and_workspace():
+    cfgs = [dict(), dict(nfft=1024, win_len=255, sigma=32.0, hop=8, subdiv=2),
+            dict(nfft=8192, win_len=2047, sigma=256.0, hop=32, f_hi=5000.0, subdiv=8,
+                 n_samples=3000)]
+    L = sst.lib()
+    h = ctypes.c_void_p()
+    assert L.sst_batch_plan(_batch_params(cfgs), len(cfgs), ctypes.byref(h)) == sst.SST_OK
+    try:
+        total = None
+        for c, kw in enumerate(cfgs):
+            sh = sst.Shape()
+            assert L.sst_batch_query(h, c, ctypes.byref(sh)) == sst.SST_OK
+            single = sst.Plan(**_params(**kw))
+            assert (sh.n_frames, sh.n_src, sh.n_dst, sh.k1) == (
+                single.n_frames, single.n_src, single.n_dst, single.k1)
+            # the batch workspace holds every channel's own workspace
+            assert sh.workspace_bytes >= single.shape.workspace_bytes
+            total = sh.workspace_bytes if total is None else total
+            assert sh.workspace_bytes == total
+        sh = sst.Shape()
+        assert L.sst_batch_query(h, len(cfgs), ctypes.byref(sh)) == sst.SST_E_ARG
+        assert L.sst_batch_query(h, -1, ctypes.byref(sh)) == sst.SST_E_ARG
+    finally:
+        L.sst_batch_destroy(h)
+
+
+def test_batch_plan_names_the_bad_channel():
+    L = sst.lib()
+    h = ctypes.c_void_p()
+    rc = L.sst_batch_plan(_batch_params([dict(), dict(hop=0)]), 2, ctypes.byref(h))
+    assert rc == sst.SST_E_ARG
+    assert b"channel 1" in L.sst_last_error()
+    assert L.sst_batch_plan(None, 1, ctypes.byref(h)) == sst.SST_E_ARG
+    assert L.sst_batch_plan(_batch_params([dict()]), 0, ctypes.byref(h)) == sst.SST_E_ARG
+
+
+def test_batch_refuses_work_before_bind_and_commit():
+    L = sst.lib()
+    h = ctypes.c_void_p()
+    assert L.sst_batch_plan(_batch_params([dict(), dict()]), 2, ctypes.byref(h)) == sst.SST_OK
+    try:
+        assert L.sst_batch_forward(h, 0, 2, 0, None) == sst.SST_E_STATE
+        assert L.sst_batch_inverse(h, 0, 2, None) == sst.SST_E_STATE
+        assert L.sst_batch_commit(h, None) == sst.SST_E_STATE
+        assert L.sst_batch_bind(h, None, 1 << 20, None) == sst.SST_E_WORKSPACE
+        assert L.sst_batch_set_io(h, 2, None, None, None, 0, 0, None, None,
+                                  None) == sst.SST_E_ARG
+        # inverse buffers are checked when recorded
+        assert L.sst_batch_set_io(h, 0, ctypes.c_void_p(16), ctypes.c_void_p(16),
+                                  ctypes.c_void_p(16), 0, 2, ctypes.c_void_p(16), None,
+                                  None) == sst.SST_E_ARG
+        assert L.sst_batch_set_io(h, 0, ctypes.c_void_p(16), ctypes.c_void_p(16), None, 0, 0,
+                                  None, None, ctypes.c_void_p(16)) == sst.SST_E_ARG
+    finally:
+        L.sst_batch_destroy(h)
