@@ -339,3 +339,58 @@ def test_forward_is_bitwise_reproducible(sst, name, n, cfg):
         same = torch.equal(torch.view_as_real(T), torch.view_as_real(ref))
         _say(f"[repro] {name} run {k}: equal={same}")
         assert same
+
+
+def test_c2_full_size_sampled(sst):
+    """The headline workload at full size (N = 2^20, 65,536 frames) in the launch
+    configuration bench.py times: gamma over every frame, sampled T rows (start,
+    middle, end) under the parity rules, and the inverse of a sampled output
+    range against the oracle on identical T."""
+    from workloads import make_c2, ridge_bins
+    w = make_c2()
+    cfg = w.cfg
+    plan = sst.Plan.from_config(w.n, cfg, device="cuda")
+    xg = torch.from_numpy(w.x).cuda()
+    gam = torch.empty(1, dtype=torch.float32, device="cuda")
+    T = plan.forward(xg, gamma=gam)            # the timed kernel variant (no debug outputs)
+    torch.cuda.synchronize()
+    x64 = w.x.astype(np.float64)
+    g_o, gd_o = oracle.gaussian_windows(cfg.win_len, cfg.sigma)
+    b = oracle.band(cfg.fs, cfg.nfft, cfg.f_lo, cfg.f_hi, cfg.subdiv)
+    gamma_o = cfg.thr * oracle.stft_maxabs(x64, g_o, cfg.hop, cfg.nfft, b.k1, b.k2)
+    g_g = float(gam.cpu()[0])
+    _say(f"[full c2] gamma gpu={g_g:.9g} oracle={gamma_o:.9g}")
+    assert abs(g_g - gamma_o) <= 1e-5 * gamma_o
+    s_pack = math.sqrt(np.sum(g_o ** 2) / np.sum(gd_o ** 2))
+    for f0 in (0, plan.n_frames // 2 - 32, plan.n_frames - 64):
+        nfr = 64
+        S = torch.empty((nfr, plan.n_src), dtype=torch.complex64, device="cuda")
+        idx = torch.empty((nfr, plan.n_src), dtype=torch.int32, device="cuda")
+        Td = plan.forward(xg, None, f0, nfr, S=S, idx=idx, reuse_gamma=True)
+        torch.cuda.synchronize()
+        rows = T[f0:f0 + nfr]
+        assert torch.equal(torch.view_as_real(Td), torch.view_as_real(rows)), f0
+        o = oracle.forward(x64, cfg, f0, nfr, gamma=gamma_o)
+        idx_g = idx.cpu().numpy()
+        ny = packed_norms(w.x, g_o, gd_o, s_pack, cfg.hop, np.arange(f0, f0 + nfr))
+        rep, _ = classify_indices(idx_g, o.idx, o.frac, o.S, o.Sd, o.gamma, cfg.nfft,
+                                  cfg.subdiv, s_pack, ny, plan.n_dst)
+        e_s = relf(S.cpu().numpy(), o.S)
+        e_t = relf(rows.cpu().numpy(), reconciled_T(o.S, idx_g, plan.n_dst))
+        _say(f"  frames {f0}+{nfr}: relF S={e_s:.2e} T(reconciled)={e_t:.2e} {rep}")
+        assert e_s <= 1e-5 and e_t <= 1e-5 and rep.ok(), (rep, rep.details)
+    # inverse of output samples [a, b) needs only the frames whose windows reach them:
+    # the oracle gets the GPU's T on those frames and zeros elsewhere
+    ridge = ridge_bins(w.inst_freq(w.frame_times()), cfg.fs, cfg.nfft, plan.k1, cfg.subdiv,
+                       plan.n_dst)
+    xh = plan.inverse(T, torch.from_numpy(ridge).cuda(), cfg.hw).cpu().numpy()
+    M = (cfg.win_len - 1) // 2
+    a, bnd = w.n // 2, w.n // 2 + 4096
+    m_lo, m_hi = (a - M) // cfg.hop, (bnd + M) // cfg.hop + 1
+    T64 = np.zeros((plan.n_frames, plan.n_dst), dtype=np.complex128)
+    T64[m_lo:m_hi + 1] = T[m_lo:m_hi + 1].cpu().numpy()
+    for q in range(ridge.shape[0]):
+        xo = oracle.inverse(T64, ridge[q], cfg.hw, g_o, cfg.hop, cfg.nfft, plan.k1, cfg.subdiv, w.n)
+        e = relf(xh[q, a:bnd], xo[a:bnd])
+        _say(f"  inverse comp {q}: relF on samples [{a}, {bnd}) = {e:.2e}")
+        assert e <= 1e-5
