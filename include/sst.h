@@ -61,7 +61,11 @@ typedef int32_t sst_status;
 #define SST_THR_REL_MAX 1       /* gamma = thr * max |S| over every frame and in-band bin */
 
 /* STFT arithmetic of the forward transform. */
-#define SST_PREC_FP32_FFT 0     /* FP32 LDS FFT pair (the only precision built) */
+#define SST_PREC_FP32_FFT 0     /* FP32 LDS FFT pair */
+#define SST_PREC_GEMM_BF16 1    /* STFT as a DFT-matrix product on the matrix cores, BF16
+                                   operands, FP32 accumulation */
+#define SST_PREC_GEMM_F16X3 2   /* the same with FP16 hi/lo split operands, three products
+                                   (hi*hi + hi*lo + lo*hi), FP32 accumulation */
 
 /* sst_forward flags */
 #define SST_FWD_REUSE_GAMMA 1u  /* keep the gamma computed by the previous forward call
@@ -86,7 +90,10 @@ typedef int32_t sst_status;
  *   subdiv       z >= 1, z*N_f <= 2^20
  *   thr_mode     SST_THR_ABS or SST_THR_REL_MAX
  *   thr          gamma (ABS, >= 0) or rho (REL_MAX, >= 0)
- *   precision    SST_PREC_FP32_FFT
+ *   precision    SST_PREC_FP32_FFT, or a DFT-as-GEMM tier (SST_PREC_GEMM_BF16,
+ *                SST_PREC_GEMM_F16X3) for 512 <= nfft <= 2048 and hop a multiple of 8;
+ *                the threshold pre-pass stays FP32 FFT; the GEMM tiers are not
+ *                supported by the batched calls
  *   flags        reserved, 0
  */
 typedef struct {

@@ -31,6 +31,10 @@ SST_E_NOMEM = -6
 SST_THR_ABS = 0
 SST_THR_REL_MAX = 1
 SST_PREC_FP32_FFT = 0
+SST_PREC_GEMM_BF16 = 1
+SST_PREC_GEMM_F16X3 = 2
+PRECISIONS = {"fp32": SST_PREC_FP32_FFT, "bf16": SST_PREC_GEMM_BF16,
+              "f16x3": SST_PREC_GEMM_F16X3}
 SST_FWD_REUSE_GAMMA = 1
 SST_INV_ACCUMULATE = 1
 SST_INV_EQ15 = 2
@@ -171,7 +175,7 @@ def _stream_handle(device) -> int:
 
 def _params(n_samples: int, fs: float, win_len: int, sigma: float, hop: int, nfft: int,
             f_lo: float, f_hi: float, subdiv: int, thr_mode: str, thr: float, window, dwindow,
-            keep: list) -> Params:
+            keep: list, precision: str = "fp32") -> Params:
     p = Params()
     p.struct_size = ctypes.sizeof(Params)
     p.n_samples = int(n_samples)
@@ -192,7 +196,7 @@ def _params(n_samples: int, fs: float, win_len: int, sigma: float, hop: int, nff
     p.subdiv = int(subdiv)
     p.thr_mode = SST_THR_ABS if thr_mode == "abs" else SST_THR_REL_MAX
     p.thr = float(thr)
-    p.precision = SST_PREC_FP32_FFT
+    p.precision = PRECISIONS[precision]
     p.flags = 0
     return p
 
@@ -202,11 +206,14 @@ class Plan:
 
     def __init__(self, n_samples: int, fs: float, win_len: int, sigma: float, hop: int,
                  nfft: int, f_lo: float, f_hi: float, subdiv: int = 1, thr_mode: str = "rel",
-                 thr: float = 1e-3, window=None, dwindow=None, device=None):
+                 thr: float = 1e-3, window=None, dwindow=None, device=None,
+                 precision: str = "fp32"):
+        """precision: "fp32" (FFT), "bf16" or "f16x3" (DFT-as-GEMM on the matrix cores)."""
         self._h = None
         keep = []
         p = _params(n_samples, fs, win_len, sigma, hop, nfft, f_lo, f_hi, subdiv, thr_mode, thr,
-                    window, dwindow, keep)
+                    window, dwindow, keep, precision)
+        self.precision = precision
         h = ctypes.c_void_p()
         _check(lib().sst_plan(ctypes.byref(p), ctypes.byref(h)), "sst_plan")
         self._h = h
@@ -224,9 +231,10 @@ class Plan:
             self.bind(device)
 
     @classmethod
-    def from_config(cls, n_samples: int, cfg, device=None) -> "Plan":
+    def from_config(cls, n_samples: int, cfg, device=None, precision: str = "fp32") -> "Plan":
         return cls(n_samples, cfg.fs, cfg.win_len, cfg.sigma, cfg.hop, cfg.nfft, cfg.f_lo,
-                   cfg.f_hi, cfg.subdiv, cfg.thr_mode, cfg.thr, device=device)
+                   cfg.f_hi, cfg.subdiv, cfg.thr_mode, cfg.thr, device=device,
+                   precision=precision)
 
     def bind(self, device="cuda"):
         import torch

@@ -14,7 +14,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libsst_hip.so")
-SOURCES = [os.path.join(CSRC, "sst_host.cpp"), os.path.join(CSRC, "sst_kernels.hip")]
+SOURCES = [os.path.join(CSRC, "sst_host.cpp"), os.path.join(CSRC, "sst_kernels.hip"),
+           os.path.join(CSRC, "sst_gemm.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 COMMON = [

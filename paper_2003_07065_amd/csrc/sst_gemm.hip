@@ -1,0 +1,323 @@
+// gfx950 DFT-as-GEMM forward kernel of the downsampled SST (precision tier).
+//
+// Method: He & Cao, arXiv 2003.07065.  The in-band STFT pair of Eq. 9 (with its
+// centre phase) is a matrix product: for FT consecutive frames m,
+//   C[r, m] = sum_j A[r, j] X[j, m],   X[j, m] = x[mH - M + j]  (j < L),
+// where row r = 4 b + p of A holds, for source bin k = k1 + b and tap t = j - M,
+//   p = 0: g[t] cos(2 pi (k t mod N_f) / N_f)     (Re S)
+//   p = 1: -g[t] sin(...)                        (Im S)
+//   p = 2, 3: the same with g' (Re S', Im S').
+// A is built once on the host in float64 and rounded to BF16, or split into
+// FP16 hi + lo parts (each scaled by a power of two into FP16's range); X is the
+// frames' sample slab staged in LDS.  The products run on the matrix cores
+// (32x32x16 MFMA, FP32 accumulation): one product for BF16, three for the
+// FP16 split (hi*hi + hi*lo + lo*hi).  The epilogue works straight from the
+// accumulators: each lane holds the four rows of a bin for one frame, so it
+// evaluates the IF estimate and the destination (Eqs. 12-13, 27-29) and adds
+// S to the frame's destination histogram in LDS (Eq. 28), which is streamed to
+// HBM as rows of T once every row tile is done.
+//
+// Histogram arithmetic.  As in the FFT kernel the sums are 32-bit fixed-point
+// integers (order independent), but the scale must be fixed before the first
+// row tile: by Parseval, sum_k |S_k|^2 <= N_f sum_j x_j^2 g_j^2 over all N_f
+// bins, hence sum over the n_src band bins of (|Re S| + |Im S|) is at most
+// sqrt(2 n_src N_f sum_j x_j^2 g_j^2), taken with a 10 % margin for the
+// rounding of the low-precision products.
+//
+// Layouts (32x32x16 MFMA, checked on the hardware): lane l holds A rows
+// l mod 32 with k = 8 (l / 32) .. +7, B columns (frames) l mod 32 with the same
+// k, and accumulator i holds row 8 (i / 4) + 4 (l / 32) + i mod 4, column l mod
+// 32.  With rows ordered 4 b + p, accumulators 4q .. 4q+3 of a lane are the
+// four parts of bin 2q + l / 32 of the row tile for frame l mod 32.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sst_internal.h"
+
+namespace sst {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef unsigned u4v __attribute__((ext_vector_type(4)));
+typedef unsigned u2v __attribute__((ext_vector_type(2)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+
+constexpr int kBufferWord3 = 0x00020000;   // raw buffer, 32-bit data format
+constexpr int kNonTemporal = 2;
+constexpr int NT = 256;                    // threads per workgroup (4 waves)
+
+// Power-of-two scale 2^K with B 2^K < 2^31 (B >= 0), clamped to [2^-100, 2^100].
+__device__ __forceinline__ float fixed_scale(float B)
+{
+    int e = 0;
+    frexpf(B, &e);
+    int K = B > 0.f ? 31 - e : 0;
+    K = K > 100 ? 100 : (K < -100 ? -100 : K);
+    return ldexpf(1.0f, K);
+}
+
+template <int PREC>
+__device__ __forceinline__ f32x16 mma(u4v a, u4v b, f32x16 c)
+{
+    if constexpr (PREC == SST_GEMM_BF16)
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
+                                                       __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+    else
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a),
+                                                      __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
+}
+
+// Low-precision copy of one sample: BF16 (round to nearest even), or the FP16
+// hi part and the FP16 rounding of the remainder.
+template <int PREC>
+__device__ __forceinline__ void split(float v, unsigned short &hi, unsigned short &lo)
+{
+    if constexpr (PREC == SST_GEMM_BF16) {
+        hi = __builtin_bit_cast(unsigned short, (__bf16)v);
+        lo = 0;
+    } else {
+        const _Float16 h = (_Float16)v;
+        hi = __builtin_bit_cast(unsigned short, h);
+        lo = __builtin_bit_cast(unsigned short, (_Float16)(v - (float)h));
+    }
+}
+
+template <int PREC>
+__device__ __forceinline__ float widen(unsigned short hi, unsigned short lo)
+{
+    if constexpr (PREC == SST_GEMM_BF16)
+        return (float)__builtin_bit_cast(__bf16, hi);
+    else
+        return (float)__builtin_bit_cast(_Float16, hi) + (float)__builtin_bit_cast(_Float16, lo);
+}
+
+__device__ __forceinline__ float block_max(float v, float *red)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        v = fmaxf(v, __shfl_xor(v, o, 64));
+    if ((threadIdx.x & 63) == 0)
+        red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    const float r = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+    __syncthreads();
+    return r;
+}
+
+// FT frames per tile (32 or 64: one or two 32-frame column tiles).
+template <int PREC, int FT, bool DEBUG>
+__global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmArgs a)
+{
+    constexpr int CT = FT / 32;               // column tiles
+    constexpr bool SPLIT = PREC == SST_GEMM_F16X3;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int slab = a.slab;                  // samples staged per tile (multiple of 8)
+    int *hist = reinterpret_cast<int *>(smem);                        // [FT][n_dst][2]
+    unsigned short *xhi = reinterpret_cast<unsigned short *>(hist + 2 * FT * a.n_dst);
+    unsigned short *xlo = xhi + slab;                                 // SPLIT only
+    float *g2 = reinterpret_cast<float *>(xlo + (SPLIT ? slab : 0));  // [L]: g^2
+    float *scf = g2 + ((a.L + 3) & ~3);                               // [FT]
+    float *red = scf + FT;                                            // [4]
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = lane & 31, half = lane >> 5;
+    const int64_t n_tiles = (a.nframes + FT - 1) / FT;
+    const float gamma2 = a.ctrl->gamma2;
+    const u4v *__restrict__ afrag = reinterpret_cast<const u4v *>(a.afrag);
+    const u4v *__restrict__ afrag_lo = reinterpret_cast<const u4v *>(a.afrag_lo);
+
+    for (int j = threadIdx.x; j < a.L; j += NT) {
+        const float g = a.win[j].x;
+        g2[j] = g * g;
+    }
+
+    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        const int64_t m0 = tile * FT;   // first frame of the tile, relative to frame0
+        const int nvalid = (int)((a.nframes - m0) < FT ? (a.nframes - m0) : FT);
+        const int64_t s0 = (a.frame0 + m0) * (int64_t)a.hop - a.M;
+        __syncthreads();   // previous tile's store phase is done with the LDS
+
+        // slab of samples, zero outside the signal; FP16 split: scaled by 2^sx
+        float vmax = 0.f;
+        for (int s = threadIdx.x; s < slab; s += NT) {
+            const int64_t n = s0 + s;
+            const float v = (n >= 0 && n < a.n) ? a.x[n] : 0.f;
+            vmax = fmaxf(vmax, fabsf(v));
+        }
+        float sxs = 1.f, sxu = 1.f;
+        if constexpr (SPLIT) {
+            const float mx = block_max(vmax, red);
+            int e = 0;
+            frexpf(mx, &e);                       // mx < 2^e
+            const int sx = mx > 0.f ? 14 - e : 0;   // mx 2^sx < 2^14
+            sxs = ldexpf(1.f, sx);
+            sxu = ldexpf(1.f, -sx);
+        }
+        for (int s = threadIdx.x; s < slab; s += NT) {
+            const int64_t n = s0 + s;
+            const float v = (n >= 0 && n < a.n) ? a.x[n] : 0.f;
+            unsigned short hi, lo;
+            split<PREC>(v * sxs, hi, lo);
+            xhi[s] = hi;
+            if constexpr (SPLIT)
+                xlo[s] = lo;
+        }
+        for (int e = threadIdx.x; e < 2 * FT * a.n_dst; e += NT)
+            hist[e] = 0;
+        __syncthreads();
+
+        // per-frame fixed-point scale from the Parseval bound
+        {
+            constexpr int TPF = NT / FT;          // threads per frame
+            const int f = threadIdx.x / TPF, part = threadIdx.x % TPF;
+            float en = 0.f;
+            for (int j = part; j < a.L; j += TPF) {
+                const int s = f * a.hop + j;
+                const float v = widen<PREC>(xhi[s], SPLIT ? xlo[s] : (unsigned short)0) * sxu;
+                en += v * v * g2[j];
+            }
+#pragma unroll
+            for (int o = TPF / 2; o > 0; o >>= 1)
+                en += __shfl_xor(en, o, 64);
+            if (part == 0)
+                scf[f] = fixed_scale(a.bound_c * sqrtf(en));
+        }
+        __syncthreads();
+
+        const float ug = a.unscale_g * sxu, ugd = a.unscale_gd * sxu;
+        for (int rt = wave; rt < a.row_tiles; rt += 4) {
+            f32x16 acc[CT];
+#pragma unroll
+            for (int c = 0; c < CT; ++c)
+                acc[c] = f32x16{};
+            const int64_t abase = (int64_t)rt * a.ksteps * 64 + lane;
+            u4v an = afrag[abase];
+            u4v anl = SPLIT ? afrag_lo[abase] : u4v{};
+            for (int ks = 0; ks < a.ksteps; ++ks) {
+                const u4v ac = an, acl = anl;
+                if (ks + 1 < a.ksteps) {
+                    an = afrag[abase + (int64_t)(ks + 1) * 64];
+                    if constexpr (SPLIT)
+                        anl = afrag_lo[abase + (int64_t)(ks + 1) * 64];
+                }
+#pragma unroll
+                for (int c = 0; c < CT; ++c) {
+                    const int s = (c * 32 + col) * a.hop + ks * 16 + 8 * half;
+                    const u4v b = *reinterpret_cast<const u4v *>(xhi + s);
+                    acc[c] = mma<PREC>(ac, b, acc[c]);
+                    if constexpr (SPLIT) {
+                        const u4v bl = *reinterpret_cast<const u4v *>(xlo + s);
+                        acc[c] = mma<PREC>(ac, bl, acc[c]);
+                        acc[c] = mma<PREC>(acl, b, acc[c]);
+                    }
+                }
+            }
+            // epilogue: IF estimate, destination, histogram (Eqs. 12-13, 27-29)
+#pragma unroll
+            for (int c = 0; c < CT; ++c) {
+                const int f = c * 32 + col;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int b = rt * 8 + 2 * q + half;
+                    if (b >= a.n_src || f >= nvalid)
+                        continue;
+                    const float sr = acc[c][4 * q] * ug, si = acc[c][4 * q + 1] * ug;
+                    const float dr = acc[c][4 * q + 2] * ugd, di = acc[c][4 * q + 3] * ugd;
+                    const float mag2 = sr * sr + si * si;
+                    const int k = a.k1 + b;
+                    int code = -1;
+                    if (mag2 > gamma2) {
+                        const float im = di * sr - dr * si;   // Im(S' conj S)
+                        const float delta = a.cdelta * im / mag2;
+                        const float zd = (float)a.z * delta;
+                        const float hi = delta <= (float)k ? 0.5f - zd : zd + 0.5f;
+                        const int ibase = delta <= (float)k ? a.z * (k - a.k1) : -a.z * (k + a.k1);
+                        const int l = ibase + (int)floorf(fminf(fmaxf(hi, -1.0e8f), 1.0e8f));
+                        code = (fabsf(zd) < 1.0e8f && l >= 0 && l < a.n_dst) ? l : -2;
+                    }
+                    if (code >= 0) {
+                        const float sc = scf[f];
+                        int *h = hist + 2 * (f * a.n_dst + code);
+                        atomicAdd(h, (int)rintf(sr * sc));
+                        atomicAdd(h + 1, (int)rintf(si * sc));
+                    }
+                    if constexpr (DEBUG) {
+                        const int64_t o = (m0 + f) * (int64_t)a.n_src + b;
+                        if (a.S)
+                            a.S[o] = make_float2(sr, si);
+                        if (a.Sd)
+                            a.Sd[o] = make_float2(dr, di);
+                        if (a.idx)
+                            a.idx[o] = code;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+
+        // store phase: the tile's rows of T are contiguous; a buffer resource
+        // bounded to the valid rows drops the rest
+        const int cnt = nvalid * a.n_dst;
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            a.T + m0 * a.n_dst, (short)0, cnt * 8, kBufferWord3);
+        const float inv_ndst = 1.0f / (float)a.n_dst;
+        for (int e = threadIdx.x; e < FT * a.n_dst; e += NT) {
+            int f = (int)(((float)e + 0.5f) * inv_ndst);
+            f = f < FT ? f : FT - 1;
+            const float isc = 1.0f / scf[f];
+            const f2v v = {(float)hist[2 * e] * isc, (float)hist[2 * e + 1] * isc};
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2v, v), rs, (unsigned)e * 8u,
+                                                  0, kNonTemporal);
+        }
+    }
+}
+
+template <int PREC, int FT>
+hipError_t launch_prec_ft(bool debug, const GemmArgs &a, int grid, hipStream_t s)
+{
+    const size_t lds = gemm_lds_bytes(PREC, FT, a.n_dst, a.slab, a.L);
+    if (debug)
+        hipLaunchKernelGGL((gemm_kernel<PREC, FT, true>), dim3(grid), dim3(NT), lds, s, a);
+    else
+        hipLaunchKernelGGL((gemm_kernel<PREC, FT, false>), dim3(grid), dim3(NT), lds, s, a);
+    return hipGetLastError();
+}
+
+template <int PREC, int FT>
+int occ_prec_ft(size_t lds)
+{
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gemm_kernel<PREC, FT, false>, NT, lds) !=
+        hipSuccess)
+        return 1;
+    return nb > 0 ? nb : 1;
+}
+
+}  // namespace
+
+size_t gemm_lds_bytes(int prec, int ft, int n_dst, int slab, int L)
+{
+    const size_t xs = (size_t)slab * 2 * (prec == SST_GEMM_F16X3 ? 2 : 1);
+    return (size_t)ft * n_dst * 8 + xs + 4 * (size_t)((L + 3) & ~3) + 4 * (size_t)ft + 16;
+}
+
+hipError_t launch_gemm_forward(int prec, int ft, bool debug, const GemmArgs &a, int grid,
+                               hipStream_t s)
+{
+    if (prec == SST_GEMM_BF16)
+        return ft == 64 ? launch_prec_ft<SST_GEMM_BF16, 64>(debug, a, grid, s)
+                        : launch_prec_ft<SST_GEMM_BF16, 32>(debug, a, grid, s);
+    return ft == 64 ? launch_prec_ft<SST_GEMM_F16X3, 64>(debug, a, grid, s)
+                    : launch_prec_ft<SST_GEMM_F16X3, 32>(debug, a, grid, s);
+}
+
+int gemm_occupancy(int prec, int ft, size_t lds)
+{
+    if (prec == SST_GEMM_BF16)
+        return ft == 64 ? occ_prec_ft<SST_GEMM_BF16, 64>(lds) : occ_prec_ft<SST_GEMM_BF16, 32>(lds);
+    return ft == 64 ? occ_prec_ft<SST_GEMM_F16X3, 64>(lds) : occ_prec_ft<SST_GEMM_F16X3, 32>(lds);
+}
+
+}  // namespace sst

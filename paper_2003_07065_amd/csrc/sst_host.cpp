@@ -55,6 +55,10 @@ struct sst_plan_s {
     double s_pack = 1.0;
     double g0 = 0.0;
     int G = 0, lo_bits = 0, n_lo = 0, n_hi = 0;
+    // DFT-as-GEMM tier
+    int gemm_ft = 0, row_tiles = 0, ksteps = 0, slab = 0;
+    float unscale_g = 1.f, unscale_gd = 1.f;
+    size_t off_afrag = 0, off_afrag_lo = 0, afrag_bytes = 0;
     // workspace layout (bytes): control block, descriptor slot, tables
     size_t off_desc = 0, off_idesc = 0, off_win = 0, off_twid = 0, off_phlo = 0, off_phhi = 0;
     size_t tables_end = 0, ws_bytes = 0;
@@ -101,8 +105,11 @@ sst_status validate(const sst_params *p)
         return fail(SST_E_ARG, "thr_mode must be SST_THR_ABS or SST_THR_REL_MAX");
     if (!(p->thr >= 0.0) || !std::isfinite(p->thr))
         return fail(SST_E_ARG, "thr must be finite and >= 0");
-    if (p->precision != SST_PREC_FP32_FFT)
-        return fail(SST_E_UNSUPPORTED, "only SST_PREC_FP32_FFT is built");
+    if (p->precision != SST_PREC_FP32_FFT && p->precision != SST_PREC_GEMM_BF16 &&
+        p->precision != SST_PREC_GEMM_F16X3)
+        return fail(SST_E_ARG, "unknown precision");
+    if (p->precision != SST_PREC_FP32_FFT && (p->nfft > 2048 || (p->hop % 8) != 0))
+        return fail(SST_E_UNSUPPORTED, "the GEMM tiers need nfft <= 2048 and hop a multiple of 8");
     if (p->flags != 0)
         return fail(SST_E_ARG, "params.flags must be 0");
     return SST_OK;
@@ -207,6 +214,79 @@ sst::InvLaunch inv_launch(const sst::InvDesc *dev, int n_ch, int64_t blk_begin, 
     return l;
 }
 
+// Round to BF16, nearest even.
+uint16_t to_bf16(float f)
+{
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+uint16_t f16_bits(_Float16 h)
+{
+    uint16_t u;
+    std::memcpy(&u, &h, 2);
+    return u;
+}
+
+// A fragments of the DFT-as-GEMM tier: row r = 4 b + p (source bin k1 + b;
+// p = Re S, Im S, Re S', Im S'), column j = tap (t = j - M), value
+// w[t] e^{-i 2 pi ((k t) mod N_f) / N_f} with w = g (p < 2) or g' (p >= 2),
+// computed in float64 and stored in the order the 32x32x16 MFMA reads them:
+// fragment (row tile, k step, lane) holds row 32 rt + lane mod 32, taps
+// 16 ks + 8 (lane / 32) .. +7.  The FP16 split scales the g rows and the g'
+// rows by powers of two that bring their largest magnitude into [2^13, 2^14).
+void build_afrag(sst_plan_s *pl, const std::vector<double> &g, const std::vector<double> &gd)
+{
+    const int L = pl->p.win_len, NF = pl->p.nfft, M = pl->M;
+    const bool split = pl->p.precision == SST_PREC_GEMM_F16X3;
+    double mg = 0.0, mgd = 0.0;
+    for (int j = 0; j < L; ++j) {
+        mg = std::max(mg, std::fabs(g[j]));
+        mgd = std::max(mgd, std::fabs(gd[j]));
+    }
+    auto pow2_scale = [](double m) {
+        int e = 0;
+        std::frexp(m, &e);   // m < 2^e
+        return m > 0.0 ? 14 - e : 0;
+    };
+    const int sg = split ? pow2_scale(mg) : 0, sgd = split ? pow2_scale(mgd) : 0;
+    pl->unscale_g = (float)std::ldexp(1.0, -sg);
+    pl->unscale_gd = (float)std::ldexp(1.0, -sgd);
+    uint16_t *hi = reinterpret_cast<uint16_t *>(pl->blob.data() + (pl->off_afrag - pl->off_win));
+    uint16_t *lo = split ? reinterpret_cast<uint16_t *>(pl->blob.data() +
+                                                        (pl->off_afrag_lo - pl->off_win))
+                         : nullptr;
+    for (int rt = 0; rt < pl->row_tiles; ++rt)
+        for (int ks = 0; ks < pl->ksteps; ++ks)
+            for (int lane = 0; lane < 64; ++lane)
+                for (int e = 0; e < 8; ++e) {
+                    const int r = rt * 32 + (lane & 31);
+                    const int j = ks * 16 + 8 * (lane >> 5) + e;
+                    double v = 0.0;
+                    if (r < 4 * pl->n_src && j < L) {
+                        const int b = r / 4, part = r % 4;
+                        const int64_t k = pl->k1 + b, t = j - M;
+                        int64_t rr = (k * t) % NF;
+                        if (rr < 0)
+                            rr += NF;
+                        const double ang = kTwoPi * (double)rr / NF;
+                        const double w = part < 2 ? g[j] : gd[j];
+                        v = (part % 2 == 0) ? w * std::cos(ang) : -w * std::sin(ang);
+                        v = std::ldexp(v, part < 2 ? sg : sgd);
+                    }
+                    const size_t o = (((size_t)rt * pl->ksteps + ks) * 64 + lane) * 8 + e;
+                    if (split) {
+                        const _Float16 h = (_Float16)v;
+                        hi[o] = f16_bits(h);
+                        lo[o] = f16_bits((_Float16)(v - (double)h));
+                    } else {
+                        hi[o] = to_bf16((float)v);
+                    }
+                }
+}
+
 }  // namespace
 
 extern "C" {
@@ -299,6 +379,31 @@ sst_status sst_plan(const sst_params *params, sst_plan_t *out)
     off = align_up(off + sizeof(float) * 2 * (size_t)pl->n_lo);
     pl->off_phhi = off;
     off = align_up(off + sizeof(float) * 2 * (size_t)pl->n_hi);
+    const bool gemm = p.precision != SST_PREC_FP32_FFT;
+    if (gemm) {
+        pl->row_tiles = (4 * pl->n_src + 31) / 32;
+        pl->ksteps = (L + 15) / 16;
+        for (int ft : {64, 32}) {
+            const int slab = ((ft - 1) * p.hop + 16 * pl->ksteps + 7) / 8 * 8;
+            if (sst::gemm_lds_bytes(p.precision, ft, pl->n_dst, slab, L) <= 80 * 1024) {
+                pl->gemm_ft = ft;
+                pl->slab = slab;
+                break;
+            }
+        }
+        if (!pl->gemm_ft) {
+            delete pl;
+            return fail(SST_E_UNSUPPORTED, "the GEMM tiers need 32 * n_dst * 8 bytes of LDS "
+                                           "histogram plus the sample slab within 80 KiB");
+        }
+        pl->afrag_bytes = (size_t)pl->row_tiles * pl->ksteps * 64 * 16;
+        pl->off_afrag = off;
+        off = align_up(off + pl->afrag_bytes);
+        if (p.precision == SST_PREC_GEMM_F16X3) {
+            pl->off_afrag_lo = off;
+            off = align_up(off + pl->afrag_bytes);
+        }
+    }
     pl->tables_end = off;
     pl->ws_bytes = off;
 
@@ -327,6 +432,8 @@ sst_status sst_plan(const sst_params *params, sst_plan_t *out)
         const double a = kTwoPi * (double)((int64_t)h << pl->lo_bits) / pl->G;
         put(pl->off_phhi, h, std::cos(a), std::sin(a));
     }
+    if (gemm)
+        build_afrag(pl, g, gd);
     *out = pl;
     return SST_OK;
 }
@@ -384,6 +491,10 @@ sst_status sst_plan_bind(sst_plan_t pl, void *workspace, size_t bytes, void *str
     pl->device = dev;
     pl->cus = cus;
     pl->fwd_grid_cap = cus * sst::fwd_occupancy(pl->p.nfft, pl->p.win_len);
+    if (pl->gemm_ft)
+        pl->fwd_grid_cap = cus * sst::gemm_occupancy(
+            pl->p.precision, pl->gemm_ft,
+            sst::gemm_lds_bytes(pl->p.precision, pl->gemm_ft, pl->n_dst, pl->slab, pl->p.win_len));
     pl->max_grid_cap = cus * sst::max_occupancy(pl->p.nfft, pl->p.win_len);
     return SST_OK;
 }
@@ -435,6 +546,46 @@ sst_status sst_forward(sst_plan_t pl, const float *x, int64_t frame0, int64_t nf
     }
     if (nframes == 0)
         return SST_OK;
+    if (pl->gemm_ft) {
+        if (aux && aux->colstats)
+            return fail(SST_E_UNSUPPORTED, "colstats are not produced by the GEMM tiers");
+        sst::GemmArgs ga{};
+        ga.x = x;
+        ga.n = pl->p.n_samples;
+        ga.frame0 = frame0;
+        ga.nframes = nframes;
+        ga.afrag = pl->ws + pl->off_afrag;
+        ga.afrag_lo = pl->off_afrag_lo ? pl->ws + pl->off_afrag_lo : nullptr;
+        ga.win = reinterpret_cast<const float2 *>(pl->ws + pl->off_win);
+        ga.ctrl = ctrl;
+        ga.T = reinterpret_cast<float2 *>(T);
+        if (aux) {
+            ga.S = reinterpret_cast<float2 *>(aux->S);
+            ga.Sd = reinterpret_cast<float2 *>(aux->Sd);
+            ga.idx = aux->idx;
+        }
+        ga.L = pl->p.win_len;
+        ga.M = pl->M;
+        ga.hop = pl->p.hop;
+        ga.k1 = pl->k1;
+        ga.n_src = pl->n_src;
+        ga.n_dst = pl->n_dst;
+        ga.z = pl->p.subdiv;
+        ga.row_tiles = pl->row_tiles;
+        ga.ksteps = pl->ksteps;
+        ga.slab = pl->slab;
+        ga.unscale_g = pl->unscale_g;
+        ga.unscale_gd = pl->unscale_gd;
+        ga.cdelta = (float)(pl->p.nfft / kTwoPi);
+        ga.bound_c = (float)(1.1 * std::sqrt(2.0 * pl->n_src * pl->p.nfft));
+        const int64_t tiles = (nframes + pl->gemm_ft - 1) / pl->gemm_ft;
+        const int grid = (int)(tiles < pl->fwd_grid_cap ? tiles : pl->fwd_grid_cap);
+        const bool dbg = aux && (aux->S || aux->Sd || aux->idx);
+        e = sst::launch_gemm_forward(pl->p.precision, pl->gemm_ft, dbg, ga, grid, s);
+        if (e != hipSuccess)
+            return hip_fail(e, "GEMM forward launch");
+        return SST_OK;
+    }
     g.item_begin = 0;
     g.item_stop = d.item_end;
     const bool debug = aux && (aux->S || aux->Sd || aux->idx || aux->colstats);
@@ -607,6 +758,11 @@ sst_status sst_batch_plan(const sst_params *params, int32_t n_channels, sst_batc
     }
     size_t off = 0;
     for (int c = 0; c < n_channels; ++c) {
+        if (params[c].precision != SST_PREC_FP32_FFT) {
+            delete b;
+            return fail(SST_E_UNSUPPORTED, "channel " + std::to_string(c) +
+                                               ": the batched calls run the FP32 FFT tier only");
+        }
         sst_status st = sst_plan(&params[c], &b->plans[(size_t)c]);
         if (st != SST_OK) {
             g_err = "channel " + std::to_string(c) + ": " + g_err;

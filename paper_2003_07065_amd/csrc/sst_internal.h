@@ -93,6 +93,33 @@ struct InvLaunch {
     int max_w;              // largest 2 hw + 1 in the list
 };
 
+// Precision tiers of the DFT-as-GEMM forward (values of sst_params.precision).
+constexpr int SST_GEMM_BF16 = 1;
+constexpr int SST_GEMM_F16X3 = 2;
+
+// Arguments of the DFT-as-GEMM forward kernel.
+struct GemmArgs {
+    const float *x;
+    int64_t n;
+    int64_t frame0, nframes;
+    const void *afrag;      // [row_tiles][ksteps][64] 16-byte A fragments (BF16, or FP16 hi)
+    const void *afrag_lo;   // FP16 lo fragments (F16X3)
+    const float2 *win;      // [L]: .x = g[j]
+    const Ctrl *ctrl;       // gamma2
+    float2 *T;              // [nframes][n_dst]
+    float2 *S;              // optional [nframes][n_src]
+    float2 *Sd;             // optional [nframes][n_src]
+    int32_t *idx;           // optional [nframes][n_src]
+    int L, M, hop, k1, n_src, n_dst, z;
+    int row_tiles;          // ceil(4 n_src / 32)
+    int ksteps;             // K / 16, K = L rounded up to 16
+    int slab;               // staged samples per tile: (FT - 1) hop + K
+    float unscale_g;        // 2^-s of the g rows (FP16 split), else 1
+    float unscale_gd;       // same for the g' rows
+    float cdelta;           // N_f / (2 pi)
+    float bound_c;          // 1.1 sqrt(2 n_src N_f)
+};
+
 // Arguments of the ridge kernel.
 struct RidgeArgs {
     const float2 *T;
@@ -111,6 +138,11 @@ hipError_t launch_threshold(int nfft, int L, const GroupLaunch &g, int grid, hip
 // max_n_src / max_n_dst / max_L bound the launch's channels.
 hipError_t launch_forward(int nfft, int max_L, int max_n_src, int max_n_dst, bool debug,
                           const GroupLaunch &g, int grid, hipStream_t s);
+// DFT-as-GEMM forward (FT frames per tile: 32 or 64).
+hipError_t launch_gemm_forward(int prec, int ft, bool debug, const GemmArgs &a, int grid,
+                               hipStream_t s);
+size_t gemm_lds_bytes(int prec, int ft, int n_dst, int slab, int L);
+int gemm_occupancy(int prec, int ft, size_t lds);
 // Copy one descriptor into device memory (a kernel, so it can be captured).
 hipError_t launch_put_desc(const ChanDesc &d, ChanDesc *dst, hipStream_t s);
 // Inverse of the launch list (blocks = ch[n_ch-1].blk_end - blk_begin).

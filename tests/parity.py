@@ -70,8 +70,13 @@ class IndexReport:
         return self.unexplained == 0
 
 
-def classify_indices(idx_g, idx_o, frac_o, S_o, Sd_o, gamma_o, nfft, z, s_pack, ny, n_dst=None):
+def classify_indices(idx_g, idx_o, frac_o, S_o, Sd_o, gamma_o, nfft, z, s_pack, ny, n_dst=None,
+                     err_s=None, err_sd=None):
     """Compare destination indices (see module doc).  ny[m] = ||y_m|| per frame.
+
+    err_s / err_sd (per frame) replace the FP32 FFT error model (2^-24 ||y_m||
+    for S, 2^-24 ||y_m|| / s for S') by the caller's bound on the absolute error
+    of S and S' (used for the matrix-core tiers).
 
     A GPU destination l is accepted for oracle position u when
     |l - u| <= 1/2 + tol (tol = max(1e-4, 8 e_u)): l is a bin that u rounds to
@@ -91,8 +96,13 @@ def classify_indices(idx_g, idx_o, frac_o, S_o, Sd_o, gamma_o, nfft, z, s_pack, 
     u = frac_o
     with np.errstate(invalid="ignore", divide="ignore"):
         dist = np.abs((u + 0.5) - np.round(u + 0.5))
-        e_u = (z * nfft / (2 * math.pi)) * 2.0 ** -24 * ny[:, None] * (
-            1.0 / (s_pack * mag) + np.abs(Sd_o) / (mag * mag))
+        if err_s is not None:
+            e_u = (z * nfft / (2 * math.pi)) * (
+                np.asarray(err_sd)[:, None] / mag
+                + np.abs(Sd_o) * np.asarray(err_s)[:, None] / (mag * mag))
+        else:
+            e_u = (z * nfft / (2 * math.pi)) * 2.0 ** -24 * ny[:, None] * (
+                1.0 / (s_pack * mag) + np.abs(Sd_o) / (mag * mag))
     tol = np.maximum(1e-4, 8.0 * e_u)
     flip = diff & both
     gi = idx_g.astype(np.float64)

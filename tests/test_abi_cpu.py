@@ -209,3 +209,31 @@ def test_batch_refuses_work_before_bind_and_commit():
                                   None, None, ctypes.c_void_p(16)) == sst.SST_E_ARG
     finally:
         L.sst_batch_destroy(h)
+
+
+def test_gemm_precision_validation():
+    L = sst.lib()
+    h = ctypes.c_void_p()
+    keep = []
+    ok = sst._params(1 << 15, 25600.0, 511, 64.0, 8, 512, 0.0, 6400.0, 1, "rel", 1e-3, None, None,
+                     keep, "bf16")
+    assert L.sst_plan(ctypes.byref(ok), ctypes.byref(h)) == sst.SST_OK
+    L.sst_destroy(h)
+    bad_hop = sst._params(1 << 15, 25600.0, 511, 64.0, 6, 512, 0.0, 6400.0, 1, "rel", 1e-3, None,
+                          None, keep, "f16x3")
+    assert L.sst_plan(ctypes.byref(bad_hop), ctypes.byref(h)) == sst.SST_E_UNSUPPORTED
+    big = sst._params(1 << 15, 25600.0, 511, 64.0, 8, 4096, 0.0, 6400.0, 1, "rel", 1e-3, None,
+                      None, keep, "bf16")
+    assert L.sst_plan(ctypes.byref(big), ctypes.byref(h)) == sst.SST_E_UNSUPPORTED
+    unknown = sst._params(1 << 15, 25600.0, 511, 64.0, 8, 512, 0.0, 6400.0, 1, "rel", 1e-3, None,
+                          None, keep)
+    unknown.precision = 7
+    assert L.sst_plan(ctypes.byref(unknown), ctypes.byref(h)) == sst.SST_E_ARG
+    # the batched calls run the FP32 FFT tier only
+    arr = (sst.Params * 1)()
+    arr[0] = ok
+    assert L.sst_batch_plan(arr, 1, ctypes.byref(h)) == sst.SST_E_UNSUPPORTED
+    # a histogram row that cannot fit 32 frames of LDS is refused at plan time
+    wide = sst._params(1 << 15, 25600.0, 1023, 128.0, 8, 2048, 0.0, 12800.0, 4, "rel", 1e-3, None,
+                       None, keep, "bf16")
+    assert L.sst_plan(ctypes.byref(wide), ctypes.byref(h)) == sst.SST_E_UNSUPPORTED

@@ -1,0 +1,124 @@
+"""GPU: the DFT-as-GEMM precision tiers (BF16, FP16 hi/lo x3 on the matrix
+cores) against the float64 oracle and against the FP32 FFT path, on c5-shaped
+inputs (N_f 512 / 1024, L = N_f - 1, sigma = N_f / 8, H = 8, band [0, 6.4 kHz],
+z = 1) and on a band with k1 > 0 and z = 2.
+
+Reported for every tier: relative Frobenius error of S, S' and T (T against
+the oracle's coefficients re-scattered with the GPU's index decisions, and
+raw), literal index mismatches, and the inverse SNR against the oracle's.
+Bars: the FP16 x3 tier meets the FP32 bars (relF <= 1e-5, index flips only
+within the per-coefficient error bound of its arithmetic, SNR within 0.1 dB);
+the BF16 tier has 8-bit significands, so S is only good to about 2^-8
+relative per product: relF <= 1e-2, SNR within 1 dB, indices reported."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from tests.parity import classify_indices, reconciled_T, relf
+from workloads import SSTConfig, make_c5, ridge_bins
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def sst():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_2003_07065_amd as m
+    m.lib()
+    return m
+
+
+def _workloads():
+    out = []
+    for nfft in (512, 1024):
+        w = make_c5(n_channels=1, n=1 << 15, nfft=nfft)[0]
+        out.append((f"c5-{nfft}", w))
+    w = make_c5(n_channels=1, n=20000, nfft=512)[0]
+    w.cfg = SSTConfig(25600.0, 255, 32.0, 16, 512, 1000.0, 6000.0, 2, "rel", 1e-3, 2)
+    out.append(("nf512-z2-k1", w))
+    return out
+
+
+WL = _workloads()
+
+
+def _l1_norms(x, w, hop, frames):
+    """sum_j |x[mH + j] w[j]| per frame (the scale of a dot product's rounding error)."""
+    L = w.shape[0]
+    M = (L - 1) // 2
+    xp = np.concatenate([np.zeros(M), x.astype(np.float64), np.zeros(M + hop)])
+    return np.array([np.sum(np.abs(xp[m * hop: m * hop + L] * w)) for m in frames])
+
+
+@pytest.mark.parametrize("prec", ["f16x3", "bf16"])
+@pytest.mark.parametrize("name,w", WL, ids=[n for n, _ in WL])
+def test_gemm_tier_against_oracle(sst, name, w, prec):
+    cfg = w.cfg
+    x = w.x
+    plan = sst.Plan.from_config(w.n, cfg, device="cuda", precision=prec)
+    xg = torch.from_numpy(x).cuda()
+    nfr = plan.n_frames
+    S = torch.empty((nfr, plan.n_src), dtype=torch.complex64, device="cuda")
+    Sd = torch.empty_like(S)
+    idx = torch.empty((nfr, plan.n_src), dtype=torch.int32, device="cuda")
+    gam = torch.empty(1, dtype=torch.float32, device="cuda")
+    T = plan.forward(xg, S=S, Sd=Sd, idx=idx, gamma=gam)
+    fft = sst.Plan.from_config(w.n, cfg, device="cuda")
+    T32 = fft.forward(xg)
+    torch.cuda.synchronize()
+    o = oracle.forward(x.astype(np.float64), cfg)
+    assert abs(float(gam.cpu()[0]) - o.gamma) <= 1e-5 * o.gamma
+    S_g, Sd_g, idx_g, T_g = S.cpu().numpy(), Sd.cpu().numpy(), idx.cpu().numpy(), T.cpu().numpy()
+    e_s, e_sd = relf(S_g, o.S), relf(Sd_g, o.Sd)
+    e_t = relf(T_g, reconciled_T(o.S, idx_g, plan.n_dst))
+    e_raw, e_32 = relf(T_g, o.T), relf(T_g, T32.cpu().numpy())
+    # index bound of this arithmetic: S and S' move by u * sum_j |x w| per frame
+    u = 2.0 ** -21 if prec == "f16x3" else 2.0 ** -7
+    frames = np.arange(nfr)
+    err_s = u * _l1_norms(x, o.g, cfg.hop, frames)
+    err_sd = u * _l1_norms(x, o.gd, cfg.hop, frames)
+    rep, _ = classify_indices(idx_g, o.idx, o.frac, o.S, o.Sd, o.gamma, cfg.nfft, cfg.subdiv,
+                              1.0, None, plan.n_dst, err_s=err_s, err_sd=err_sd)
+    # inverse with the true ridges, against the oracle's pipeline
+    ridge = ridge_bins(w.inst_freq(w.frame_times()), cfg.fs, cfg.nfft, plan.k1, cfg.subdiv,
+                       plan.n_dst)
+    xh = plan.inverse(T, torch.from_numpy(ridge).cuda(), cfg.hw).cpu().numpy()
+    M = (cfg.win_len - 1) // 2
+    d_snr = []
+    for q in range(ridge.shape[0]):
+        xo = oracle.inverse(o.T, ridge[q], cfg.hw, o.g, cfg.hop, cfg.nfft, o.band.k1, cfg.subdiv,
+                            w.n)
+        ref = w.comps[q][M:w.n - M].astype(np.float64)
+        s_g = 10 * math.log10(np.sum(ref ** 2) / np.sum((ref - xh[q][M:w.n - M]) ** 2))
+        s_o = 10 * math.log10(np.sum(ref ** 2) / np.sum((ref - xo[M:w.n - M]) ** 2))
+        d_snr.append(s_g - s_o)
+    _say(f"[gemm {prec}] {name}: relF S={e_s:.2e} S'={e_sd:.2e} T(reconciled)={e_t:.2e} "
+         f"T(raw)={e_raw:.2e} T-vs-FP32-FFT={e_32:.2e} dSNR={['%.3f' % d for d in d_snr]} {rep}")
+    if prec == "f16x3":
+        assert e_s <= 1e-5 and e_sd <= 1e-5 and e_t <= 1e-5
+        assert rep.ok(), (rep, rep.details)
+        assert max(abs(d) for d in d_snr) <= 0.1
+    else:
+        assert e_s <= 1e-2 and e_sd <= 1e-2 and e_t <= 1e-2
+        assert max(abs(d) for d in d_snr) <= 1.0
+
+
+@pytest.mark.parametrize("prec", ["f16x3", "bf16"])
+def test_gemm_tier_is_reproducible(sst, prec):
+    name, w = WL[0]
+    plan = sst.Plan.from_config(w.n, w.cfg, device="cuda", precision=prec)
+    xg = torch.from_numpy(w.x).cuda()
+    T1 = plan.forward(xg)
+    T2 = plan.forward(xg, reuse_gamma=True)
+    torch.cuda.synchronize()
+    assert torch.equal(torch.view_as_real(T1), torch.view_as_real(T2))
