@@ -204,13 +204,115 @@ def run_c4(args):
     print(json.dumps(out), flush=True)
 
 
+def run_c5(args):
+    """Precision tier (c5): many equal-length channels, STFT + SST forward in the
+    FP32 FFT path and as DFT-as-GEMM on the matrix cores (BF16, FP16 hi/lo x3);
+    speedup of each tier over the FP32 FFT path and its error on channel 0."""
+    import numpy as np
+    import torch
+    import paper_2003_07065_amd as sst
+    from workloads import make_c5, ridge_bins
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    n = 1 << 20
+    nch = args.c5_channels
+    t0 = time.perf_counter()
+    xs, w0 = [], None
+    for c0 in range(0, nch, 32):
+        chunk = make_c5(n_channels=min(32, nch - c0), n=n, nfft=args.c5_nfft, seed=c0)
+        if w0 is None:
+            w0 = chunk[0]
+        for w in chunk:
+            xs.append(torch.from_numpy(w.x).to(dev))
+            if w is not w0:
+                w.comps = None
+    gen_s = time.perf_counter() - t0
+    cfg = w0.cfg
+    stream = torch.cuda.current_stream(dev)
+    res = {}
+    T0 = {}
+    for prec in ("fp32", "bf16", "f16x3"):
+        plan = sst.Plan.from_config(n, cfg, device=dev, precision=prec)
+        T = torch.empty((plan.n_frames, plan.n_dst), dtype=torch.complex64, device=dev)
+
+        def step(reuse=False):
+            for x in xs:
+                plan.forward(x, T, reuse_gamma=reuse)
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        e[0].record(stream)
+        for _ in range(args.steps):
+            step()
+        e[1].record(stream)
+        for _ in range(args.steps):
+            step(reuse=True)
+        e[2].record(stream)
+        torch.cuda.synchronize()
+        full_ms = e[0].elapsed_time(e[1]) / args.steps
+        fwd_ms = e[1].elapsed_time(e[2]) / args.steps
+        # error of the tier on channel 0: T against the FP32 FFT path, inverse SNR
+        plan.forward(xs[0], T)
+        ridge = ridge_bins(w0.inst_freq(w0.frame_times()), cfg.fs, cfg.nfft, plan.k1,
+                           cfg.subdiv, plan.n_dst)
+        xh = plan.inverse(T, torch.from_numpy(ridge).to(dev), cfg.hw).cpu().numpy()
+        torch.cuda.synchronize()
+        T0[prec] = T.cpu().numpy()
+        M = (cfg.win_len - 1) // 2
+        snr = []
+        for q in range(ridge.shape[0]):
+            ref = w0.comps[q][M:n - M].astype(np.float64)
+            snr.append(round(10 * math.log10(np.sum(ref ** 2)
+                                             / np.sum((ref - xh[q][M:n - M]) ** 2)), 3))
+        flops = None
+        if prec != "fp32":
+            products = 3 if prec == "f16x3" else 1
+            flops = 2.0 * 4 * plan.n_src * cfg.win_len * plan.n_frames * nch * products
+        res[prec] = {"ms_with_threshold": round(full_ms, 3), "forward_ms": round(fwd_ms, 3),
+                     "Msamples_per_s": round(n * nch / (full_ms / 1e3) / 1e6, 1),
+                     "snr_db_channel0": snr,
+                     "mfma_tflops": (round(flops / (fwd_ms / 1e3) / 1e12, 1) if flops else None)}
+        del plan, T
+    base = res["fp32"]["ms_with_threshold"]
+    for prec in ("bf16", "f16x3"):
+        res[prec]["speedup_vs_fp32_fft"] = round(base / res[prec]["ms_with_threshold"], 3)
+        res[prec]["forward_speedup_vs_fp32_fft"] = round(res["fp32"]["forward_ms"]
+                                                         / res[prec]["forward_ms"], 3)
+        d = T0[prec] - T0["fp32"]
+        res[prec]["T_relF_vs_fp32_fft"] = float(np.linalg.norm(d) / np.linalg.norm(T0["fp32"]))
+    peak = 2500.0
+    best = res["f16x3"]
+    out = {
+        "metric": METRIC, "value": best["Msamples_per_s"], "unit": "Msamples/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": best["ms_with_threshold"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f16x3",
+        "data": "synthetic",
+        "config": {"workload": f"precision tier: {nch} channels x 2^20 samples at 25.6 kHz, "
+                               f"three AM-FM components + noise 10 dB, N_f={args.c5_nfft}, "
+                               f"L=N_f-1, sigma=N_f/8, H=8, band [0, 6.4 kHz], z=1, "
+                               "rho=1e-3; STFT+SST forward (threshold pre-pass included)",
+                   "generation_s": round(gen_s, 1)},
+        "roofline": {"kernel": "gemm_kernel (FP16 hi/lo x3, 32x32x16 MFMA)", "bound": "mfma",
+                     "achieved": best["mfma_tflops"], "peak": peak, "unit": "TFLOP/s",
+                     "frac": round(best["mfma_tflops"] / peak, 4), "traffic": None},
+        "tiers": res,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", choices=["c2", "c4"], default="c2",
-                    help="c2: one long channel (default); c4: batched uneven channels")
+    ap.add_argument("--workload", choices=["c2", "c4", "c5"], default="c2",
+                    help="c2: one long channel (default); c4: batched uneven channels; "
+                         "c5: precision tiers")
+    ap.add_argument("--c5-channels", type=int, default=512)
+    ap.add_argument("--c5-nfft", type=int, default=512, choices=[512, 1024])
     ap.add_argument("--c4-channels", type=int, default=256)
     ap.add_argument("--t-pool-gb", type=float, default=120.0,
                     help="c4: device memory for T; channels are processed in passes that fit")
@@ -236,6 +338,9 @@ def main():
         sys.exit(2)
     if args.workload == "c4":
         run_c4(args)
+        return
+    if args.workload == "c5":
+        run_c5(args)
         return
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)

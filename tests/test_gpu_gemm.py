@@ -8,8 +8,9 @@ the oracle's coefficients re-scattered with the GPU's index decisions, and
 raw), literal index mismatches, and the inverse SNR against the oracle's.
 Bars: the FP16 x3 tier meets the FP32 bars (relF <= 1e-5, index flips only
 within the per-coefficient error bound of its arithmetic, SNR within 0.1 dB);
-the BF16 tier has 8-bit significands, so S is only good to about 2^-8
-relative per product: relF <= 1e-2, SNR within 1 dB, indices reported."""
+the BF16 tier has 8-bit significands, so each product of two rounded operands
+is only good to about 2^-7 relative: relF <= 1e-2, SNR within 1 dB, indices
+reported."""
 import math
 import sys
 
