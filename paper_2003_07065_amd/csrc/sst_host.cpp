@@ -61,6 +61,7 @@ struct sst_plan_s {
     size_t off_afrag = 0, off_afrag_lo = 0, afrag_bytes = 0;
     // workspace layout (bytes): control block, descriptor slot, tables
     size_t off_desc = 0, off_idesc = 0, off_win = 0, off_twid = 0, off_phlo = 0, off_phhi = 0;
+    size_t off_den = 0;
     size_t tables_end = 0, ws_bytes = 0;
     std::vector<unsigned char> blob;   // host image of [off_win, tables_end)
     // bound state
@@ -162,6 +163,7 @@ sst::InvDesc inv_desc(const sst_plan_s *pl, const float *T, int64_t frame0, int6
     a.win = reinterpret_cast<const float2 *>(pl->ws + pl->off_win);
     a.ph_lo = reinterpret_cast<const float2 *>(pl->ws + pl->off_phlo);
     a.ph_hi = reinterpret_cast<const float2 *>(pl->ws + pl->off_phhi);
+    a.den = reinterpret_cast<const float *>(pl->ws + pl->off_den);
     a.n = pl->p.n_samples;
     a.n_frames = pl->n_frames;
     a.frame0 = frame0;
@@ -194,23 +196,29 @@ sst::InvDesc inv_desc(const sst_plan_s *pl, const float *T, int64_t frame0, int6
         a.span_lo = lo;
         a.span_len = hi >= lo ? hi - lo + 1 : 0;
     }
-    a.tiles = (a.span_len + 255) / 256;
+    a.tiles = (a.span_len + sst::kInvTileSamples - 1) / sst::kInvTileSamples;
     a.blk0 = 0;
     a.blk_end = (int64_t)n_comp * a.tiles;
     return a;
 }
 
-sst::InvLaunch inv_launch(const sst::InvDesc *dev, int n_ch, int64_t blk_begin, int max_w,
-                          int max_tab)
+// Frames of one call that a tile of output samples can meet (even).
+int inv_max_k(const sst_plan_s *pl)
+{
+    const int k = (sst::kInvTileSamples - 1 + 2 * pl->M) / pl->p.hop + 2;
+    return (k + 1) & ~1;
+}
+
+sst::InvLaunch inv_launch(const sst::InvDesc *dev, int n_ch, int64_t blk_begin, int max_k,
+                          int max_tab, int max_L)
 {
     sst::InvLaunch l{};
     l.ch = dev;
     l.n_ch = n_ch;
     l.blk_begin = blk_begin;
-    l.max_w = max_w;
+    l.max_k = max_k;
     l.max_tab = max_tab;
-    const int fb = 2048 / max_w;
-    l.fb = fb < 1 ? 1 : (fb > 128 ? 128 : fb);
+    l.max_L = (max_L + 3) & ~3;
     return l;
 }
 
@@ -379,6 +387,8 @@ sst_status sst_plan(const sst_params *params, sst_plan_t *out)
     off = align_up(off + sizeof(float) * 2 * (size_t)pl->n_lo);
     pl->off_phhi = off;
     off = align_up(off + sizeof(float) * 2 * (size_t)pl->n_hi);
+    pl->off_den = off;
+    off = align_up(off + sizeof(float) * (size_t)p.hop);
     const bool gemm = p.precision != SST_PREC_FP32_FFT;
     if (gemm) {
         pl->row_tiles = (4 * pl->n_src + 31) / 32;
@@ -431,6 +441,16 @@ sst_status sst_plan(const sst_params *params, sst_plan_t *out)
     for (int h = 0; h < pl->n_hi; ++h) {
         const double a = kTwoPi * (double)((int64_t)h << pl->lo_bits) / pl->G;
         put(pl->off_phhi, h, std::cos(a), std::sin(a));
+    }
+    {   // interior OLA denominators (Eq. 26): g[0] sum of g[j] over j = r mod H, |j| <= M
+        float *den = reinterpret_cast<float *>(pl->blob.data() + (pl->off_den - pl->off_win));
+        for (int r = 0; r < p.hop; ++r) {
+            double acc = 0.0;
+            for (int j = -pl->M; j <= pl->M; ++j)
+                if ((((j % p.hop) + p.hop) % p.hop) == r)
+                    acc += g[j + pl->M];
+            den[r] = (float)(pl->g0 * acc);
+        }
     }
     if (gemm)
         build_afrag(pl, g, gd);
@@ -670,9 +690,11 @@ sst_status sst_inverse(sst_plan_t pl, const float *T, int64_t frame0, int64_t nf
     }
     if (a.span_len <= 0)
         return SST_OK;
-    sst::InvLaunch l = inv_launch(slot, 1, a.blk0, 2 * hw + 1, pl->n_lo + pl->n_hi);
+    sst::InvLaunch l = inv_launch(slot, 1, a.blk0, inv_max_k(pl), pl->n_lo + pl->n_hi,
+                                  pl->p.win_len);
     if (sst::inv_lds_bytes(l) > 64 * 1024)
-        return fail(SST_E_UNSUPPORTED, "inverse LDS tables exceed 64 KiB");
+        return fail(SST_E_UNSUPPORTED, "inverse tiles need more than 64 KiB of LDS "
+                                       "(window too long for the hop)");
     hipError_t e = sst::launch_put_inv_desc(a, slot, s);
     if (e == hipSuccess)
         e = sst::launch_inverse(l, a.blk_end - a.blk0, err != nullptr, s);
@@ -980,7 +1002,7 @@ sst_status sst_batch_inverse(sst_batch_t b, int32_t c_begin, int32_t c_end, void
         return fail(SST_E_STATE, "batch not bound or buffers not committed");
     if (c_begin < 0 || c_end > (int32_t)b->plans.size() || c_begin >= c_end)
         return fail(SST_E_ARG, "channel range empty or outside [0, n_channels)");
-    int max_w = 1, max_tab = 1;
+    int max_k = 2, max_tab = 1, max_L = 1;
     bool any_err = false;
     for (int c = c_begin; c < c_end; ++c) {
         const sst_batch_s::Io &o = b->io[(size_t)c];
@@ -989,15 +1011,17 @@ sst_status sst_batch_inverse(sst_batch_t b, int32_t c_begin, int32_t c_end, void
             return fail(SST_E_ARG, "channel " + std::to_string(c) + " has no T, ridge or xhat");
         if (pl->G > 65536)
             return fail(SST_E_UNSUPPORTED, "inverse needs subdiv * nfft <= 65536");
-        max_w = std::max(max_w, 2 * o.hw + 1);
+        max_k = std::max(max_k, inv_max_k(pl));
         max_tab = std::max(max_tab, pl->n_lo + pl->n_hi);
+        max_L = std::max(max_L, pl->p.win_len);
         any_err = any_err || o.err;
     }
     const sst::InvDesc *dev = reinterpret_cast<const sst::InvDesc *>(b->ws + b->off_idesc);
     sst::InvLaunch l = inv_launch(dev + c_begin, c_end - c_begin, b->idesc[(size_t)c_begin].blk0,
-                                  max_w, max_tab);
+                                  max_k, max_tab, max_L);
     if (sst::inv_lds_bytes(l) > 64 * 1024)
-        return fail(SST_E_UNSUPPORTED, "inverse LDS tables exceed 64 KiB");
+        return fail(SST_E_UNSUPPORTED, "inverse tiles need more than 64 KiB of LDS "
+                                       "(window too long for the hop)");
     const int64_t blocks = b->idesc[(size_t)c_end - 1].blk_end - l.blk_begin;
     hipError_t e = sst::launch_inverse(l, blocks, any_err, reinterpret_cast<hipStream_t>(stream));
     if (e != hipSuccess)

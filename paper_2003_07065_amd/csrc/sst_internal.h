@@ -65,6 +65,8 @@ struct InvDesc {
     const float2 *win;      // [L]; .x = g[j]
     const float2 *ph_lo;    // [1 << lo_bits]: exp(+i 2 pi r / G), r < 2^lo_bits
     const float2 *ph_hi;    // [G >> lo_bits]: exp(+i 2 pi (h << lo_bits) / G)
+    const float *den;       // [hop]: sum_m g[0] g[n - mH] for samples n = r mod hop whose
+                            // frames all exist
     int64_t n;              // signal length
     int64_t n_frames;       // all frames of the signal
     int64_t frame0, nframes;
@@ -87,11 +89,13 @@ struct InvDesc {
 struct InvLaunch {
     const InvDesc *ch;      // device array
     int n_ch;
-    int fb;                 // frames staged per LDS block (same for the launch)
+    int max_k;              // most frames one output tile meets
     int64_t blk_begin;      // ch[0].blk0
     int max_tab;            // LDS float2 entries of the largest phase tables in the list
-    int max_w;              // largest 2 hw + 1 in the list
+    int max_L;              // longest window in the list
 };
+
+constexpr int kInvTileSamples = 256;   // output samples per inverse workgroup
 
 // Precision tiers of the DFT-as-GEMM forward (values of sst_params.precision).
 constexpr int SST_GEMM_BF16 = 1;

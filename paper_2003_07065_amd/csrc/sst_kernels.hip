@@ -1050,6 +1050,33 @@ __device__ __forceinline__ int inv_chan_of(const CA InvDesc *ch, int n_ch, int64
     return lo;
 }
 
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// Inverse on the matrix cores.  For the output samples n of a tile and the
+// frames m of the call whose windows reach them, with d = l - d_lo (l the
+// destination bin, d_lo the lowest destination of the zones met) and
+// b = z k1 + l the bin on the zN_f grid,
+//   e^{i 2 pi b (n - mH)/G} = e^{i 2 pi b n / G} e^{-i 2 pi b m H / G},
+// so the numerator of Eq. 26 is
+//   sum_d Re( e^{i 2 pi b n / G} Z[d, n] ),
+//   Z[d, n] = sum_m c~[m, d] g[n - mH],  c~[m, d] = (a_l / N_f) T[m, l] e^{-i 2 pi b m H / G}
+// (zero outside the frame's zone).  Z is the product of the coefficient matrix
+// (16 bins x real/imaginary = 32 rows, frames) with the banded window matrix
+// (frames x samples), run on the 32x32x2 FP32 MFMA (FP32 products and sums,
+// as the vector path), frames in blocks of KB staged in LDS.  Each lane then
+// holds 16 of the 32 rows of one sample column: the sum over bins is 16
+// multiply-adds in registers and one exchange with the lane holding the other
+// 16 rows.  Phase indices are reduced mod G in integers.  Lane layout (checked
+// on the hardware): A lane l = row l mod 32, k = l / 32; B lane l = k l / 32,
+// column l mod 32; accumulator i = row 8 (i / 4) + 4 (l / 32) + i mod 4,
+// column l mod 32.
+//
+// Denominator: for samples whose frames all exist it depends on n mod H only
+// and comes from a table built on the host in float64; near the ends of the
+// signal it is summed here.
+constexpr int kInvTile = 256;   // output samples per workgroup (4 waves x 2 x 32)
+constexpr int kInvKB = 128;     // frames staged per block
+
 __global__ __launch_bounds__(256) void inv_kernel(InvLaunch l)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -1058,38 +1085,28 @@ __global__ __launch_bounds__(256) void inv_kernel(InvLaunch l)
     const CA InvDesc &a = chs[inv_chan_of(chs, l.n_ch, blk)];
     const int nlo = 1 << a.lo_bits;
     const int nhi = (a.G + nlo - 1) >> a.lo_bits;
-    const int W = 2 * a.hw + 1;
-    const int fb = l.fb;
     v2 *tlo = reinterpret_cast<v2 *>(smem);
     v2 *thi = tlo + nlo;
-    v2 *coef = tlo + l.max_tab;
-    int *rbase = reinterpret_cast<int *>(coef + fb * l.max_w);
+    float *gtab = reinterpret_cast<float *>(tlo + l.max_tab);   // [L]
+    int *rid = reinterpret_cast<int *>(gtab + l.max_L);         // [max_k]
+    float *bst = reinterpret_cast<float *>(rid + l.max_k);      // [kInvKB][32]
+    int *red = reinterpret_cast<int *>(bst + 32 * kInvKB);      // [2]
 
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = lane & 31, half = lane >> 5;
     const int64_t local = blk - a.blk0;
     const int q = (int)(local / a.tiles);
-    const int64_t tile_lo = a.span_lo + (local - (int64_t)q * a.tiles) * 256;
-    const int64_t tile_hi = (tile_lo + 255 < a.span_lo + a.span_len - 1) ? tile_lo + 255
-                                                                          : a.span_lo + a.span_len - 1;
-    const int64_t n = tile_lo + threadIdx.x;
-    const bool nvalid = n <= tile_hi;
+    const int64_t tile_lo = a.span_lo + (local - (int64_t)q * a.tiles) * kInvTile;
+    const int64_t span_end = a.span_lo + a.span_len - 1;
+    const int64_t tile_hi = tile_lo + kInvTile - 1 < span_end ? tile_lo + kInvTile - 1 : span_end;
     const v2 *__restrict__ win = reinterpret_cast<const v2 *>(a.win);
 
     for (int e = threadIdx.x; e < nlo; e += 256)
         tlo[e] = reinterpret_cast<const v2 *>(a.ph_lo)[e];
     for (int e = threadIdx.x; e < nhi; e += 256)
         thi[e] = reinterpret_cast<const v2 *>(a.ph_hi)[e];
-
-    // Denominator sum_m g[0] g[n - mH] over every frame of the signal.
-    float den = 0.f;
-    if (nvalid) {
-        const int64_t lo = n - a.M > 0 ? (n - a.M + a.hop - 1) / a.hop : 0;
-        int64_t hi = (n + a.M) / a.hop;
-        if (hi > a.n_frames - 1)
-            hi = a.n_frames - 1;
-        for (int64_t m = lo; m <= hi; ++m)
-            den += win[n - m * a.hop + a.M].x;
-        den *= win[a.M].x;
-    }
+    for (int e = threadIdx.x; e < a.L; e += 256)
+        gtab[e] = win[e].x;
 
     // Frames of this call whose window reaches the tile.
     int64_t mlo = tile_lo - a.M > 0 ? (tile_lo - a.M + a.hop - 1) / a.hop : 0;
@@ -1098,76 +1115,138 @@ __global__ __launch_bounds__(256) void inv_kernel(InvLaunch l)
         mlo = a.frame0;
     if (mhi > a.frame0 + a.nframes - 1)
         mhi = a.frame0 + a.nframes - 1;
-
-    const v2 *__restrict__ T = reinterpret_cast<const v2 *>(a.T);
+    const int K = mhi >= mlo ? (int)(mhi - mlo + 1) : 0;
     const int32_t *__restrict__ ridge = a.ridge + (int64_t)q * a.nframes;
-    const int zk1 = a.z * a.k1;
-    float acc = 0.f;
-    for (int64_t mb = mlo; mb <= mhi; mb += fb) {
-        const int cnt = (int)((mhi - mb + 1) < fb ? (mhi - mb + 1) : fb);
-        __syncthreads();
-        for (int e = threadIdx.x; e < cnt * W; e += 256) {
-            const int mi = e / W, d = e - mi * W;
-            const int64_t mloc = mb + mi - a.frame0;
-            const int r = ridge[mloc];
-            const int lq = r - a.hw + d;
-            v2 c = mk(0.f, 0.f);
-            if (r >= 0 && lq >= 0 && lq < a.n_dst) {
-                const int b = zk1 + lq;
-                const float wgt = (b == 0 || 2 * b == a.G) ? 1.f : 2.f;
-                c = (wgt * a.inv_nfft) * T[mloc * a.n_dst + lq];
-            }
-            coef[e] = c;
-            if (d == 0) {
-                int rb = -1;
-                if (r >= 0) {
-                    rb = (zk1 + r - a.hw) % a.G;
-                    if (rb < 0)
-                        rb += a.G;
-                }
-                rbase[mi] = rb;
+    for (int k = threadIdx.x; k < K; k += 256)
+        rid[k] = ridge[mlo + k - a.frame0];
+    if (threadIdx.x < 2)
+        red[threadIdx.x] = threadIdx.x == 0 ? 0x7fffffff : -1;
+    __syncthreads();
+    {   // destinations met by the zones of these frames
+        int dmin = 0x7fffffff, dmax = -1;
+        for (int k = threadIdx.x; k < K; k += 256) {
+            const int r = rid[k];
+            if (r >= 0) {
+                dmin = min(dmin, max(r - a.hw, 0));
+                dmax = max(dmax, min(r + a.hw, a.n_dst - 1));
             }
         }
-        __syncthreads();
-        if (!nvalid)
-            continue;
-        for (int mi = 0; mi < cnt; ++mi) {
-            const int64_t j64 = n - (mb + mi) * a.hop;
-            if (j64 < -a.M || j64 > a.M)
-                continue;
-            const int rb = rbase[mi];
-            if (rb < 0)
-                continue;
-            const int j = (int)j64;
-            const int jm = j < 0 ? j + a.G : j;
-            const v2 pw = phasor(tlo, thi, jm, a.lo_bits);
-            const v2 pb = phasor(tlo, thi, mulmod((uint32_t)rb, (uint32_t)jm, a.G, a.g_pow2, a.inv_G),
-                                 a.lo_bits);
-            const v2 *c = coef + mi * W;
-            v2 P = c[W - 1];
-            for (int d = W - 2; d >= 0; --d)
-                P = cmul(P, pw) + c[d];
-            acc += win[j + a.M].x * (pb.x * P.x - pb.y * P.y);
+        if (dmax >= 0) {
+            atomicMin(&red[0], dmin);
+            atomicMax(&red[1], dmax);
+        }
+    }
+    __syncthreads();
+    const int d_lo = red[0], d_hi = red[1];
+    const int zk1 = a.z * a.k1;
+    const uint32_t G = (uint32_t)a.G;
+    const uint32_t mh0 = (uint32_t)((mlo * (int64_t)a.hop) % a.G);   // (m_lo H) mod G
+    const uint32_t n0g = (uint32_t)(tile_lo % a.G);                  // tile_lo mod G
+
+    // the two sample columns of this lane and their offsets to the first frame
+    const int s0 = wave * 64 + col, s1 = s0 + 32;              // samples within the tile
+    const int jb0 = (int)(tile_lo - mlo * (int64_t)a.hop) + s0;   // n - m_lo H
+    const int jb1 = jb0 + 32;
+    float y0 = 0.f, y1 = 0.f;
+    for (int d0 = d_lo; d0 <= d_hi; d0 += 16) {
+        f32x16 acc0 = {}, acc1 = {};
+        for (int kb = 0; kb < K; kb += kInvKB) {
+            const int kn = K - kb < kInvKB ? K - kb : kInvKB;
+            const int knp = (kn + 1) & ~1;
+            __syncthreads();   // bst of the previous block consumed
+            // c~[m, d] of this block: 16 destinations, real and imaginary rows
+            for (int e = threadIdx.x; e < knp * 16; e += 256) {
+                const int kk = e >> 4, dd = e & 15;
+                const int k = kb + kk;
+                const int ld = d0 + dd;
+                v2 c = mk(0.f, 0.f);
+                const int r = k < K ? rid[k] : -1;
+                if (r >= 0 && ld <= d_hi && ld >= r - a.hw && ld <= r + a.hw) {
+                    const int b = zk1 + ld;   // < z (k2 + 1) <= G
+                    const float wgt = (b == 0 || 2 * b == a.G) ? 1.f : 2.f;
+                    const v2 t = reinterpret_cast<const v2 *>(a.T)[(mlo + k - a.frame0) * a.n_dst + ld];
+                    const uint32_t mh = (mh0 + (uint32_t)k * (uint32_t)a.hop) % G;
+                    const int bm = mulmod((uint32_t)b, mh, a.G, a.g_pow2, a.inv_G);
+                    const v2 ph = phasor(tlo, thi, bm, a.lo_bits);   // e^{+i 2 pi b m H / G}
+                    c = (wgt * a.inv_nfft) * cmul(t, conjv(ph));
+                }
+                bst[kk * 32 + 2 * dd] = c.x;
+                bst[kk * 32 + 2 * dd + 1] = c.y;
+            }
+            __syncthreads();
+#pragma unroll 4
+            for (int k0 = 0; k0 < knp; k0 += 2) {
+                const int kk = k0 + half;
+                const float av = bst[kk * 32 + col];
+                const int j0 = jb0 - (kb + kk) * a.hop, j1 = jb1 - (kb + kk) * a.hop;
+                const bool in = kb + kk < K;
+                const float g0 = (in && j0 >= -a.M && j0 <= a.M) ? gtab[j0 + a.M] : 0.f;
+                const float g1 = (in && j1 >= -a.M && j1 <= a.M) ? gtab[j1 + a.M] : 0.f;
+                acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(av, g0, acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(av, g1, acc1, 0, 0, 0);
+            }
+        }
+        // rows 8 (i/4) + 4 half + i mod 4 = 2 dd + p: dd = 4 (i/4) + 2 half + (i mod 4) / 2
+        const uint32_t bb = (uint32_t)(zk1 + d0 + 2 * half);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            uint32_t nm = n0g + (uint32_t)(c ? s1 : s0);
+            nm = nm >= G ? nm - G : nm;   // G >= 512 > 255
+            const v2 w = phasor(tlo, thi, nm, a.lo_bits);                                   // e^{i 2 pi n/G}
+            v2 e = phasor(tlo, thi, mulmod(bb, nm, a.G, a.g_pow2, a.inv_G), a.lo_bits);   // bin bb
+            const v2 w4 = cmul(cmul(w, w), cmul(w, w));
+            const f32x16 &acc = c ? acc1 : acc0;
+            float t = 0.f;
+#pragma unroll
+            for (int g4 = 0; g4 < 4; ++g4) {
+                const v2 e1 = cmul(e, w);   // next bin
+                t += e.x * acc[4 * g4] - e.y * acc[4 * g4 + 1];
+                t += e1.x * acc[4 * g4 + 2] - e1.y * acc[4 * g4 + 3];
+                e = cmul(e, w4);
+            }
+            t += __shfl_xor(t, 32, 64);
+            if (c)
+                y1 += t;
+            else
+                y0 += t;
         }
     }
 
-    float xv = 0.f;
-    if (nvalid) {
-        xv = den > 0.f ? acc / den : 0.f;
-        float *out = a.xhat + (int64_t)q * a.n + n;
-        if (a.accumulate)
-            xv += *out;
-        *out = xv;
-    }
-    if (a.err) {
-        double d2 = 0.0, r2 = 0.0;
-        if (nvalid && n >= a.M && n < a.n - a.M) {
-            const double rv = a.xref[(int64_t)q * a.n + n];
-            d2 = (rv - (double)xv) * (rv - (double)xv);
-            r2 = rv * rv;
+    // denominator and output: lanes of the first half write their two samples
+    double d2 = 0.0, r2 = 0.0;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const int srow = c ? s1 : s0;
+        const int64_t n = tile_lo + srow;
+        const bool writer = half == 0 && n <= tile_hi;
+        float xv = 0.f;
+        if (writer) {
+            const int64_t flo = n - a.M > 0 ? (n - a.M + a.hop - 1) / a.hop : 0;
+            const int64_t fhi = (n + a.M) / a.hop;
+            float dv;
+            if (n >= a.M && fhi <= a.n_frames - 1) {
+                dv = a.den[n % a.hop];
+            } else {
+                dv = 0.f;
+                const int64_t hi = fhi < a.n_frames - 1 ? fhi : a.n_frames - 1;
+                for (int64_t m = flo; m <= hi; ++m)
+                    dv += gtab[n - m * a.hop + a.M];
+                dv *= gtab[a.M];
+            }
+            xv = dv > 0.f ? (c ? y1 : y0) / dv : 0.f;
+            float *out = a.xhat + (int64_t)q * a.n + n;
+            if (a.accumulate)
+                xv += *out;
+            *out = xv;
         }
-        err_reduce(d2, r2, a.err, q);
+        if (a.err && writer && n >= a.M && n < a.n - a.M) {
+            const double rv = a.xref[(int64_t)q * a.n + n];
+            d2 += (rv - (double)xv) * (rv - (double)xv);
+            r2 += rv * rv;
+        }
     }
+    if (a.err)
+        err_reduce(d2, r2, a.err, q);
 }
 
 // Clear the error sums of every channel of an inverse launch.
@@ -1412,7 +1491,8 @@ hipError_t launch_put_desc(const ChanDesc &d, ChanDesc *dst, hipStream_t s)
 
 size_t inv_lds_bytes(const InvLaunch &l)
 {
-    return sizeof(float2) * (size_t)(l.max_tab + l.fb * l.max_w) + sizeof(int) * (size_t)l.fb;
+    return sizeof(float2) * (size_t)l.max_tab + 4 * (size_t)l.max_L + 4 * (size_t)l.max_k +
+           4 * 32 * (size_t)kInvKB + 16;
 }
 
 hipError_t launch_inverse(const InvLaunch &l, int64_t blocks, bool clear_err, hipStream_t s)
