@@ -427,7 +427,7 @@ def main():
     fwd_alg_bytes = t_bytes + x_bytes
     achieved = fwd_alg_bytes / (fwd_ms / 1e3) / 1e9
     traffic = load_traffic("c2")
-    roof = {"kernel": "fwd_kernel<4096,4> (fused framing + FFT pair + IF + reassignment)",
+    roof = {"kernel": "fwd_kernel (fused framing + FFT pair + IF + reassignment, N_f=4096)",
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": (traffic or {}).get("bytes_per_launch"),
