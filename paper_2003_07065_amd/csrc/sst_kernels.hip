@@ -202,12 +202,13 @@ struct Geo {
     static constexpr bool P4 = NF == 8192;            // radix-2 pass 4
 };
 
-// w^r for r = 0 .. R-1 from the bases B_b = w^(2^b) (b < log2 R, each the
-// correctly rounded value of a double-precision table): w^r is the product of
-// the bases of the set bits of r, formed as w^(2^p) w^(r - 2^p) with 2^p the
-// top bit of r, so each power is at most log2(R) - 1 products deep and its
-// error does not grow with r (powering a single rounded base would multiply
-// that base's rounding error by r).
+// w^r for r = 0 .. R-1 from the bases w^(4^c) (c = 0, 1, ..., each the
+// correctly rounded value of a double-precision table, `stride` apart): the
+// odd powers of two w^(2 4^c) are squares of the stored bases, and every other
+// power is the product of the powers of two of its set bits, formed as
+// w^(2^p) w^(r - 2^p) with 2^p the top bit of r.  Each power is a few products
+// deep and its error does not grow with r (powering a single rounded base
+// would multiply that base's rounding error by r).
 template <int R>
 __device__ __forceinline__ void powers(const v2 *bases, int stride, v2 (&p)[R])
 {
@@ -216,7 +217,10 @@ __device__ __forceinline__ void powers(const v2 *bases, int stride, v2 (&p)[R])
     for (int r = 1; r < R; ++r) {
         const int lb = 31 - __builtin_clz(r);
         const int hb = 1 << lb;
-        p[r] = hb == r ? bases[lb * stride] : cmul(p[hb], p[r - hb]);
+        if (hb == r)
+            p[r] = (lb & 1) ? cmul(p[r / 2], p[r / 2]) : bases[(lb >> 1) * stride];
+        else
+            p[r] = cmul(p[hb], p[r - hb]);
     }
 }
 
@@ -226,25 +230,25 @@ constexpr int log2i() { return R <= 1 ? 0 : 1 + log2i<R / 2>(); }
 // One Stockham pass of radix R and stride NS over the F frames in LDS.  The
 // twiddles W_{NS R}^{k r} with k = (j mod N_f/R) mod NS = tid mod NS (every
 // butterfly of a thread has the same k, as NS divides both N_f/R and the
-// thread count) are formed from the log2(R) bases W_{NS R}^{k 2^b}, staged
-// once in LDS as [b][k] (TW entries) so that they hold no registers between
-// passes.
+// thread count) are formed from the bases W_{NS R}^{k 4^c}, staged once in LDS
+// as [c][k] (TW entries) so that they hold no registers between passes.
 template <int NF, int R, int NS>
 struct Pass {
     using G = Geo<NF>;
     static constexpr int NR = NF / R;
     static constexpr int NB = (NF * G::F / R) / G::NT;   // butterflies per thread
     static constexpr int NBITS = log2i<R>();
-    static constexpr int TW = NS > 1 ? NS * NBITS : 0;    // LDS table entries
+    static constexpr int NSTORE = (NBITS + 1) / 2;         // stored bases w^(4^c)
+    static constexpr int TW = NS > 1 ? NS * NSTORE : 0;    // LDS table entries
     static_assert(NS == 1 || (G::NT % NS == 0 && NR % NS == 0), "one twiddle set per thread");
 
-    // tbl[b NS + k] = W_{NS R}^{k 2^b} = W_{N_f}^{(N_f / (NS R)) k 2^b}; the
+    // tbl[c NS + k] = W_{NS R}^{k 4^c} = W_{N_f}^{(N_f / (NS R)) k 4^c}; the
     // exponent stays below N_f / 2.
     static __device__ __forceinline__ void stage(v2 *tbl, const v2 *__restrict__ twid)
     {
         for (int e = threadIdx.x; e < TW; e += G::NT) {
-            const int b = e / NS, k = e % NS;
-            tbl[e] = twid[(unsigned)((NF / (NS * R)) * (k << b))];
+            const int c = e / NS, k = e % NS;
+            tbl[e] = twid[(unsigned)((NF / (NS * R)) * (k << (2 * c)))];
         }
     }
 
@@ -507,9 +511,10 @@ __device__ __forceinline__ v2 cphase_of(const v2 *lo, const v2 *hi, int t)
 }
 
 template <int NF, int NZ, int R, bool DEBUG, bool CHUNKED, bool MULTI>
-// Waves per SIMD: 4 for N_f = 8192 (two 8-wave workgroups fill a CU's LDS), 3 otherwise.
-// MULTI: the launch may hold several channels (else exactly one).
-__global__ __launch_bounds__(Geo<NF>::NT, DEBUG ? 2 : (NF == 8192 ? 4 : 3)) void fwd_kernel(GroupLaunch g)
+// Waves per SIMD: 4 for N_f = 8192 and for N_f = 4096 with at most 8 tap rows
+// (two 8-wave or four 4-wave workgroups fill a CU's LDS), 3 otherwise.  MULTI: the launch may hold several channels (else
+// exactly one).
+__global__ __launch_bounds__(Geo<NF>::NT, DEBUG ? 2 : ((NF == 8192 || (NF == 4096 && NZ < 16)) ? 4 : 3)) void fwd_kernel(GroupLaunch g)
 {
     using G = Geo<NF>;
     constexpr int F = G::F, NT = G::NT, Q = NF / 16;
@@ -844,7 +849,7 @@ __device__ __forceinline__ void block_max_flush(float v, float *red, unsigned *d
 }
 
 template <int NF, int NZ>
-__global__ __launch_bounds__(Geo<NF>::NT, NF == 8192 ? 4 : 3) void max_kernel(GroupLaunch g)
+__global__ __launch_bounds__(Geo<NF>::NT, (NF == 8192 || (NF == 4096 && NZ < 16)) ? 4 : 3) void max_kernel(GroupLaunch g)
 {
     using G = Geo<NF>;
     constexpr int F = G::F, NT = G::NT, Q = NF / 16;
