@@ -216,7 +216,8 @@ sst_status sst_ridge(sst_plan_t plan, const float *T, int64_t nframes, const int
  *   xref     optional device float [n_comp][n_samples] (noise-free components)
  *   err      optional device double [n_comp][2]: sum (xref - xhat)^2 and sum xref^2
  *            over n in [M, N - M), FP64 (Eq. 33); needs xref and a whole-signal call
- * Errors: SST_E_ARG, SST_E_STATE, SST_E_DEVICE.
+ * Errors: SST_E_ARG, SST_E_STATE, SST_E_DEVICE, SST_E_UNSUPPORTED (n_comp * ceil(span / 256)
+ * >= 2^31, or a window too long for the hop to fit the per-tile tables).
  */
 sst_status sst_inverse(sst_plan_t plan, const float *T, int64_t frame0, int64_t nframes,
                        const int32_t *ridge, int32_t n_comp, int32_t hw, float *xhat,

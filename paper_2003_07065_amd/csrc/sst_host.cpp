@@ -82,6 +82,8 @@ sst_status validate(const sst_params *p)
         return fail(SST_E_ARG, "params.struct_size smaller than sizeof(sst_params)");
     if (p->n_samples < 1)
         return fail(SST_E_ARG, "n_samples must be >= 1");
+    if (p->n_samples >= (int64_t(1) << 30))
+        return fail(SST_E_UNSUPPORTED, "n_samples must be below 2^30 (32-bit sample indices)");
     if (!(p->fs > 0.0) || !std::isfinite(p->fs))
         return fail(SST_E_ARG, "fs must be finite and > 0");
     if (p->win_len < 1 || (p->win_len % 2) == 0)
@@ -690,6 +692,8 @@ sst_status sst_inverse(sst_plan_t pl, const float *T, int64_t frame0, int64_t nf
     }
     if (a.span_len <= 0)
         return SST_OK;
+    if (a.blk_end >= (int64_t(1) << 31))
+        return fail(SST_E_UNSUPPORTED, "n_comp * ceil(span / 256) must be below 2^31");
     sst::InvLaunch l = inv_launch(slot, 1, a.blk0, inv_max_k(pl), pl->n_lo + pl->n_hi,
                                   pl->p.win_len);
     if (sst::inv_lds_bytes(l) > 64 * 1024)
@@ -1023,6 +1027,9 @@ sst_status sst_batch_inverse(sst_batch_t b, int32_t c_begin, int32_t c_end, void
         return fail(SST_E_UNSUPPORTED, "inverse tiles need more than 64 KiB of LDS "
                                        "(window too long for the hop)");
     const int64_t blocks = b->idesc[(size_t)c_end - 1].blk_end - l.blk_begin;
+    for (int c = c_begin; c < c_end; ++c)
+        if (b->idesc[(size_t)c].blk_end - b->idesc[(size_t)c].blk0 >= (int64_t(1) << 31))
+            return fail(SST_E_UNSUPPORTED, "n_comp * ceil(n_samples / 256) must be below 2^31");
     hipError_t e = sst::launch_inverse(l, blocks, any_err, reinterpret_cast<hipStream_t>(stream));
     if (e != hipSuccess)
         return hip_fail(e, "batched inverse launch");

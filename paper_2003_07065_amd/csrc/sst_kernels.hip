@@ -1082,7 +1082,7 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 constexpr int kInvTile = 256;   // output samples per workgroup (4 waves x 2 x 32)
 constexpr int kInvKB = 128;     // frames staged per block
 
-__global__ __launch_bounds__(256) void inv_kernel(InvLaunch l)
+__global__ __launch_bounds__(256, 4) void inv_kernel(InvLaunch l)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int64_t blk = l.blk_begin + (int64_t)blockIdx.x;
@@ -1097,13 +1097,18 @@ __global__ __launch_bounds__(256) void inv_kernel(InvLaunch l)
     float *bst = reinterpret_cast<float *>(rid + l.max_k);      // [kInvKB][32]
     int *red = reinterpret_cast<int *>(bst + 32 * kInvKB);      // [2]
 
+    // Signals hold fewer than 2^30 samples and n_comp * tiles < 2^31 (checked
+    // by the host), so sample, frame and tile indices fit 32 bits.
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int col = lane & 31, half = lane >> 5;
-    const int64_t local = blk - a.blk0;
-    const int q = (int)(local / a.tiles);
-    const int64_t tile_lo = a.span_lo + (local - (int64_t)q * a.tiles) * kInvTile;
-    const int64_t span_end = a.span_lo + a.span_len - 1;
-    const int64_t tile_hi = tile_lo + kInvTile - 1 < span_end ? tile_lo + kInvTile - 1 : span_end;
+    const unsigned local = (unsigned)(blk - a.blk0);
+    const unsigned tiles = (unsigned)a.tiles;
+    const int q = (int)(local / tiles);
+    const int span_lo = (int)a.span_lo, span_end = (int)(a.span_lo + a.span_len - 1);
+    const int tile_lo = span_lo + (int)(local - (unsigned)q * tiles) * kInvTile;
+    const int tile_hi = tile_lo + kInvTile - 1 < span_end ? tile_lo + kInvTile - 1 : span_end;
+    const int M = a.M, H = a.hop, Gi = a.G;
+    const int frame0 = (int)a.frame0, nfr = (int)a.nframes, nframes_all = (int)a.n_frames;
     const v2 *__restrict__ win = reinterpret_cast<const v2 *>(a.win);
 
     for (int e = threadIdx.x; e < nlo; e += 256)
@@ -1114,16 +1119,16 @@ __global__ __launch_bounds__(256) void inv_kernel(InvLaunch l)
         gtab[e] = win[e].x;
 
     // Frames of this call whose window reaches the tile.
-    int64_t mlo = tile_lo - a.M > 0 ? (tile_lo - a.M + a.hop - 1) / a.hop : 0;
-    int64_t mhi = (tile_hi + a.M) / a.hop;
-    if (mlo < a.frame0)
-        mlo = a.frame0;
-    if (mhi > a.frame0 + a.nframes - 1)
-        mhi = a.frame0 + a.nframes - 1;
-    const int K = mhi >= mlo ? (int)(mhi - mlo + 1) : 0;
-    const int32_t *__restrict__ ridge = a.ridge + (int64_t)q * a.nframes;
+    int mlo = tile_lo - M > 0 ? (tile_lo - M + H - 1) / H : 0;
+    int mhi = (tile_hi + M) / H;
+    if (mlo < frame0)
+        mlo = frame0;
+    if (mhi > frame0 + nfr - 1)
+        mhi = frame0 + nfr - 1;
+    const int K = mhi >= mlo ? mhi - mlo + 1 : 0;
+    const int32_t *__restrict__ ridge = a.ridge + (int64_t)q * a.nframes + (mlo - frame0);
     for (int k = threadIdx.x; k < K; k += 256)
-        rid[k] = ridge[mlo + k - a.frame0];
+        rid[k] = ridge[k];
     if (threadIdx.x < 2)
         red[threadIdx.x] = threadIdx.x == 0 ? 0x7fffffff : -1;
     __syncthreads();
@@ -1144,14 +1149,16 @@ __global__ __launch_bounds__(256) void inv_kernel(InvLaunch l)
     __syncthreads();
     const int d_lo = red[0], d_hi = red[1];
     const int zk1 = a.z * a.k1;
-    const uint32_t G = (uint32_t)a.G;
-    const uint32_t mh0 = (uint32_t)((mlo * (int64_t)a.hop) % a.G);   // (m_lo H) mod G
-    const uint32_t n0g = (uint32_t)(tile_lo % a.G);                  // tile_lo mod G
+    const uint32_t G = (uint32_t)Gi;
+    const bool pow2 = a.g_pow2 != 0;
+    const uint32_t mh0 = (uint32_t)(mlo * H) % G;    // (m_lo H) mod G
+    const uint32_t n0g = (uint32_t)tile_lo % G;      // tile_lo mod G
+    const uint32_t hg = (uint32_t)H % G;             // H mod G
 
     // the two sample columns of this lane and their offsets to the first frame
-    const int s0 = wave * 64 + col, s1 = s0 + 32;              // samples within the tile
-    const int jb0 = (int)(tile_lo - mlo * (int64_t)a.hop) + s0;   // n - m_lo H
-    const int jb1 = jb0 + 32;
+    const int s0 = wave * 64 + col;                  // sample within the tile
+    const int jb0 = tile_lo - mlo * H + s0;          // n - m_lo H for column 0; column 1 is +32
+    const v2 *__restrict__ Trow = reinterpret_cast<const v2 *>(a.T) + (int64_t)(mlo - frame0) * a.n_dst;
     float y0 = 0.f, y1 = 0.f;
     for (int d0 = d_lo; d0 <= d_hi; d0 += 16) {
         f32x16 acc0 = {}, acc1 = {};
@@ -1168,10 +1175,12 @@ __global__ __launch_bounds__(256) void inv_kernel(InvLaunch l)
                 const int r = k < K ? rid[k] : -1;
                 if (r >= 0 && ld <= d_hi && ld >= r - a.hw && ld <= r + a.hw) {
                     const int b = zk1 + ld;   // < z (k2 + 1) <= G
-                    const float wgt = (b == 0 || 2 * b == a.G) ? 1.f : 2.f;
-                    const v2 t = reinterpret_cast<const v2 *>(a.T)[(mlo + k - a.frame0) * a.n_dst + ld];
-                    const uint32_t mh = (mh0 + (uint32_t)k * (uint32_t)a.hop) % G;
-                    const int bm = mulmod((uint32_t)b, mh, a.G, a.g_pow2, a.inv_G);
+                    const float wgt = (b == 0 || 2 * b == Gi) ? 1.f : 2.f;
+                    const v2 t = Trow[(int64_t)k * a.n_dst + ld];
+                    // (m H) mod G = (m_lo H + k H) mod G, k H < 2^31
+                    uint32_t mh = mh0 + (uint32_t)k * hg;
+                    mh = pow2 ? (mh & (G - 1)) : mh % G;
+                    const int bm = mulmod((uint32_t)b, mh, Gi, a.g_pow2, a.inv_G);
                     const v2 ph = phasor(tlo, thi, bm, a.lo_bits);   // e^{+i 2 pi b m H / G}
                     c = (wgt * a.inv_nfft) * cmul(t, conjv(ph));
                 }
@@ -1179,26 +1188,30 @@ __global__ __launch_bounds__(256) void inv_kernel(InvLaunch l)
                 bst[kk * 32 + 2 * dd + 1] = c.y;
             }
             __syncthreads();
+            // j = n - m H for this lane's rows: (jb0 - (kb + kk) H), stepping by 2H
+            int j0 = jb0 - (kb + half) * H;
+            const unsigned span = 2u * (unsigned)M;
+            const float *gt = gtab + M;
+            const float *bp = bst + half * 32 + col;
 #pragma unroll 4
             for (int k0 = 0; k0 < knp; k0 += 2) {
-                const int kk = k0 + half;
-                const float av = bst[kk * 32 + col];
-                const int j0 = jb0 - (kb + kk) * a.hop, j1 = jb1 - (kb + kk) * a.hop;
-                const bool in = kb + kk < K;
-                const float g0 = (in && j0 >= -a.M && j0 <= a.M) ? gtab[j0 + a.M] : 0.f;
-                const float g1 = (in && j1 >= -a.M && j1 <= a.M) ? gtab[j1 + a.M] : 0.f;
+                const float av = bp[k0 * 32];
+                const int j1 = j0 + 32;
+                const float g0 = ((unsigned)(j0 + M) <= span) ? gt[j0] : 0.f;
+                const float g1 = ((unsigned)(j1 + M) <= span) ? gt[j1] : 0.f;
                 acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(av, g0, acc0, 0, 0, 0);
                 acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(av, g1, acc1, 0, 0, 0);
+                j0 -= 2 * H;
             }
         }
         // rows 8 (i/4) + 4 half + i mod 4 = 2 dd + p: dd = 4 (i/4) + 2 half + (i mod 4) / 2
         const uint32_t bb = (uint32_t)(zk1 + d0 + 2 * half);
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
-            uint32_t nm = n0g + (uint32_t)(c ? s1 : s0);
+            uint32_t nm = n0g + (uint32_t)(s0 + 32 * c);
             nm = nm >= G ? nm - G : nm;   // G >= 512 > 255
-            const v2 w = phasor(tlo, thi, nm, a.lo_bits);                                   // e^{i 2 pi n/G}
-            v2 e = phasor(tlo, thi, mulmod(bb, nm, a.G, a.g_pow2, a.inv_G), a.lo_bits);   // bin bb
+            const v2 w = phasor(tlo, thi, nm, a.lo_bits);                                  // e^{i 2 pi n/G}
+            v2 e = phasor(tlo, thi, mulmod(bb, nm, Gi, a.g_pow2, a.inv_G), a.lo_bits);   // bin bb
             const v2 w4 = cmul(cmul(w, w), cmul(w, w));
             const f32x16 &acc = c ? acc1 : acc0;
             float t = 0.f;
@@ -1221,22 +1234,21 @@ __global__ __launch_bounds__(256) void inv_kernel(InvLaunch l)
     double d2 = 0.0, r2 = 0.0;
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
-        const int srow = c ? s1 : s0;
-        const int64_t n = tile_lo + srow;
+        const int n = tile_lo + s0 + 32 * c;
         const bool writer = half == 0 && n <= tile_hi;
         float xv = 0.f;
         if (writer) {
-            const int64_t flo = n - a.M > 0 ? (n - a.M + a.hop - 1) / a.hop : 0;
-            const int64_t fhi = (n + a.M) / a.hop;
+            const int flo = n - M > 0 ? (n - M + H - 1) / H : 0;
+            const int fhi = (n + M) / H;
             float dv;
-            if (n >= a.M && fhi <= a.n_frames - 1) {
-                dv = a.den[n % a.hop];
+            if (n >= M && fhi <= nframes_all - 1) {
+                dv = a.den[n % H];
             } else {
                 dv = 0.f;
-                const int64_t hi = fhi < a.n_frames - 1 ? fhi : a.n_frames - 1;
-                for (int64_t m = flo; m <= hi; ++m)
-                    dv += gtab[n - m * a.hop + a.M];
-                dv *= gtab[a.M];
+                const int hi = fhi < nframes_all - 1 ? fhi : nframes_all - 1;
+                for (int m = flo; m <= hi; ++m)
+                    dv += gtab[n - m * H + M];
+                dv *= gtab[M];
             }
             xv = dv > 0.f ? (c ? y1 : y0) / dv : 0.f;
             float *out = a.xhat + (int64_t)q * a.n + n;
@@ -1244,7 +1256,7 @@ __global__ __launch_bounds__(256) void inv_kernel(InvLaunch l)
                 xv += *out;
             *out = xv;
         }
-        if (a.err && writer && n >= a.M && n < a.n - a.M) {
+        if (a.err && writer && n >= M && n < a.n - M) {
             const double rv = a.xref[(int64_t)q * a.n + n];
             d2 += (rv - (double)xv) * (rv - (double)xv);
             r2 += rv * rv;
