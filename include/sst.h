@@ -78,7 +78,7 @@ typedef int32_t sst_status;
 /*
  * Transform parameters, copied at plan time (Sec. 2.1, 2.2, 2.4).
  *   struct_size  sizeof(sst_params), for forward compatibility
- *   n_samples    N, signal length, >= 1
+ *   n_samples    N, signal length, 1 <= N < 2^30
  *   fs           sampling rate in Hz, > 0
  *   win_len      L = 2M+1, odd, 1 <= L <= nfft
  *   sigma        Gaussian width in samples, > 0 (ignored when window given)
