@@ -62,6 +62,9 @@ __device__ __forceinline__ v2 cmul(v2 a, v2 b)
 __device__ __forceinline__ v2 mul_mi(v2 a) { return mk(a.y, -a.x); }   // -i a
 __device__ __forceinline__ v2 conjv(v2 a) { return mk(a.x, -a.y); }
 __device__ __forceinline__ int pad16(int a) { return a + (a >> 4); }
+// pad16(a + 16 u) = pad16(a) + 17 u for a >= 0: strided accesses take one padded
+// base and constant offsets, which the LDS instructions encode as immediates.
+constexpr int padded_stride(int s) { return s + s / 16; }
 
 // ---------------------------------------------------------------------------
 // Register DFTs (forward, exp(-i ...)), natural order in and out.
@@ -265,7 +268,7 @@ struct Pass {
             const int f = j / NR, jj = j % NR;
 #pragma unroll
             for (int r = 0; r < R; ++r)
-                v[b][r] = lds[pad16(f * NF + jj + r * NR)];
+                v[b][r] = lds[pad16(f * NF + jj) + r * padded_stride(NR)];
         }
         if constexpr (NS > 1) {
             v2 p[R];
@@ -288,7 +291,7 @@ struct Pass {
             const int base_i = f * NF + (jj / NS) * NS * R + k;
 #pragma unroll
             for (int r = 0; r < R; ++r)
-                lds[pad16(base_i + r * NS)] = v[b][r];
+                lds[pad16(base_i) + r * padded_stride(NS)] = v[b][r];
         }
         __syncthreads();
     }
@@ -338,7 +341,7 @@ struct Twiddles {
         for (int b = 0; b < NB4; ++b) {
             const int j = tid + b * G::NT;
             v[b][0] = lds[pad16(j)];
-            v[b][1] = cmul(lds[pad16(j + 4096)], t4[b]);
+            v[b][1] = cmul(lds[pad16(j) + padded_stride(4096)], t4[b]);
             const v2 u = v[b][0];
             v[b][0] = u + v[b][1];
             v[b][1] = u - v[b][1];
@@ -348,7 +351,7 @@ struct Twiddles {
         for (int b = 0; b < NB4; ++b) {
             const int j = tid + b * G::NT;
             lds[pad16(j)] = v[b][0];
-            lds[pad16(j + 4096)] = v[b][1];
+            lds[pad16(j) + padded_stride(4096)] = v[b][1];
         }
         __syncthreads();
     }
@@ -375,7 +378,7 @@ __device__ __forceinline__ void pass1(v2 *lds, const Loader &load)
     const int base = f * NF + jj * 16;
 #pragma unroll
     for (int r = 0; r < 16; ++r)
-        lds[pad16(base + r)] = v[r];
+        lds[pad16(base) + r] = v[r];   // base: a multiple of 16
     __syncthreads();
 }
 
@@ -618,7 +621,7 @@ __global__ __launch_bounds__(Geo<NF>::NT, DEBUG ? 2 : ((NF == 8192 || (NF == 409
             const int base = f1 * NF + jj * 16;
 #pragma unroll
             for (int r = 0; r < 16; ++r)
-                lds[pad16(base + r)] = v[r];
+                lds[pad16(base) + r] = v[r];   // base: a multiple of 16
         }
         // next iteration's samples, issued before this one's stores
         const int64_t itn = it + gridDim.x;
@@ -652,6 +655,8 @@ __global__ __launch_bounds__(Geo<NF>::NT, DEBUG ? 2 : ((NF == 8192 || (NF == 409
         // differ by the constant factor for (NT M) mod N_f, so they are
         // generated by rotation; otherwise each is looked up.
         v2 ph_cur = ph0;
+        const int pk0 = pad16(a.k1 + tid);        // F == 1: bin of round 0
+        const int qk0 = pad16(NF - a.k1 - tid);   // and its mirror
 #pragma unroll
         for (int i = 0; i < R; ++i) {
             // rounds are independent; keeping the scheduler from interleaving
@@ -674,8 +679,16 @@ __global__ __launch_bounds__(Geo<NF>::NT, DEBUG ? 2 : ((NF == 8192 || (NF == 409
             if (e >= E)
                 continue;
             const int k = a.k1 + ik;
-            const v2 P = lds[pad16(f * NF + k)];
-            const v2 Qc = conjv(lds[pad16(f * NF + ((NF - k) & (NF - 1)))]);
+            v2 P, Qc;
+            if constexpr (F == 1) {
+                // k = k1 + tid + i NT: P at pk0 + i (NT + NT/16), the mirror
+                // bin N_f - k at qk0 - i (NT + NT/16) (bin 0 is its own mirror)
+                P = lds[pk0 + i * padded_stride(NT)];
+                Qc = conjv(lds[k == 0 ? 0 : qk0 - i * padded_stride(NT)]);
+            } else {
+                P = lds[pad16(f * NF + k)];
+                Qc = conjv(lds[pad16(f * NF + ((NF - k) & (NF - 1)))]);
+            }
             const v2 A = 0.5f * (P + Qc);
             const v2 D = P - Qc;
             const v2 B = mk(0.5f * D.y, -0.5f * D.x);
@@ -922,7 +935,7 @@ __global__ __launch_bounds__(Geo<NF>::NT, (NF == 8192 || (NF == 4096 && NZ < 16)
             const int base = f1 * NF + jj * 16;
 #pragma unroll
             for (int r = 0; r < 16; ++r)
-                lds[pad16(base + r)] = v[r];
+                lds[pad16(base) + r] = v[r];   // base: a multiple of 16
         }
         const int64_t itn = it + gridDim.x;
         Chan an = a;
