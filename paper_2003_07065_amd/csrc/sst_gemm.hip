@@ -22,7 +22,9 @@
 // row tile: by Parseval, sum_k |S_k|^2 <= N_f sum_j x_j^2 g_j^2 over all N_f
 // bins, hence sum over the n_src band bins of (|Re S| + |Im S|) is at most
 // sqrt(2 n_src N_f sum_j x_j^2 g_j^2), taken with a 10 % margin for the
-// rounding of the low-precision products.
+// rounding of the low-precision products; sum_j x_j^2 g_j^2 is bounded in turn
+// by max g^2 times the sums of squares of the 8-sample groups that cover the
+// frame's window (about one bit of scale lost against the exact sum).
 //
 // Layouts (32x32x16 MFMA, checked on the hardware): lane l holds A rows
 // l mod 32 with k = 8 (l / 32) .. +7, B columns (frames) l mod 32 with the same
@@ -114,12 +116,14 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmArgs a)
     constexpr bool SPLIT = PREC == SST_GEMM_F16X3;
     extern __shared__ __align__(16) unsigned char smem[];
     const int slab = a.slab;                  // samples staged per tile (multiple of 8)
+    const int ngrp = slab / 8;                // groups of 8 staged samples
     int *hist = reinterpret_cast<int *>(smem);                        // [FT][n_dst][2]
     unsigned short *xhi = reinterpret_cast<unsigned short *>(hist + 2 * FT * a.n_dst);
     unsigned short *xlo = xhi + slab;                                 // SPLIT only
-    float *g2 = reinterpret_cast<float *>(xlo + (SPLIT ? slab : 0));  // [L]: g^2
-    float *scf = g2 + ((a.L + 3) & ~3);                               // [FT]
-    float *red = scf + FT;                                            // [4]
+    float *gsq = reinterpret_cast<float *>(xlo + (SPLIT ? slab : 0)); // [ngrp]: sum x^2
+    float *scf = gsq + ((ngrp + 3) & ~3);                             // [FT]
+    float *iscf = scf + FT;                                           // [FT]
+    float *red = iscf + FT;                                           // [4]
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int col = lane & 31, half = lane >> 5;
@@ -128,26 +132,30 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmArgs a)
     const u4v *__restrict__ afrag = reinterpret_cast<const u4v *>(a.afrag);
     const u4v *__restrict__ afrag_lo = reinterpret_cast<const u4v *>(a.afrag_lo);
 
-    for (int j = threadIdx.x; j < a.L; j += NT) {
-        const float g = a.win[j].x;
-        g2[j] = g * g;
-    }
-
     for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const int64_t m0 = tile * FT;   // first frame of the tile, relative to frame0
         const int nvalid = (int)((a.nframes - m0) < FT ? (a.nframes - m0) : FT);
         const int64_t s0 = (a.frame0 + m0) * (int64_t)a.hop - a.M;
         __syncthreads();   // previous tile's store phase is done with the LDS
 
-        // slab of samples, zero outside the signal; FP16 split: scaled by 2^sx
-        float vmax = 0.f;
-        for (int s = threadIdx.x; s < slab; s += NT) {
-            const int64_t n = s0 + s;
-            const float v = (n >= 0 && n < a.n) ? a.x[n] : 0.f;
-            vmax = fmaxf(vmax, fabsf(v));
-        }
+        // slab of samples in groups of 8, zero outside the signal; FP16 split:
+        // scaled by 2^sx.  The sums of squares per group feed the scale bound.
+        auto load8 = [&](int gi, float (&v)[8]) {
+            const int64_t n = s0 + 8 * gi;
+#pragma unroll
+            for (int t = 0; t < 8; ++t)
+                v[t] = (n + t >= 0 && n + t < a.n) ? a.x[n + t] : 0.f;
+        };
         float sxs = 1.f, sxu = 1.f;
         if constexpr (SPLIT) {
+            float vmax = 0.f;
+            for (int gi = threadIdx.x; gi < ngrp; gi += NT) {
+                float v[8];
+                load8(gi, v);
+#pragma unroll
+                for (int t = 0; t < 8; ++t)
+                    vmax = fmaxf(vmax, fabsf(v[t]));
+            }
             const float mx = block_max(vmax, red);
             int e = 0;
             frexpf(mx, &e);                       // mx < 2^e
@@ -155,34 +163,48 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmArgs a)
             sxs = ldexpf(1.f, sx);
             sxu = ldexpf(1.f, -sx);
         }
-        for (int s = threadIdx.x; s < slab; s += NT) {
-            const int64_t n = s0 + s;
-            const float v = (n >= 0 && n < a.n) ? a.x[n] : 0.f;
-            unsigned short hi, lo;
-            split<PREC>(v * sxs, hi, lo);
-            xhi[s] = hi;
+        for (int gi = threadIdx.x; gi < ngrp; gi += NT) {
+            float v[8];
+            load8(gi, v);
+            float sq = 0.f;
+            unsigned short hi[8], lo[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                sq += v[t] * v[t];
+                split<PREC>(v[t] * sxs, hi[t], lo[t]);
+            }
+            gsq[gi] = sq;
+            u4v ph, pl;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                ph[t] = (unsigned)hi[2 * t] | ((unsigned)hi[2 * t + 1] << 16);
+                pl[t] = (unsigned)lo[2 * t] | ((unsigned)lo[2 * t + 1] << 16);
+            }
+            *reinterpret_cast<u4v *>(xhi + 8 * gi) = ph;
             if constexpr (SPLIT)
-                xlo[s] = lo;
+                *reinterpret_cast<u4v *>(xlo + 8 * gi) = pl;
         }
         for (int e = threadIdx.x; e < 2 * FT * a.n_dst; e += NT)
             hist[e] = 0;
         __syncthreads();
 
-        // per-frame fixed-point scale from the Parseval bound
+        // per-frame fixed-point scale: Parseval bound with sum_j x_j^2 g_j^2 <=
+        // max g^2 times the sums of squares of the groups covering the window
         {
             constexpr int TPF = NT / FT;          // threads per frame
             const int f = threadIdx.x / TPF, part = threadIdx.x % TPF;
+            const int g0 = f * (a.hop / 8), gn = (a.L + 7) / 8;
             float en = 0.f;
-            for (int j = part; j < a.L; j += TPF) {
-                const int s = f * a.hop + j;
-                const float v = widen<PREC>(xhi[s], SPLIT ? xlo[s] : (unsigned short)0) * sxu;
-                en += v * v * g2[j];
-            }
+            for (int gi = part; gi < gn; gi += TPF)
+                en += gsq[g0 + gi];
 #pragma unroll
             for (int o = TPF / 2; o > 0; o >>= 1)
                 en += __shfl_xor(en, o, 64);
-            if (part == 0)
-                scf[f] = fixed_scale(a.bound_c * sqrtf(en));
+            if (part == 0) {
+                const float sc = fixed_scale(a.bound_c * sqrtf(a.gmax2 * en));
+                scf[f] = sc;
+                iscf[f] = 1.0f / sc;   // exact: a power of two
+            }
         }
         __syncthreads();
 
@@ -195,20 +217,24 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmArgs a)
             const int64_t abase = (int64_t)rt * a.ksteps * 64 + lane;
             u4v an = afrag[abase];
             u4v anl = SPLIT ? afrag_lo[abase] : u4v{};
+            const u4v *ap = afrag + abase, *apl = afrag_lo + abase;
+            const unsigned short *bp = xhi + col * a.hop + 8 * half;   // k = 0, column tile 0
+            const int cstride = 32 * a.hop;                             // next column tile
+#pragma unroll 4
             for (int ks = 0; ks < a.ksteps; ++ks) {
                 const u4v ac = an, acl = anl;
                 if (ks + 1 < a.ksteps) {
-                    an = afrag[abase + (int64_t)(ks + 1) * 64];
+                    an = ap[(ks + 1) * 64];
                     if constexpr (SPLIT)
-                        anl = afrag_lo[abase + (int64_t)(ks + 1) * 64];
+                        anl = apl[(ks + 1) * 64];
                 }
 #pragma unroll
                 for (int c = 0; c < CT; ++c) {
-                    const int s = (c * 32 + col) * a.hop + ks * 16 + 8 * half;
-                    const u4v b = *reinterpret_cast<const u4v *>(xhi + s);
+                    const unsigned short *q = bp + c * cstride + ks * 16;
+                    const u4v b = *reinterpret_cast<const u4v *>(q);
                     acc[c] = mma<PREC>(ac, b, acc[c]);
                     if constexpr (SPLIT) {
-                        const u4v bl = *reinterpret_cast<const u4v *>(xlo + s);
+                        const u4v bl = *reinterpret_cast<const u4v *>(q + slab);
                         acc[c] = mma<PREC>(ac, bl, acc[c]);
                         acc[c] = mma<PREC>(acl, b, acc[c]);
                     }
@@ -266,7 +292,7 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmArgs a)
         for (int e = threadIdx.x; e < FT * a.n_dst; e += NT) {
             int f = (int)(((float)e + 0.5f) * inv_ndst);
             f = f < FT ? f : FT - 1;
-            const float isc = 1.0f / scf[f];
+            const float isc = iscf[f];
             const f2v v = {(float)hist[2 * e] * isc, (float)hist[2 * e + 1] * isc};
             __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2v, v), rs, (unsigned)e * 8u,
                                                   0, kNonTemporal);
@@ -300,7 +326,9 @@ int occ_prec_ft(size_t lds)
 size_t gemm_lds_bytes(int prec, int ft, int n_dst, int slab, int L)
 {
     const size_t xs = (size_t)slab * 2 * (prec == SST_GEMM_F16X3 ? 2 : 1);
-    return (size_t)ft * n_dst * 8 + xs + 4 * (size_t)((L + 3) & ~3) + 4 * (size_t)ft + 16;
+    const size_t ngrp = (size_t)(slab / 8);
+    (void)L;
+    return (size_t)ft * n_dst * 8 + xs + 4 * ((ngrp + 3) & ~(size_t)3) + 8 * (size_t)ft + 16;
 }
 
 hipError_t launch_gemm_forward(int prec, int ft, bool debug, const GemmArgs &a, int grid,

@@ -57,7 +57,7 @@ struct sst_plan_s {
     int G = 0, lo_bits = 0, n_lo = 0, n_hi = 0;
     // DFT-as-GEMM tier
     int gemm_ft = 0, row_tiles = 0, ksteps = 0, slab = 0;
-    float unscale_g = 1.f, unscale_gd = 1.f;
+    float unscale_g = 1.f, unscale_gd = 1.f, gmax2 = 0.f;
     size_t off_afrag = 0, off_afrag_lo = 0, afrag_bytes = 0;
     // workspace layout (bytes): control block, descriptor slot, tables
     size_t off_desc = 0, off_idesc = 0, off_win = 0, off_twid = 0, off_phlo = 0, off_phhi = 0;
@@ -262,6 +262,7 @@ void build_afrag(sst_plan_s *pl, const std::vector<double> &g, const std::vector
         return m > 0.0 ? 14 - e : 0;
     };
     const int sg = split ? pow2_scale(mg) : 0, sgd = split ? pow2_scale(mgd) : 0;
+    pl->gmax2 = (float)(mg * mg * (1.0 + 1e-6));
     pl->unscale_g = (float)std::ldexp(1.0, -sg);
     pl->unscale_gd = (float)std::ldexp(1.0, -sgd);
     uint16_t *hi = reinterpret_cast<uint16_t *>(pl->blob.data() + (pl->off_afrag - pl->off_win));
@@ -600,6 +601,7 @@ sst_status sst_forward(sst_plan_t pl, const float *x, int64_t frame0, int64_t nf
         ga.unscale_gd = pl->unscale_gd;
         ga.cdelta = (float)(pl->p.nfft / kTwoPi);
         ga.bound_c = (float)(1.1 * std::sqrt(2.0 * pl->n_src * pl->p.nfft));
+        ga.gmax2 = pl->gmax2;
         const int64_t tiles = (nframes + pl->gemm_ft - 1) / pl->gemm_ft;
         const int grid = (int)(tiles < pl->fwd_grid_cap ? tiles : pl->fwd_grid_cap);
         const bool dbg = aux && (aux->S || aux->Sd || aux->idx);

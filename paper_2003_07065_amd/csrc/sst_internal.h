@@ -122,6 +122,7 @@ struct GemmArgs {
     float unscale_gd;       // same for the g' rows
     float cdelta;           // N_f / (2 pi)
     float bound_c;          // 1.1 sqrt(2 n_src N_f)
+    float gmax2;            // max_j g[j]^2
 };
 
 // Arguments of the ridge kernel.
