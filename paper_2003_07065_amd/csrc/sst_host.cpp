@@ -1032,6 +1032,9 @@ sst_status sst_batch_inverse(sst_batch_t b, int32_t c_begin, int32_t c_end, void
     for (int c = c_begin; c < c_end; ++c)
         if (b->idesc[(size_t)c].blk_end - b->idesc[(size_t)c].blk0 >= (int64_t(1) << 31))
             return fail(SST_E_UNSUPPORTED, "n_comp * ceil(n_samples / 256) must be below 2^31");
+    if (blocks >= (int64_t(1) << 31))
+        return fail(SST_E_UNSUPPORTED, "the channel range needs 2^31 or more inverse tiles; "
+                                       "split it over several calls");
     hipError_t e = sst::launch_inverse(l, blocks, any_err, reinterpret_cast<hipStream_t>(stream));
     if (e != hipSuccess)
         return hip_fail(e, "batched inverse launch");

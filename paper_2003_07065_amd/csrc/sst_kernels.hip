@@ -1093,9 +1093,9 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 // and comes from a table built on the host in float64; near the ends of the
 // signal it is summed here.
 constexpr int kInvTile = 256;   // output samples per workgroup (4 waves x 2 x 32)
-constexpr int kInvKB = 128;     // frames staged per block
+constexpr int kInvKB = 96;      // frames staged per block
 
-__global__ __launch_bounds__(256, 4) void inv_kernel(InvLaunch l)
+__global__ __launch_bounds__(256, 8) void inv_kernel(InvLaunch l)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int64_t blk = l.blk_begin + (int64_t)blockIdx.x;
@@ -1171,6 +1171,11 @@ __global__ __launch_bounds__(256, 4) void inv_kernel(InvLaunch l)
     // the two sample columns of this lane and their offsets to the first frame
     const int s0 = wave * 64 + col;                  // sample within the tile
     const int jb0 = tile_lo - mlo * H + s0;          // n - m_lo H for column 0; column 1 is +32
+    // frames whose windows reach this wave's samples [w_lo, w_lo + 63]; the
+    // other frames of the tile meet g = 0 in every column of the wave
+    const int w_lo = tile_lo + 64 * __builtin_amdgcn_readfirstlane(wave);
+    const int wm_lo = w_lo - M > 0 ? (w_lo - M + H - 1) / H : 0;
+    const int wm_hi = (w_lo + 63 + M) / H;
     const v2 *__restrict__ Trow = reinterpret_cast<const v2 *>(a.T) + (int64_t)(mlo - frame0) * a.n_dst;
     float y0 = 0.f, y1 = 0.f;
     for (int d0 = d_lo; d0 <= d_hi; d0 += 16) {
@@ -1202,12 +1207,16 @@ __global__ __launch_bounds__(256, 4) void inv_kernel(InvLaunch l)
             }
             __syncthreads();
             // j = n - m H for this lane's rows: (jb0 - (kb + kk) H), stepping by 2H
-            int j0 = jb0 - (kb + half) * H;
+            // this wave's frames within the block, from an even k0 (pairs k0, k0 + 1)
+            int kw0 = wm_lo - mlo - kb, kw1 = wm_hi - mlo - kb;
+            kw0 = kw0 > 0 ? kw0 & ~1 : 0;
+            kw1 = kw1 < knp - 1 ? kw1 : knp - 1;
+            int j0 = jb0 - (kb + kw0 + half) * H;
             const unsigned span = 2u * (unsigned)M;
             const float *gt = gtab + M;
             const float *bp = bst + half * 32 + col;
-#pragma unroll 4
-            for (int k0 = 0; k0 < knp; k0 += 2) {
+#pragma unroll 2
+            for (int k0 = kw0; k0 <= kw1; k0 += 2) {
                 const float av = bp[k0 * 32];
                 const int j1 = j0 + 32;
                 const float g0 = ((unsigned)(j0 + M) <= span) ? gt[j0] : 0.f;
