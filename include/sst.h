@@ -160,6 +160,10 @@ sst_status sst_plan_bind(sst_plan_t plan, void *workspace_dev, size_t bytes, voi
  *   colstats double [nframes][3]: sum_l Re T, sum_l Im T, sum_l |T|^2,
  *            accumulated in FP64 from the FP32 row of T
  *   gamma    float [1]: the threshold gamma used by the call
+ *   kernel_events  two hipEvent_t handles (created by the caller), recorded
+ *            on the call's stream right before and right after the launch of
+ *            the fused forward kernel (or of the GEMM-tier kernel), so that
+ *            the caller can time that kernel alone; NULL entries are skipped
  */
 typedef struct {
     float *S;
@@ -167,6 +171,7 @@ typedef struct {
     int32_t *idx;
     double *colstats;
     float *gamma;
+    void *kernel_events[2];
 } sst_fwd_aux;
 
 /*
@@ -178,9 +183,16 @@ typedef struct {
  *            every element of the rows is written (zeros included)
  *   aux      optional outputs, may be NULL
  *   flags    0 or SST_FWD_REUSE_GAMMA
- * With SST_THR_REL_MAX and no SST_FWD_REUSE_GAMMA the call first computes
- * max |S| over ALL frames of x (not only the chunk).  Calls on one plan share
- * the workspace: calls that overlap in time on different streams race.
+ * With SST_THR_REL_MAX and no SST_FWD_REUSE_GAMMA, gamma comes from max |S|
+ * over ALL frames of x (not only the chunk), on the forward kernel's own FP32
+ * arithmetic.  A call over the whole signal (frame0 = 0, nframes = n_frames,
+ * no per-coefficient outputs) computes it speculatively: the maximum over
+ * every 32nd frame group and the running maximum give a lower bound of gamma,
+ * each group records the least |S| it kept, and the groups that kept a
+ * coefficient at or below the final gamma are transformed again -- T is the
+ * same, bit for bit, as with the final gamma given.  Other calls run a
+ * maximum pre-pass over all frames first.  Calls on one plan share the
+ * workspace: calls that overlap in time on different streams race.
  * Errors: SST_E_ARG (range, NULL x/T), SST_E_STATE, SST_E_DEVICE.
  */
 sst_status sst_forward(sst_plan_t plan, const float *x, int64_t frame0, int64_t nframes,

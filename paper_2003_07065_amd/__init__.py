@@ -97,6 +97,7 @@ class FwdAux(ctypes.Structure):
         ("idx", ctypes.c_void_p),
         ("colstats", ctypes.c_void_p),
         ("gamma", ctypes.c_void_p),
+        ("kernel_events", ctypes.c_void_p * 2),
     ]
 
 
@@ -262,8 +263,12 @@ class Plan:
 
     def forward(self, x, T=None, frame0: int = 0, nframes: Optional[int] = None, *,
                 S=None, Sd=None, idx=None, colstats=None, gamma=None,
-                reuse_gamma: bool = False):
-        """SST rows of frames [frame0, frame0+nframes) into T (complex64 [nframes, n_dst])."""
+                reuse_gamma: bool = False, kernel_events=None):
+        """SST rows of frames [frame0, frame0+nframes) into T (complex64 [nframes, n_dst]).
+
+        kernel_events: optional pair of torch.cuda.Event, already recorded once
+        (so that they exist); the library records them again right around the
+        fused forward kernel."""
         import torch
         self._need_bound()
         if nframes is None:
@@ -284,6 +289,11 @@ class Plan:
         if gamma is not None and (gamma.dtype != torch.float32 or gamma.numel() < 1):
             raise ValueError("gamma must be a float32 tensor with one element")
         aux = FwdAux(_ptr(S), _ptr(Sd), _ptr(idx), _ptr(colstats), _ptr(gamma))
+        if kernel_events is not None:
+            for i, ev in enumerate(kernel_events):
+                if not ev.cuda_event:
+                    raise ValueError("kernel_events must have been recorded once")
+                aux.kernel_events[i] = ev.cuda_event
         _check(lib().sst_forward(self._h, ctypes.c_void_p(x.data_ptr()), int(frame0),
                                  int(nframes), ctypes.c_void_p(T.data_ptr()), ctypes.byref(aux),
                                  SST_FWD_REUSE_GAMMA if reuse_gamma else 0,

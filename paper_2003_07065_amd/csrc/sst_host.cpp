@@ -41,6 +41,15 @@ sst_status hip_fail(hipError_t e, const char *what)
 
 constexpr double kTwoPi = 6.283185307179586476925286766559;
 constexpr size_t kAlign = 256;
+// The speculative forward starts from the maximum over every k-th item,
+// k = max(kSeedStep, items / workgroups): one round of the grid at most.
+constexpr int kSeedStep = 32;
+
+int64_t seed_step(int64_t items, int grid_cap)
+{
+    const int64_t k = grid_cap > 0 ? (items + grid_cap - 1) / grid_cap : 1;
+    return k > kSeedStep ? k : kSeedStep;
+}
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -63,6 +72,10 @@ struct sst_plan_s {
     size_t off_desc = 0, off_idesc = 0, off_win = 0, off_twid = 0, off_phlo = 0, off_phhi = 0;
     size_t off_den = 0;
     size_t tables_end = 0, ws_bytes = 0;
+    // speculative threshold (FFT tier): least kept |S|^2 per forward item, the
+    // fix-up list and its count
+    int64_t n_items = 0;
+    size_t off_smin = 0, off_list = 0, off_list_n = 0;
     std::vector<unsigned char> blob;   // host image of [off_win, tables_end)
     // bound state
     unsigned char *ws = nullptr;
@@ -202,6 +215,14 @@ sst::InvDesc inv_desc(const sst_plan_s *pl, const float *T, int64_t frame0, int6
     a.blk0 = 0;
     a.blk_end = (int64_t)n_comp * a.tiles;
     return a;
+}
+
+// Records aux->kernel_events[i] (when given) on stream s.
+hipError_t record_event(const sst_fwd_aux *aux, int i, hipStream_t s)
+{
+    if (!aux || !aux->kernel_events[i])
+        return hipSuccess;
+    return hipEventRecord(reinterpret_cast<hipEvent_t>(aux->kernel_events[i]), s);
 }
 
 // Frames of one call that a tile of output samples can meet (even).
@@ -418,6 +439,15 @@ sst_status sst_plan(const sst_params *params, sst_plan_t *out)
         }
     }
     pl->tables_end = off;
+    if (!gemm) {
+        pl->n_items = (pl->n_frames + sst::fwd_frames_per_iter(NF) - 1) / sst::fwd_frames_per_iter(NF);
+        pl->off_smin = off;
+        off = align_up(off + sizeof(float) * (size_t)pl->n_items);
+        pl->off_list = off;
+        off = align_up(off + sizeof(int32_t) * (size_t)pl->n_items);
+        pl->off_list_n = off;
+        off = align_up(off + sizeof(int32_t));
+    }
     pl->ws_bytes = off;
 
     try {
@@ -541,28 +571,53 @@ sst_status sst_forward(sst_plan_t pl, const float *x, int64_t frame0, int64_t nf
     sst::Ctrl *ctrl = reinterpret_cast<sst::Ctrl *>(pl->ws);
     sst::ChanDesc *slot = reinterpret_cast<sst::ChanDesc *>(pl->ws + pl->off_desc);
     const bool threshold = !(flags & SST_FWD_REUSE_GAMMA);
+    const bool rel = pl->p.thr_mode == SST_THR_REL_MAX;
+    const bool fft = !pl->gemm_ft;
+    const bool debug = aux && (aux->S || aux->Sd || aux->idx || aux->colstats);
+    // A call over the whole signal that needs gamma takes the speculative
+    // forward: threshold at a lower bound of gamma, then redo the items whose
+    // decisions the final gamma changes.
+    const bool spec = threshold && rel && fft && !debug && frame0 == 0 &&
+                      nframes == pl->n_frames && nframes > 0;
     sst::ChanDesc d = chan_desc(pl, x, frame0, nframes, T, aux, ctrl);
     d.item0 = 0;
     d.item_end = (nframes + F - 1) / F;
     d.mitem0 = 0;
-    d.mitem_end = (threshold && pl->p.thr_mode == SST_THR_REL_MAX)
-                      ? ((pl->n_frames + 1) / 2 + F - 1) / F : 0;
-    hipError_t e = sst::launch_put_desc(d, slot, s);
+    // threshold items: forward items of the whole signal (FFT tier) or frame
+    // pairs (the GEMM tiers' two-frames-per-FFT pre-pass)
+    d.mitem_end = !(threshold && rel) ? 0
+                  : fft ? (pl->n_frames + F - 1) / F : ((pl->n_frames + 1) / 2 + F - 1) / F;
+    int32_t *list = fft ? reinterpret_cast<int32_t *>(pl->ws + pl->off_list) : nullptr;
+    int32_t *list_n = fft ? reinterpret_cast<int32_t *>(pl->ws + pl->off_list_n) : nullptr;
+    // the upload also clears the running maximum (and the fix-up count)
+    hipError_t e = sst::launch_put_desc(d, slot, threshold && fft, spec ? list_n : nullptr, s);
     if (e != hipSuccess)
         return hip_fail(e, "descriptor upload");
     sst::GroupLaunch g{};
     g.ch = slot;
     g.n_ch = 1;
     g.twid = reinterpret_cast<const float2 *>(pl->ws + pl->off_twid);
-    if (threshold) {
+    if (threshold && !fft) {
         g.item_begin = 0;
         g.item_stop = d.mitem_end;
         const int grid = (int)(d.mitem_end < pl->max_grid_cap ? d.mitem_end : pl->max_grid_cap);
         e = sst::launch_threshold(NF, pl->p.win_len, g, grid, s);
         if (e != hipSuccess)
             return hip_fail(e, "threshold launch");
+    } else if (threshold) {
+        g.item_begin = 0;
+        g.item_stop = d.mitem_end;
+        g.step = spec ? (int)seed_step(d.mitem_end, pl->fwd_grid_cap) : 1;
+        const int64_t visits = (d.mitem_end + g.step - 1) / g.step;
+        const int grid = (int)(visits < pl->fwd_grid_cap ? visits : pl->fwd_grid_cap);
+        e = sst::launch_max_prepass(NF, pl->p.win_len, g, grid, s);
+        g.step = 0;
+        if (e == hipSuccess && !spec)
+            e = sst::launch_gamma(g, s);
+        if (e != hipSuccess)
+            return hip_fail(e, "threshold launch");
     }
-    if (aux && aux->gamma) {
+    if (aux && aux->gamma && !spec) {
         e = hipMemcpyAsync(aux->gamma, &ctrl->gamma, sizeof(float), hipMemcpyDeviceToDevice, s);
         if (e != hipSuccess)
             return hip_fail(e, "hipMemcpyAsync(gamma)");
@@ -605,18 +660,50 @@ sst_status sst_forward(sst_plan_t pl, const float *x, int64_t frame0, int64_t nf
         const int64_t tiles = (nframes + pl->gemm_ft - 1) / pl->gemm_ft;
         const int grid = (int)(tiles < pl->fwd_grid_cap ? tiles : pl->fwd_grid_cap);
         const bool dbg = aux && (aux->S || aux->Sd || aux->idx);
-        e = sst::launch_gemm_forward(pl->p.precision, pl->gemm_ft, dbg, ga, grid, s);
+        e = record_event(aux, 0, s);
+        if (e == hipSuccess)
+            e = sst::launch_gemm_forward(pl->p.precision, pl->gemm_ft, dbg, ga, grid, s);
+        if (e == hipSuccess)
+            e = record_event(aux, 1, s);
         if (e != hipSuccess)
             return hip_fail(e, "GEMM forward launch");
         return SST_OK;
     }
     g.item_begin = 0;
     g.item_stop = d.item_end;
-    const bool debug = aux && (aux->S || aux->Sd || aux->idx || aux->colstats);
     const int grid = (int)(d.item_end < pl->fwd_grid_cap ? d.item_end : pl->fwd_grid_cap);
-    e = sst::launch_forward(NF, pl->p.win_len, pl->n_src, pl->n_dst, debug, g, grid, s);
+    if (!spec) {
+        e = record_event(aux, 0, s);
+        if (e == hipSuccess)
+            e = sst::launch_forward(NF, pl->p.win_len, pl->n_src, pl->n_dst, debug, g, grid, s);
+        if (e == hipSuccess)
+            e = record_event(aux, 1, s);
+        if (e != hipSuccess)
+            return hip_fail(e, "forward launch");
+        return SST_OK;
+    }
+    g.spec = 1;
+    g.smin = reinterpret_cast<float *>(pl->ws + pl->off_smin);
+    e = record_event(aux, 0, s);
+    if (e == hipSuccess)
+        e = sst::launch_forward(NF, pl->p.win_len, pl->n_src, pl->n_dst, false, g, grid, s);
+    if (e == hipSuccess)
+        e = record_event(aux, 1, s);
+    g.spec = 0;
+    g.list = list;
+    g.list_n = list_n;
+    if (e == hipSuccess)
+        e = sst::launch_spec_list(g, s);   // gamma, then the fix-up list
+    g.smin = nullptr;
+    if (e == hipSuccess)
+        e = sst::launch_forward(NF, pl->p.win_len, pl->n_src, pl->n_dst, false, g, grid, s);
     if (e != hipSuccess)
-        return hip_fail(e, "forward launch");
+        return hip_fail(e, "speculative forward launch");
+    if (aux && aux->gamma) {
+        e = hipMemcpyAsync(aux->gamma, &ctrl->gamma, sizeof(float), hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess)
+            return hip_fail(e, "hipMemcpyAsync(gamma)");
+    }
     return SST_OK;
 }
 
@@ -737,6 +824,9 @@ struct sst_batch_s {
         size_t off_desc = 0;        // ChanDesc[chans.size()]
         std::vector<sst::ChanDesc> desc;
         int fwd_grid_cap = 0, max_grid_cap = 0;
+        // speculative forward: least kept |S|^2 per item of the group, fix-up list
+        int64_t n_items = 0;
+        size_t off_smin = 0, off_list = 0, off_list_n = 0;
     };
     std::vector<sst_plan_s *> plans;
     std::vector<Io> io;
@@ -821,6 +911,14 @@ sst_status sst_batch_plan(const sst_params *params, int32_t n_channels, sst_batc
     for (auto &gr : b->groups) {
         gr.off_desc = off;
         off = align_up(off + sizeof(sst::ChanDesc) * gr.chans.size());
+        for (int c : gr.chans)
+            gr.n_items += b->plans[(size_t)c]->n_items;
+        gr.off_smin = off;
+        off = align_up(off + sizeof(float) * (size_t)gr.n_items);
+        gr.off_list = off;
+        off = align_up(off + sizeof(int32_t) * (size_t)gr.n_items);
+        gr.off_list_n = off;
+        off = align_up(off + sizeof(int32_t));
     }
     b->off_idesc = off;
     off = align_up(off + sizeof(sst::InvDesc) * (size_t)n_channels);
@@ -915,7 +1013,7 @@ sst_status sst_batch_commit(sst_batch_t b, void *stream)
             d.item_end = items;
             d.mitem0 = mitems;
             if (pl->p.thr_mode == SST_THR_REL_MAX)
-                mitems += ((pl->n_frames + 1) / 2 + F - 1) / F;
+                mitems += (pl->n_frames + F - 1) / F;   // max-only pre-pass: forward items
             d.mitem_end = mitems;
             gr.desc[i] = d;
         }
@@ -977,12 +1075,25 @@ sst_status sst_batch_forward(sst_batch_t b, int32_t c_begin, int32_t c_end, uint
         g.ch = reinterpret_cast<const sst::ChanDesc *>(b->ws + gr.off_desc) + i0;
         g.n_ch = (int)(i1 - i0);
         g.twid = reinterpret_cast<const float2 *>(p0->ws + p0->off_twid);
-        if (!(flags & SST_FWD_REUSE_GAMMA)) {
+        // Speculative forward (see sst_forward): the maximum over every
+        // kSeedStep-th item, the forward at the lower bound of gamma it gives,
+        // gamma, then the items whose decisions the final gamma changes.
+        const bool spec = !(flags & SST_FWD_REUSE_GAMMA);
+        int32_t *list = reinterpret_cast<int32_t *>(b->ws + gr.off_list);
+        int32_t *list_n = reinterpret_cast<int32_t *>(b->ws + gr.off_list_n);
+        hipError_t e = hipSuccess;
+        if (spec) {
+            g.list_n = list_n;
+            e = sst::launch_clear_max(g, s);
+            g.list_n = nullptr;
             g.item_begin = gr.desc[i0].mitem0;
             g.item_stop = gr.desc[i1 - 1].mitem_end;
-            const int64_t items = g.item_stop - g.item_begin;
-            const int grid = (int)(items < gr.max_grid_cap ? items : gr.max_grid_cap);
-            hipError_t e = sst::launch_threshold(gr.nfft, gr.max_L, g, grid, s);
+            g.step = (int)seed_step(g.item_stop - g.item_begin, gr.fwd_grid_cap);
+            const int64_t visits = (g.item_stop - g.item_begin + g.step - 1) / g.step;
+            const int grid = (int)(visits < gr.fwd_grid_cap ? visits : gr.fwd_grid_cap);
+            if (e == hipSuccess)
+                e = sst::launch_max_prepass(gr.nfft, gr.max_L, g, grid, s);
+            g.step = 0;
             if (e != hipSuccess)
                 return hip_fail(e, "batched threshold launch");
         }
@@ -990,12 +1101,27 @@ sst_status sst_batch_forward(sst_batch_t b, int32_t c_begin, int32_t c_end, uint
         g.item_stop = gr.desc[i1 - 1].item_end;
         const int64_t items = g.item_stop - g.item_begin;
         const int grid = (int)(items < gr.fwd_grid_cap ? items : gr.fwd_grid_cap);
-        if (grid > 0) {
-            hipError_t e = sst::launch_forward(gr.nfft, gr.max_L, gr.max_n_src, gr.max_n_dst,
-                                               false, g, grid, s);
-            if (e != hipSuccess)
-                return hip_fail(e, "batched forward launch");
+        if (grid <= 0) {
+            if (spec && (e = sst::launch_gamma(g, s)) != hipSuccess)
+                return hip_fail(e, "batched threshold launch");
+            continue;
         }
+        g.spec = spec ? 1 : 0;
+        g.smin = spec ? reinterpret_cast<float *>(b->ws + gr.off_smin) : nullptr;
+        e = sst::launch_forward(gr.nfft, gr.max_L, gr.max_n_src, gr.max_n_dst, false, g, grid, s);
+        g.spec = 0;
+        if (spec) {
+            g.list = list;
+            g.list_n = list_n;
+            if (e == hipSuccess)
+                e = sst::launch_spec_list(g, s);
+            g.smin = nullptr;
+            if (e == hipSuccess)
+                e = sst::launch_forward(gr.nfft, gr.max_L, gr.max_n_src, gr.max_n_dst, false, g,
+                                        grid, s);
+        }
+        if (e != hipSuccess)
+            return hip_fail(e, "batched forward launch");
     }
     return SST_OK;
 }

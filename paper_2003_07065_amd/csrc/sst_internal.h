@@ -52,6 +52,11 @@ struct GroupLaunch {
     int64_t item_begin;     // first item: ch[0].item0 (forward) or ch[0].mitem0 (threshold)
     int64_t item_stop;      // ch[n_ch-1].item_end or .mitem_end
     const float2 *twid;     // [N_f]: exp(-i 2 pi r / N_f), shared by the launch
+    int step;               // max-only pre-pass: visit every step-th item (0 or 1: all)
+    int spec;               // forward: threshold each item at a lower bound of gamma
+    float *smin;            // spec: per item (launch numbering), least |S|^2 kept
+    int32_t *list;          // forward: only the items list[0 .. *list_n) (fix-up pass)
+    int32_t *list_n;        // count of list; cleared by launch_clear_max when non-null
 };
 
 // Per-channel descriptor of the direct inverse (one call's frames of one
@@ -136,9 +141,21 @@ struct RidgeArgs {
 };
 
 // Launchers (sst_kernels.hip).  Each returns the hipError_t of its launch.
-// Threshold: clears maxbits of the launch's channels, runs the pre-pass when
-// `rel_items` > 0 and sets gamma of every channel of the list.
+// Threshold of the GEMM tiers: clears maxbits of the launch's channels, runs
+// the two-frames-per-FFT pre-pass over items [item_begin, item_stop) when
+// there are any and sets gamma of every channel of the list.
 hipError_t launch_threshold(int nfft, int L, const GroupLaunch &g, int grid, hipStream_t s);
+// Pieces of the threshold of the FFT path.  launch_clear_max zeroes maxbits of
+// every channel (and *g.list_n); launch_max_prepass folds max |S|^2 of every
+// g.step-th forward item of the whole signals (items numbered by mitem0, with
+// the forward kernel's own arithmetic) into maxbits; launch_gamma sets gamma.
+hipError_t launch_clear_max(const GroupLaunch &g, hipStream_t s);
+hipError_t launch_max_prepass(int nfft, int L, const GroupLaunch &g, int grid, hipStream_t s);
+hipError_t launch_gamma(const GroupLaunch &g, hipStream_t s);
+// After a speculative forward: sets gamma of every channel (as launch_gamma)
+// and appends to g.list the items whose least kept |S|^2 does not exceed the
+// final gamma^2.
+hipError_t launch_spec_list(const GroupLaunch &g, hipStream_t s);
 // Forward: `debug` selects the variant that writes S, S', idx and colstats;
 // max_n_src / max_n_dst / max_L bound the launch's channels.
 hipError_t launch_forward(int nfft, int max_L, int max_n_src, int max_n_dst, bool debug,
@@ -148,8 +165,10 @@ hipError_t launch_gemm_forward(int prec, int ft, bool debug, const GemmArgs &a, 
                                hipStream_t s);
 size_t gemm_lds_bytes(int prec, int ft, int n_dst, int slab, int L);
 int gemm_occupancy(int prec, int ft, size_t lds);
-// Copy one descriptor into device memory (a kernel, so it can be captured).
-hipError_t launch_put_desc(const ChanDesc &d, ChanDesc *dst, hipStream_t s);
+// Copy one descriptor into device memory (a kernel, so it can be captured);
+// with clear_max also zero d.ctrl->maxbits, and *list_n when non-null.
+hipError_t launch_put_desc(const ChanDesc &d, ChanDesc *dst, bool clear_max, int32_t *list_n,
+                           hipStream_t s);
 // Inverse of the launch list (blocks = ch[n_ch-1].blk_end - blk_begin).
 // Clears err first when `clear_err`.
 hipError_t launch_inverse(const InvLaunch &l, int64_t blocks, bool clear_err, hipStream_t s);

@@ -457,6 +457,77 @@ __device__ __forceinline__ int chan_of(const CA ChanDesc *ch, int n_ch, int c, i
 
 // Per-channel values a workgroup keeps in scalar registers while it works
 // on that channel's items; reloaded only when the channel changes.
+__device__ __forceinline__ float wave_max(float v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ __forceinline__ float wave_min(float v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        v = fminf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Block-wide max of v, then one atomicMax of its float bits into *dst
+// (non-negative floats order like their bit patterns).  Every thread calls it.
+template <int NT>
+__device__ __forceinline__ void block_max_flush(float v, float *red, unsigned *dst)
+{
+    v = wave_max(v);
+    if ((threadIdx.x & 63) == 0)
+        red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float b = red[0];
+        for (int w = 1; w < NT / 64; ++w)
+            b = fmaxf(b, red[w]);
+        atomicMax(dst, __float_as_uint(b));
+    }
+    __syncthreads();
+}
+
+// Wave reductions on the data-parallel primitives (no LDS round trips): xor
+// 1 and xor 2 within quads, rotations by 4 and 8 within rows of 16 lanes,
+// then row 0 -> 1 and row 2 -> 3 and lane 31 -> rows 2, 3.  The reduction
+// of all 64 lanes is left in lane 63.  `id` is the identity of `op`.
+template <int CTRL, int ROWS = 0xf>
+__device__ __forceinline__ float dpp_mov(float old, float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v),
+                                                      CTRL, ROWS, 0xf, false));
+}
+
+template <class Op>
+__device__ __forceinline__ float wave_reduce63(float v, float id, Op op)
+{
+    v = op(v, dpp_mov<0xb1>(id, v));         // quad_perm [1, 0, 3, 2]
+    v = op(v, dpp_mov<0x4e>(id, v));         // quad_perm [2, 3, 0, 1]
+    v = op(v, dpp_mov<0x124>(id, v));        // row_ror 4
+    v = op(v, dpp_mov<0x128>(id, v));        // row_ror 8
+    v = op(v, dpp_mov<0x142, 0xa>(id, v));   // row_bcast 15 into rows 1, 3
+    v = op(v, dpp_mov<0x143, 0xc>(id, v));   // row_bcast 31 into rows 2, 3
+    return v;
+}
+
+// |A|^2 as every threshold decision of the FFT path computes it (one
+// rounding order, so the pre-pass maximum and the forward agree bit for bit).
+__device__ __forceinline__ float mag2_of(v2 A)
+{
+    return __builtin_fmaf(A.x, A.x, A.y * A.y);
+}
+
+// gamma^2 from max |S|^2: rho^2 max (relative) or the given gamma (absolute).
+__device__ __forceinline__ float gamma2_of(int thr_mode, float thr, float max2)
+{
+    const float gm = thr_mode == 1 ? thr * sqrtf(max2) : thr;
+    return gm * gm;
+}
+
 struct Chan {
     const float *x;
     const float2 *win;
@@ -467,8 +538,8 @@ struct Chan {
     double *colstats;
     Ctrl *ctrl;
     int64_t n, n_frames, frame0, nframes, item0, item_end;
-    int L, M, hop, k1, n_src, n_dst, z;
-    float gamma2, inv_s, cdelta, inv_nsrc, inv_ndst;
+    int L, M, hop, k1, n_src, n_dst, z, thr_mode;
+    float gamma2, thr, inv_s, cdelta, inv_nsrc, inv_ndst;
 };
 
 template <bool THRESHOLD>
@@ -486,8 +557,9 @@ __device__ __forceinline__ Chan load_chan(const CA ChanDesc *ch, int c)
     r.ctrl = d.ctrl;
     r.n = d.n;
     r.n_frames = d.n_frames;
-    r.frame0 = d.frame0;
-    r.nframes = d.nframes;
+    // threshold passes cover every frame of the signal
+    r.frame0 = THRESHOLD ? 0 : d.frame0;
+    r.nframes = THRESHOLD ? d.n_frames : d.nframes;
     r.item0 = THRESHOLD ? d.mitem0 : d.item0;
     r.item_end = THRESHOLD ? d.mitem_end : d.item_end;
     r.L = d.L;
@@ -497,6 +569,8 @@ __device__ __forceinline__ Chan load_chan(const CA ChanDesc *ch, int c)
     r.n_src = d.n_src;
     r.n_dst = d.n_dst;
     r.z = d.z;
+    r.thr_mode = d.thr_mode;
+    r.thr = d.thr;
     r.gamma2 = THRESHOLD ? 0.f : ((const CA Ctrl *)d.ctrl)->gamma2;
     r.inv_s = d.inv_s;
     r.cdelta = d.cdelta;
@@ -513,12 +587,25 @@ __device__ __forceinline__ v2 cphase_of(const v2 *lo, const v2 *hi, int t)
     return conjv(cmul(hi[t >> 6], lo[t & 63]));
 }
 
-template <int NF, int NZ, int R, bool DEBUG, bool CHUNKED, bool MULTI>
+// Modes of the forward kernel.
+constexpr int kFwdPlain = 0;     // the forward over items item_begin, item_begin + 1, ...
+constexpr int kFwdMaxOnly = 1;   // threshold pre-pass on the forward's arithmetic
+constexpr int kFwdFixup = 2;     // the forward over the items of a fix-up list
+
+template <int NF, int NZ, int R, bool DEBUG, bool CHUNKED, bool MULTI, int MODE = kFwdPlain>
 // Waves per SIMD: 4 for N_f = 8192 and for N_f = 4096 with at most 8 tap rows
 // (two 8-wave or four 4-wave workgroups fill a CU's LDS), 3 otherwise.  MULTI: the launch may hold several channels (else
 // exactly one).
 __global__ __launch_bounds__(Geo<NF>::NT, DEBUG ? 2 : ((NF == 8192 || (NF == 4096 && NZ < 16)) ? 4 : 3)) void fwd_kernel(GroupLaunch g)
 {
+    // kFwdMaxOnly: the threshold pre-pass on the forward's own arithmetic --
+    // pass 1 and the FFT passes, then max |A|^2 over the band, folded into
+    // maxbits of each channel; items are numbered by mitem0 over the whole
+    // signal.  kFwdFixup: the items of g.list only.
+    constexpr bool MAXONLY = MODE == kFwdMaxOnly;
+    constexpr bool listed = MODE == kFwdFixup;
+    if (listed && (int64_t)blockIdx.x >= (int64_t)*g.list_n)
+        return;   // no entry for this workgroup (the usual case: an empty list)
     using G = Geo<NF>;
     constexpr int F = G::F, NT = G::NT, Q = NF / 16;
     constexpr int HB = G::LDS;        // histogram bins (two 32-bit integers each)
@@ -528,6 +615,7 @@ __global__ __launch_bounds__(Geo<NF>::NT, DEBUG ? 2 : ((NF == 8192 || (NF == 409
     constexpr int NHI = NF / 64;
     __shared__ v2 lds[G::LDS];
     __shared__ float bpart[NT / 64][F];   // per-wave partial bounds, summed in fixed order
+    __shared__ float spart[NT / 64][2];   // per-wave max |S|^2 and least kept |S|^2
     __shared__ double colacc[DEBUG ? 3 * F : 1];
     __shared__ v2 twl[Twiddles<NF>::TW];
     __shared__ v2 clo[64], chi[NHI];   // centre-phase tables (Eq. 9)
@@ -580,10 +668,22 @@ __global__ __launch_bounds__(Geo<NF>::NT, DEBUG ? 2 : ((NF == 8192 || (NF == 409
 
     if (DEBUG && threadIdx.x < 3 * F)
         colacc[threadIdx.x] = 0.0;
-    int64_t it = g.item_begin + blockIdx.x;
-    int c = chan_of<false>(ch, g.n_ch, 0, it);
-    Chan a = load_chan<false>(ch, c);
+    // Items of this workgroup: every gridDim.x-th entry of the fix-up list, or
+    // of item_begin, item_begin + step, ...; item_stop ends the sequence.
+    const int64_t n_list = listed ? (int64_t)*g.list_n : 0;
+    const int64_t st = g.step > 1 ? g.step : 1;
+    auto item_at = [&](int64_t li) -> int64_t {
+        if (listed)
+            return li < n_list ? (int64_t)g.list[li] : g.item_stop;
+        const int64_t v = g.item_begin + li * st;
+        return v < g.item_stop ? v : g.item_stop;
+    };
+    int64_t li = blockIdx.x;
+    int64_t it = item_at(li);
+    int c = chan_of<MAXONLY>(ch, g.n_ch, 0, it);
+    Chan a = load_chan<MAXONLY>(ch, c);
     fetch(it, a, true);
+    float best = 0.f;   // MAXONLY: running max |A|^2 of the current channel
     // Wait here for every load issued so far (tables, first samples), so that
     // inside the loop the samples prefetched by the previous iteration are the
     // only loads the first use has to wait for (vmcnt(0), expcnt and lgkmcnt
@@ -593,16 +693,22 @@ __global__ __launch_bounds__(Geo<NF>::NT, DEBUG ? 2 : ((NF == 8192 || (NF == 409
     // centre phase of bin k1 + tid and the rotation step (F == 1), per channel
     v2 ph0 = mk(1.f, 0.f), ph_step = mk(1.f, 0.f);
     bool new_chan = true;
-    for (; it < g.item_stop; it += gridDim.x) {
+    while (it < g.item_stop) {
         const int64_t m0 = (it - a.item0) * F;   // first frame of the item, relative to frame0
         const int nvalid = (int)((a.nframes - m0) < F ? (a.nframes - m0) : F);
-        const float gamma2 = a.gamma2;
+        float gamma2 = a.gamma2;
+        // Speculative threshold (relative gamma): max |S|^2 seen so far by any
+        // workgroup is at most the final maximum, so the gamma it gives is a
+        // lower bound and keeps a superset of the coefficients.
+        unsigned runbits = 0u;
+        if (MODE == kFwdPlain && g.spec && a.thr_mode == 1)
+            runbits = __hip_atomic_load(&a.ctrl->maxbits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const float inv_nsrc = a.inv_nsrc;
         const float inv_ndst = a.inv_ndst;
         // the previous iteration's store phase is done with the buffer (and,
         // on the first iteration, the staged tables are complete)
         __syncthreads();
-        if (F == 1 && (MULTI ? new_chan : it == g.item_begin + blockIdx.x)) {
+        if (F == 1 && !MAXONLY && new_chan) {
             ph0 = cphase_of(clo, chi, ((a.k1 + (int)threadIdx.x) * a.M) & (NF - 1));
             ph_step = cphase_of(clo, chi, (NT * a.M) & (NF - 1));
         }
@@ -624,16 +730,46 @@ __global__ __launch_bounds__(Geo<NF>::NT, DEBUG ? 2 : ((NF == 8192 || (NF == 409
                 lds[pad16(base) + r] = v[r];   // base: a multiple of 16
         }
         // next iteration's samples, issued before this one's stores
-        const int64_t itn = it + gridDim.x;
+        const int64_t itn = item_at(li + gridDim.x);
         Chan an = a;
-        const bool chg = MULTI && itn < g.item_stop && itn >= a.item_end;
+        const bool chg = MULTI && itn < g.item_stop && (itn >= a.item_end || itn < a.item0);
         if (chg) {
-            c = chan_of<false>(ch, g.n_ch, c, itn);
-            an = load_chan<false>(ch, c);
+            c = chan_of<MAXONLY>(ch, g.n_ch, itn < a.item0 ? 0 : c, itn);
+            an = load_chan<MAXONLY>(ch, c);
         }
         fetch(itn, an, chg);
         __syncthreads();
         tw.passes(lds, twl);
+
+        if constexpr (MAXONLY) {
+            const int EM = nvalid * a.n_src;
+            for (int e = threadIdx.x; e < EM; e += NT) {
+                int f, ik;
+                if constexpr (F == 1) {
+                    f = 0;
+                    ik = e;
+                } else {
+                    split_flat(e, a.n_src, inv_nsrc, f, ik);
+                }
+                const int k = a.k1 + ik;
+                const v2 P = lds[pad16(f * NF + k)];
+                const v2 Qc = conjv(lds[pad16(f * NF + ((NF - k) & (NF - 1)))]);
+                best = fmaxf(best, mag2_of(0.5f * (P + Qc)));
+            }
+            if (chg || itn >= g.item_stop) {
+                // leaving this channel: fold the workgroup's maximum into it
+                block_max_flush<NT>(best, &spart[0][0], &a.ctrl->maxbits);
+                best = 0.f;
+            }
+            a = an;
+            new_chan = chg;
+            it = itn;
+            li += gridDim.x;
+            continue;
+        }
+        const bool spec = MODE == kFwdPlain && g.spec;
+        if (spec)
+            gamma2 = gamma2_of(a.thr_mode, a.thr, __uint_as_float(runbits)) * 0.999999f;
 
         // IF phase: Eqs. 12-13 and 27-29 for every in-band coefficient of the
         // F frames; kept coefficients stay in registers as (key, S).
@@ -647,6 +783,7 @@ __global__ __launch_bounds__(Geo<NF>::NT, DEBUG ? 2 : ((NF == 8192 || (NF == 409
         int key[R];
         v2 sv[R];
         float part[F];
+        float mx = 0.f, mn = __builtin_huge_valf();   // max |S|^2, least kept |S|^2
 #pragma unroll
         for (int f = 0; f < F; ++f)
             part[f] = 0.f;
@@ -692,7 +829,8 @@ __global__ __launch_bounds__(Geo<NF>::NT, DEBUG ? 2 : ((NF == 8192 || (NF == 409
             const v2 A = 0.5f * (P + Qc);
             const v2 D = P - Qc;
             const v2 B = mk(0.5f * D.y, -0.5f * D.x);
-            const float mag2 = A.x * A.x + A.y * A.y;
+            const float mag2 = mag2_of(A);
+            mx = fmaxf(mx, mag2);
             const v2 S = cmul(phk, A);
             int code = -1;
             if (mag2 > gamma2) {
@@ -707,6 +845,7 @@ __global__ __launch_bounds__(Geo<NF>::NT, DEBUG ? 2 : ((NF == 8192 || (NF == 409
                 code = (fabsf(zd) < 1.0e8f && l >= 0 && l < a.n_dst) ? l : -2;
             }
             if (code >= 0) {
+                mn = fminf(mn, mag2);
                 key[i] = (f << SEGF) | (f * a.n_dst + code);
                 sv[i] = S;
                 const float mag1 = fabsf(S.x) + fabsf(S.y);
@@ -723,16 +862,38 @@ __global__ __launch_bounds__(Geo<NF>::NT, DEBUG ? 2 : ((NF == 8192 || (NF == 409
                     a.idx[m0 * a.n_src + (unsigned)e] = code;
             }
         }
+        // wave reductions (results in lane 63)
+        auto add = [](float p, float q) { return p + q; };
 #pragma unroll
-        for (int ff = 0; ff < F; ++ff) {
-            float p = part[ff];
+        for (int ff = 0; ff < F; ++ff)
+            part[ff] = wave_reduce63(part[ff], 0.f, add);
+        if (spec) {
+            mx = wave_reduce63(mx, 0.f, [](float p, float q) { return fmaxf(p, q); });
+            mn = wave_reduce63(mn, __builtin_huge_valf(), [](float p, float q) { return fminf(p, q); });
+            if ((threadIdx.x & 63) == 63) {
+                spart[threadIdx.x >> 6][0] = mx;
+                spart[threadIdx.x >> 6][1] = mn;
+            }
+        }
+        if ((threadIdx.x & 63) == 63) {
 #pragma unroll
-            for (int o = 32; o > 0; o >>= 1)
-                p += __shfl_xor(p, o, 64);
-            if ((threadIdx.x & 63) == 0)
-                bpart[threadIdx.x >> 6][ff] = p;
+            for (int ff = 0; ff < F; ++ff)
+                bpart[threadIdx.x >> 6][ff] = part[ff];
         }
         __syncthreads();   // FFT buffer free, frame bounds complete
+        if (spec && threadIdx.x == 0) {
+            // the item is final if nothing it kept lies at or below the final
+            // gamma; the running maximum grows with the item's
+            float imx = spart[0][0], imn = spart[0][1];
+#pragma unroll
+            for (int wv = 1; wv < NT / 64; ++wv) {
+                imx = fmaxf(imx, spart[wv][0]);
+                imn = fminf(imn, spart[wv][1]);
+            }
+            g.smin[it] = imn;
+            if (imx > __uint_as_float(runbits))
+                atomicMax(&a.ctrl->maxbits, __float_as_uint(imx));
+        }
 
         v2 *__restrict__ trow = reinterpret_cast<v2 *>(a.T) + m0 * (int64_t)a.n_dst;
         // the bound is summed in a fixed order so the scale, hence T, is
@@ -828,38 +989,57 @@ __global__ __launch_bounds__(Geo<NF>::NT, DEBUG ? 2 : ((NF == 8192 || (NF == 409
         }
         a = an;
         new_chan = chg;
+        it = itn;
+        li += gridDim.x;
+    }
+}
+
+// Fix-up list of a speculative forward: items whose least kept |S|^2 is at or
+// below the channel's final gamma^2 (one atomic per wave appends them).  The
+// final gamma follows from maxbits as in gamma_kernel; workgroup 0 also writes
+// it into the channels' control blocks.
+__global__ __launch_bounds__(256) void spec_list_kernel(GroupLaunch g)
+{
+    const CA ChanDesc *ch = (const CA ChanDesc *)g.ch;
+    const int lane = threadIdx.x & 63;
+    if (blockIdx.x == 0) {
+        for (int cc = threadIdx.x; cc < g.n_ch; cc += 256) {
+            Ctrl *ctrl = g.ch[cc].ctrl;
+            const float m2 = __uint_as_float(ctrl->maxbits);
+            const float gm = g.ch[cc].thr_mode == 1 ? g.ch[cc].thr * sqrtf(m2) : g.ch[cc].thr;
+            ctrl->maxabs2 = m2;
+            ctrl->gamma = gm;
+            ctrl->gamma2 = gamma2_of(g.ch[cc].thr_mode, g.ch[cc].thr, m2);
+        }
+    }
+    int c = 0;
+    for (int64_t base = g.item_begin + (int64_t)blockIdx.x * 256 + (threadIdx.x & ~63);
+         base < g.item_stop; base += (int64_t)gridDim.x * 256) {
+        const int64_t it = base + lane;
+        bool redo = false;
+        if (it < g.item_stop) {
+            while (c < g.n_ch - 1 && it >= ch[c].item_end)
+                ++c;
+            const float m2 = __uint_as_float(__hip_atomic_load(&g.ch[c].ctrl->maxbits, __ATOMIC_RELAXED,
+                                                               __HIP_MEMORY_SCOPE_AGENT));
+            redo = g.smin[it] <= gamma2_of(ch[c].thr_mode, ch[c].thr, m2);
+        }
+        const unsigned long long bal = __ballot(redo);
+        if (bal == 0ull)
+            continue;
+        int at = 0;
+        if (lane == 0)
+            at = atomicAdd(g.list_n, __popcll(bal));
+        at = __shfl(at, 0, 64);
+        if (redo)
+            g.list[at + __popcll(bal & ((1ull << lane) - 1ull))] = (int32_t)it;
     }
 }
 
 // ---------------------------------------------------------------------------
-// Threshold pre-pass: max |S|^2 over all frames, two frames per complex FFT.
+// Threshold pre-pass of the GEMM tiers: max |S|^2 over all frames, two frames
+// per complex FFT.
 // ---------------------------------------------------------------------------
-
-__device__ __forceinline__ float wave_max(float v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1)
-        v = fmaxf(v, __shfl_xor(v, o, 64));
-    return v;
-}
-
-// Block-wide max of v, then one atomicMax of its float bits into *dst
-// (non-negative floats order like their bit patterns).  Every thread calls it.
-template <int NT>
-__device__ __forceinline__ void block_max_flush(float v, float *red, unsigned *dst)
-{
-    v = wave_max(v);
-    if ((threadIdx.x & 63) == 0)
-        red[threadIdx.x >> 6] = v;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        float b = red[0];
-        for (int w = 1; w < NT / 64; ++w)
-            b = fmaxf(b, red[w]);
-        atomicMax(dst, __float_as_uint(b));
-    }
-    __syncthreads();
-}
 
 template <int NF, int NZ>
 __global__ __launch_bounds__(Geo<NF>::NT, (NF == 8192 || (NF == 4096 && NZ < 16)) ? 4 : 3) void max_kernel(GroupLaunch g)
@@ -975,12 +1155,14 @@ __global__ __launch_bounds__(Geo<NF>::NT, (NF == 8192 || (NF == 4096 && NZ < 16)
     }
 }
 
-// Clear the running maxima of the launch's channels.
+// Clear the running maxima of the launch's channels (and the fix-up count).
 __global__ __launch_bounds__(256) void clear_max_kernel(GroupLaunch g)
 {
     const int c = blockIdx.x * 256 + threadIdx.x;
     if (c < g.n_ch)
         g.ch[c].ctrl->maxbits = 0u;
+    if (c == 0 && g.list_n)
+        *g.list_n = 0;
 }
 
 // gamma of every channel: rho sqrt(max |S|^2) (relative) or the given value.
@@ -994,14 +1176,20 @@ __global__ __launch_bounds__(256) void gamma_kernel(GroupLaunch g)
     const float gm = g.ch[c].thr_mode == 1 ? g.ch[c].thr * sqrtf(m2) : g.ch[c].thr;
     ctrl->maxabs2 = m2;
     ctrl->gamma = gm;
-    ctrl->gamma2 = gm * gm;
+    ctrl->gamma2 = gamma2_of(g.ch[c].thr_mode, g.ch[c].thr, m2);
 }
 
 // Write one descriptor into device memory.
-__global__ __launch_bounds__(64) void put_desc_kernel(ChanDesc d, ChanDesc *dst)
+__global__ __launch_bounds__(64) void put_desc_kernel(ChanDesc d, ChanDesc *dst, int clear,
+                                                      int32_t *list_n)
 {
-    if (threadIdx.x == 0)
+    if (threadIdx.x == 0) {
         *dst = d;
+        if (clear)
+            d.ctrl->maxbits = 0u;
+        if (list_n)
+            *list_n = 0;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1215,7 +1403,7 @@ __global__ __launch_bounds__(256, 8) void inv_kernel(InvLaunch l)
             const unsigned span = 2u * (unsigned)M;
             const float *gt = gtab + M;
             const float *bp = bst + half * 32 + col;
-#pragma unroll 2
+#pragma unroll 1
             for (int k0 = kw0; k0 <= kw1; k0 += 2) {
                 const float av = bp[k0 * 32];
                 const int j1 = j0 + 32;
@@ -1403,7 +1591,11 @@ hipError_t launch_fwd_nzm(int max_n_src, int max_n_dst, bool debug, const GroupL
 {
     const dim3 g(grid), b(Geo<NF>::NT);
     const bool chunked = (int64_t)Geo<NF>::F * max_n_dst > Geo<NF>::LDS;
-    if (debug) {
+    if (gl.list) {
+        // fix-up pass: the general variant (any row length, nine rounds) gives
+        // every row bit for bit what the variant chosen below gives
+        hipLaunchKernelGGL((fwd_kernel<NF, NZ, 9, false, true, MULTI, kFwdFixup>), g, b, 0, s, gl);
+    } else if (debug) {
         hipLaunchKernelGGL((fwd_kernel<NF, NZ, 9, true, true, MULTI>), g, b, 0, s, gl);
     } else if (chunked) {
         hipLaunchKernelGGL((fwd_kernel<NF, NZ, 9, false, true, MULTI>), g, b, 0, s, gl);
@@ -1433,6 +1625,27 @@ hipError_t launch_fwd_t(int max_L, int max_n_src, int max_n_dst, bool debug, con
     case 4: return launch_fwd_nz<NF, 4>(max_n_src, max_n_dst, debug, gl, grid, s);
     case 8: return launch_fwd_nz<NF, 8>(max_n_src, max_n_dst, debug, gl, grid, s);
     default: return launch_fwd_nz<NF, 16>(max_n_src, max_n_dst, debug, gl, grid, s);
+    }
+}
+
+template <int NF, int NZ>
+hipError_t launch_maxonly_nz(const GroupLaunch &gl, int grid, hipStream_t s)
+{
+    const dim3 g(grid), b(Geo<NF>::NT);
+    if (gl.n_ch > 1)
+        hipLaunchKernelGGL((fwd_kernel<NF, NZ, 3, false, false, true, kFwdMaxOnly>), g, b, 0, s, gl);
+    else
+        hipLaunchKernelGGL((fwd_kernel<NF, NZ, 3, false, false, false, kFwdMaxOnly>), g, b, 0, s, gl);
+    return hipGetLastError();
+}
+
+template <int NF>
+hipError_t launch_maxonly_t(int L, const GroupLaunch &gl, int grid, hipStream_t s)
+{
+    switch (nz_rows<NF>(L)) {
+    case 4: return launch_maxonly_nz<NF, 4>(gl, grid, s);
+    case 8: return launch_maxonly_nz<NF, 8>(gl, grid, s);
+    default: return launch_maxonly_nz<NF, 16>(gl, grid, s);
     }
 }
 
@@ -1515,6 +1728,38 @@ hipError_t launch_threshold(int nfft, int L, const GroupLaunch &g, int grid, hip
     return hipGetLastError();
 }
 
+hipError_t launch_clear_max(const GroupLaunch &g, hipStream_t s)
+{
+    const unsigned cb = (unsigned)((g.n_ch + 255) / 256);
+    hipLaunchKernelGGL(clear_max_kernel, dim3(cb), dim3(256), 0, s, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_max_prepass(int nfft, int L, const GroupLaunch &g, int grid, hipStream_t s)
+{
+    if (g.item_stop <= g.item_begin || grid <= 0)
+        return hipSuccess;
+    SST_DISPATCH_NF(nfft, return launch_maxonly_t<NFv>(L, g, grid, s))
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_gamma(const GroupLaunch &g, hipStream_t s)
+{
+    const unsigned cb = (unsigned)((g.n_ch + 255) / 256);
+    hipLaunchKernelGGL(gamma_kernel, dim3(cb), dim3(256), 0, s, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_spec_list(const GroupLaunch &g, hipStream_t s)
+{
+    // at least one workgroup: workgroup 0 sets gamma
+    const int64_t items = g.item_stop > g.item_begin ? g.item_stop - g.item_begin : 0;
+    const int64_t blocks = items > 0 ? (items + 255) / 256 : 1;
+    hipLaunchKernelGGL(spec_list_kernel, dim3((unsigned)(blocks < 1024 ? blocks : 1024)),
+                       dim3(256), 0, s, g);
+    return hipGetLastError();
+}
+
 hipError_t launch_forward(int nfft, int max_L, int max_n_src, int max_n_dst, bool debug,
                           const GroupLaunch &g, int grid, hipStream_t s)
 {
@@ -1522,9 +1767,10 @@ hipError_t launch_forward(int nfft, int max_L, int max_n_src, int max_n_dst, boo
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_put_desc(const ChanDesc &d, ChanDesc *dst, hipStream_t s)
+hipError_t launch_put_desc(const ChanDesc &d, ChanDesc *dst, bool clear_max, int32_t *list_n,
+                           hipStream_t s)
 {
-    hipLaunchKernelGGL(put_desc_kernel, dim3(1), dim3(64), 0, s, d, dst);
+    hipLaunchKernelGGL(put_desc_kernel, dim3(1), dim3(64), 0, s, d, dst, clear_max ? 1 : 0, list_n);
     return hipGetLastError();
 }
 

@@ -463,3 +463,54 @@ def test_c3_full_size_sampled(sst):
         snr = 10 * math.log10(np.sum(ref ** 2) / np.sum((ref - xh_g[q]) ** 2))
         _say(f"  harmonic {q + 1}: inverse relF on [{a}, {b}) = {e:.2e}, SNR there {snr:.1f} dB")
         assert e <= 1e-5
+
+
+def test_speculative_threshold_fixup(sst):
+    """The speculative forward with a large fix-up pass.  Unit white noise plus
+    one impulse of 15000 at the centre of frame 8208 (N = 2^18, the c2
+    configuration, one frame per item): the pre-pass samples every 32nd item,
+    whose nearest frames lie 16 frames from the impulse, so it sees about 0.14
+    of max |S|.  gamma = 1e-3 max |S| ~ 15 sits in the bulk of the noise
+    coefficients (|S| rms ~ 15), so the items run before the impulse's frames
+    keep coefficients that the final gamma drops and are redone.  The result
+    must equal, bit for bit, the forward given the final gamma, and match the
+    oracle (with that gamma) on frames at the start, around the impulse and at
+    the end; gamma must match the oracle's, whose maximum lies at the impulse."""
+    from workloads import make_c2
+    cfg = make_c2(n=1 << 12).cfg
+    n = 1 << 18
+    m_star = 8208
+    rng = np.random.default_rng(7)
+    x = rng.standard_normal(n).astype(np.float32)
+    x[m_star * cfg.hop] += 15000.0
+    plan = sst.Plan.from_config(n, cfg, device="cuda")
+    xg = torch.from_numpy(x).cuda()
+    gam = torch.empty(1, dtype=torch.float32, device="cuda")
+    T = plan.forward(xg, gamma=gam)
+    T2 = torch.full_like(T, float("nan"))
+    plan.forward(xg, T2, reuse_gamma=True)
+    torch.cuda.synchronize()
+    same = torch.equal(torch.view_as_real(T), torch.view_as_real(T2))
+    gamma_g = float(gam.cpu()[0])
+    x64 = x.astype(np.float64)
+    o_peak = oracle.forward(x64, cfg, m_star - 40, 80)
+    _say(f"[spec] gamma GPU {gamma_g:.6g} oracle {o_peak.gamma:.6g}; speculative == exact-gamma "
+         f"forward: {same}")
+    assert same
+    assert abs(gamma_g - o_peak.gamma) <= 1e-5 * o_peak.gamma
+    g_o, gd_o = oracle.gaussian_windows(cfg.win_len, cfg.sigma)
+    s_pack = math.sqrt(np.sum(g_o ** 2) / np.sum(gd_o ** 2))
+    nfr = 32
+    for f0 in (0, m_star - 16, plan.n_frames - nfr):
+        S = torch.empty((nfr, plan.n_src), dtype=torch.complex64, device="cuda")
+        idx = torch.empty((nfr, plan.n_src), dtype=torch.int32, device="cuda")
+        plan.forward(xg, None, f0, nfr, S=S, idx=idx, reuse_gamma=True)
+        torch.cuda.synchronize()
+        o = oracle.forward(x64, cfg, f0, nfr, gamma=gamma_g)
+        idx_g = idx.cpu().numpy()
+        ny = packed_norms(x, g_o, gd_o, s_pack, cfg.hop, np.arange(f0, f0 + nfr))
+        rep, _ = classify_indices(idx_g, o.idx, o.frac, o.S, o.Sd, o.gamma, cfg.nfft,
+                                  cfg.subdiv, s_pack, ny, plan.n_dst)
+        e_t = relf(T[f0:f0 + nfr].cpu().numpy(), reconciled_T(o.S, idx_g, plan.n_dst))
+        _say(f"  frames {f0}+{nfr}: T(reconciled) relF={e_t:.2e} {rep}")
+        assert e_t <= 1e-5 and rep.ok(), (rep, rep.details)
