@@ -1538,43 +1538,70 @@ __global__ void zero_f64(double *p, int count)
 }
 
 // ---------------------------------------------------------------------------
-// Ridge: one wave per (frame, component).
+// Ridge: a 16-lane row per (frame, component).
 // ---------------------------------------------------------------------------
+
+// 64-bit key max over the 16 lanes of each DPP row (rotations by 1, 2, 4, 8);
+// every lane of the row ends with the row's maximum.
+__device__ __forceinline__ unsigned long long row_max_u64(unsigned long long k)
+{
+#define SST_ROW_STEP(CTRL)                                                                    \
+    {                                                                                         \
+        const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)k, CTRL,  \
+                                                                  0xf, 0xf, false);           \
+        const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(k >> 32), \
+                                                                  CTRL, 0xf, 0xf, false);     \
+        const unsigned long long o = ((unsigned long long)hi << 32) | lo;                     \
+        k = o > k ? o : k;                                                                    \
+    }
+    SST_ROW_STEP(0x121)
+    SST_ROW_STEP(0x122)
+    SST_ROW_STEP(0x124)
+    SST_ROW_STEP(0x128)
+#undef SST_ROW_STEP
+    return k;
+}
+
+// Ridge of component q (Sec. 2.2, zone M_q[m]): per frame, the destination of
+// largest |T|^2 in [lo, hi], ties to the smallest l, -1 when all are zero.
+// A 16-lane row per frame (lanes across the band), four frames per wave, four
+// passes per workgroup (64 frames); the key (|T|^2 bits, ~l) orders by
+// magnitude, then by smallest l.
+constexpr int kRidgeFrames = 64;   // frames per workgroup
 
 __global__ __launch_bounds__(256) void ridge_kernel(RidgeArgs a)
 {
     const int q = blockIdx.y;
-    const int64_t m = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (m >= a.nframes)
-        return;
     int lo = a.band[2 * q], hi = a.band[2 * q + 1];
     if (lo < 0)
         lo = 0;
     if (hi > a.n_dst - 1)
         hi = a.n_dst - 1;
-    const v2 *__restrict__ row = reinterpret_cast<const v2 *>(a.T) + m * a.n_dst;
-    float best = 0.f;
-    int arg = 0x7fffffff;
-    for (int l = lo + lane; l <= hi; l += 64) {
-        const v2 v = row[l];
-        const float m2 = v.x * v.x + v.y * v.y;
-        if (m2 > best) {
-            best = m2;
-            arg = l;
+    const int sub = threadIdx.x & 15;
+    const int64_t m0 = (int64_t)blockIdx.x * kRidgeFrames + (threadIdx.x >> 4);
+    unsigned long long key[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        const int64_t m = m0 + 16 * p;
+        key[p] = 0ull;
+        if (m < a.nframes) {
+            const v2 *__restrict__ row = reinterpret_cast<const v2 *>(a.T) + m * a.n_dst;
+            for (int l = lo + sub; l <= hi; l += 16) {
+                const v2 v = row[l];
+                const float m2 = v.x * v.x + v.y * v.y;
+                const unsigned long long k =
+                    ((unsigned long long)__float_as_uint(m2) << 32) | (unsigned)~l;
+                key[p] = k > key[p] ? k : key[p];
+            }
         }
     }
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        const float ob = __shfl_xor(best, o, 64);
-        const int oa = __shfl_xor(arg, o, 64);
-        if (ob > best || (ob == best && oa < arg)) {
-            best = ob;
-            arg = oa;
-        }
+    for (int p = 0; p < 4; ++p) {
+        const unsigned long long k = row_max_u64(key[p]);
+        const int64_t m = m0 + 16 * p;
+        if (sub == 0 && m < a.nframes)
+            a.ridge[(int64_t)q * a.nframes + m] = (k >> 32) != 0ull ? (int)~(unsigned)k : -1;
     }
-    if (lane == 0)
-        a.ridge[(int64_t)q * a.nframes + m] = best > 0.f ? arg : -1;
 }
 
 // Non-zero input rows of pass 1 for window length L: 4, 8 or 16.
@@ -1816,7 +1843,7 @@ hipError_t launch_put_inv_desc(const InvDesc &d, InvDesc *dst, hipStream_t s)
 
 hipError_t launch_ridge(const RidgeArgs &a, hipStream_t s)
 {
-    const int64_t blocks = (a.nframes + 3) / 4;
+    const int64_t blocks = (a.nframes + kRidgeFrames - 1) / kRidgeFrames;
     hipLaunchKernelGGL(ridge_kernel, dim3((unsigned)blocks, a.n_comp), dim3(256), 0, s, a);
     return hipGetLastError();
 }
