@@ -67,6 +67,8 @@ struct sst_plan_s {
     // DFT-as-GEMM tier
     int gemm_ft = 0, row_tiles = 0, ksteps = 0, slab = 0;
     float unscale_g = 1.f, unscale_gd = 1.f, gmax2 = 0.f;
+    // inverse: power of two that puts the window's largest |g| in [2^13, 2^14)
+    float inv_g_scale = 1.f, inv_g_unscale = 1.f;
     size_t off_afrag = 0, off_afrag_lo = 0, afrag_bytes = 0;
     // workspace layout (bytes): control block, descriptor slot, tables
     size_t off_desc = 0, off_idesc = 0, off_win = 0, off_twid = 0, off_phlo = 0, off_phhi = 0;
@@ -197,6 +199,8 @@ sst::InvDesc inv_desc(const sst_plan_s *pl, const float *T, int64_t frame0, int6
     a.g_pow2 = is_pow2(pl->G) ? 1 : 0;
     a.inv_G = (float)(1.0 / pl->G);
     a.inv_nfft = (float)(1.0 / pl->p.nfft);
+    a.g_scale = pl->inv_g_scale;
+    a.g_unscale = pl->inv_g_unscale;
     a.accumulate = accumulate ? 1 : 0;
     if (frame0 == 0 && nframes == pl->n_frames) {
         a.span_lo = 0;
@@ -461,8 +465,18 @@ sst_status sst_plan(const sst_params *params, sst_plan_t *out)
         f[2 * i] = (float)re;
         f[2 * i + 1] = (float)im;
     };
-    for (int i = 0; i < L; ++i)
+    double mgi = 0.0;
+    for (int i = 0; i < L; ++i) {
         put(pl->off_win, i, g[i], pl->s_pack * gd[i]);
+        mgi = std::max(mgi, std::fabs((double)(float)g[i]));
+    }
+    {
+        int eg = 0;
+        std::frexp(mgi, &eg);   // mgi < 2^eg
+        const int tg = mgi > 0.0 ? 14 - eg : 0;
+        pl->inv_g_scale = (float)std::ldexp(1.0, tg);
+        pl->inv_g_unscale = (float)std::ldexp(1.0, -tg);
+    }
     for (int r = 0; r < NF; ++r) {
         const double a = kTwoPi * (double)r / NF;
         put(pl->off_twid, r, std::cos(a), -std::sin(a));

@@ -86,6 +86,8 @@ struct InvDesc {
     int g_pow2;             // G is a power of two
     float inv_G;            // 1/G
     float inv_nfft;
+    float g_scale;          // 2^tg: the window's largest |g[j]| 2^tg lies in [2^13, 2^14)
+    float g_unscale;        // 2^-tg
     int accumulate;         // add into xhat
     int pad_;
 };

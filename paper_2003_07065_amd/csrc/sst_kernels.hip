@@ -465,14 +465,6 @@ __device__ __forceinline__ float wave_max(float v)
     return v;
 }
 
-__device__ __forceinline__ float wave_min(float v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1)
-        v = fminf(v, __shfl_xor(v, o, 64));
-    return v;
-}
-
 // Block-wide max of v, then one atomicMax of its float bits into *dst
 // (non-negative floats order like their bit patterns).  Every thread calls it.
 template <int NT>
@@ -1268,22 +1260,65 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 //   Z[d, n] = sum_m c~[m, d] g[n - mH],  c~[m, d] = (a_l / N_f) T[m, l] e^{-i 2 pi b m H / G}
 // (zero outside the frame's zone).  Z is the product of the coefficient matrix
 // (16 bins x real/imaginary = 32 rows, frames) with the banded window matrix
-// (frames x samples), run on the 32x32x2 FP32 MFMA (FP32 products and sums,
-// as the vector path), frames in blocks of KB staged in LDS.  Each lane then
-// holds 16 of the 32 rows of one sample column: the sum over bins is 16
+// (frames x samples), run on the 32x32x16 FP16 MFMA with both operands split:
+// v 2^s = hi + lo, each an FP16 number (hi the rounding of v 2^s, lo that of
+// the remainder), so hi + lo carries 22 significant bits, and the three
+// products hi hi + hi lo + lo hi are exact in the FP32 accumulator (the
+// dropped lo lo is below 2^-22 of the term).  The coefficients' power of two
+// 2^s puts the block's largest one just under 2^14; the window's, 2^tg, is
+// fixed on the host.  Frames come in blocks of KB staged in LDS as FP16 rows
+// (frames contiguous, so a lane's 8 frames are one 16-byte read).  Each lane
+// then holds 16 of the 32 rows of one sample column: the sum over bins is 16
 // multiply-adds in registers and one exchange with the lane holding the other
-// 16 rows.  Phase indices are reduced mod G in integers.  Lane layout (checked
-// on the hardware): A lane l = row l mod 32, k = l / 32; B lane l = k l / 32,
-// column l mod 32; accumulator i = row 8 (i / 4) + 4 (l / 32) + i mod 4,
-// column l mod 32.
+// 16 rows.  Phase indices are reduced mod G in integers.  Lane layout
+// (checked on the hardware): A lane l = row l mod 32, k = 8 (l / 32) .. + 7;
+// B lane l = the same k, column l mod 32; accumulator i = row
+// 8 (i / 4) + 4 (l / 32) + i mod 4, column l mod 32.
 //
 // Denominator: for samples whose frames all exist it depends on n mod H only
 // and comes from a table built on the host in float64; near the ends of the
 // signal it is summed here.
-constexpr int kInvTile = 256;   // output samples per workgroup (4 waves x 2 x 32)
-constexpr int kInvKB = 96;      // frames staged per block
+constexpr int kInvTile = 256;                  // output samples per workgroup (4 waves x 2 x 32)
+constexpr int kInvKB = 96;                     // frames staged per block (a multiple of 16)
+constexpr int kInvKBP = kInvKB + 8;            // padded row of staged halves
+constexpr int kInvStage = kInvKB * 16 / 256;   // staged coefficients per thread and block
 
-__global__ __launch_bounds__(256, 8) void inv_kernel(InvLaunch l)
+typedef _Float16 f16x8v __attribute__((ext_vector_type(8)));
+typedef unsigned u4v_t __attribute__((ext_vector_type(4)));
+
+// v ~ hi + lo in FP16 (|v| < 2^15), as bit patterns
+__device__ __forceinline__ void split_f16(float v, unsigned &hi, unsigned &lo)
+{
+    const _Float16 h = (_Float16)v;
+    hi = __builtin_bit_cast(unsigned short, h);
+    lo = __builtin_bit_cast(unsigned short, (_Float16)(v - (float)h));
+}
+
+// LDS layout of the inverse (byte offsets, each 16-byte aligned).
+struct InvLds {
+    size_t gpk, rid, ahi, alo, fred, red, total;
+};
+__host__ __device__ inline size_t inv_align16(size_t v)
+{
+    return (v + 15) & ~(size_t)15;
+}
+__host__ __device__ inline InvLds inv_lds_layout(int max_tab, int max_L, int max_k)
+{
+    InvLds o;
+    o.gpk = inv_align16(8 * (size_t)max_tab);
+    o.rid = inv_align16(o.gpk + 4 * ((size_t)max_L + 2));
+    o.ahi = inv_align16(o.rid + 4 * (size_t)max_k);
+    o.alo = o.ahi + 2 * 32 * (size_t)kInvKBP;
+    o.fred = inv_align16(o.alo + 2 * 32 * (size_t)kInvKBP);
+    o.red = o.fred + 16;
+    o.total = o.red + 16;
+    return o;
+}
+
+// ONE: every tile's frames fit one staged block (K <= KB), so the sums start
+// after the staging and need no registers during it.
+template <bool ONE>
+__global__ __launch_bounds__(256, ONE ? 5 : 4) void inv_kernel(InvLaunch l)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int64_t blk = l.blk_begin + (int64_t)blockIdx.x;
@@ -1291,12 +1326,15 @@ __global__ __launch_bounds__(256, 8) void inv_kernel(InvLaunch l)
     const CA InvDesc &a = chs[inv_chan_of(chs, l.n_ch, blk)];
     const int nlo = 1 << a.lo_bits;
     const int nhi = (a.G + nlo - 1) >> a.lo_bits;
+    const InvLds lay = inv_lds_layout(l.max_tab, l.max_L, l.max_k);
     v2 *tlo = reinterpret_cast<v2 *>(smem);
     v2 *thi = tlo + nlo;
-    float *gtab = reinterpret_cast<float *>(tlo + l.max_tab);   // [L]
-    int *rid = reinterpret_cast<int *>(gtab + l.max_L);         // [max_k]
-    float *bst = reinterpret_cast<float *>(rid + l.max_k);      // [kInvKB][32]
-    int *red = reinterpret_cast<int *>(bst + 32 * kInvKB);      // [2]
+    unsigned *gpk = reinterpret_cast<unsigned *>(smem + lay.gpk);   // [L + 2]: window, packed
+    int *rid = reinterpret_cast<int *>(smem + lay.rid);             // [max_k]
+    unsigned short *ahi = reinterpret_cast<unsigned short *>(smem + lay.ahi);   // [32][KBP]
+    unsigned short *alo = reinterpret_cast<unsigned short *>(smem + lay.alo);   // [32][KBP]
+    float *fred = reinterpret_cast<float *>(smem + lay.fred);       // [4]
+    int *red = reinterpret_cast<int *>(smem + lay.red);             // [2]
 
     // Signals hold fewer than 2^30 samples and n_comp * tiles < 2^31 (checked
     // by the host), so sample, frame and tile indices fit 32 bits.
@@ -1312,12 +1350,25 @@ __global__ __launch_bounds__(256, 8) void inv_kernel(InvLaunch l)
     const int frame0 = (int)a.frame0, nfr = (int)a.nframes, nframes_all = (int)a.n_frames;
     const v2 *__restrict__ win = reinterpret_cast<const v2 *>(a.win);
 
+#pragma unroll 2
     for (int e = threadIdx.x; e < nlo; e += 256)
         tlo[e] = reinterpret_cast<const v2 *>(a.ph_lo)[e];
+#pragma unroll 2
     for (int e = threadIdx.x; e < nhi; e += 256)
         thi[e] = reinterpret_cast<const v2 *>(a.ph_hi)[e];
-    for (int e = threadIdx.x; e < a.L; e += 256)
-        gtab[e] = win[e].x;
+    // gpk[j + M + 1] = g[j] 2^tg as FP16 hi | lo << 16 for |j| <= M, zero at
+    // j = -M - 1 and M + 1 (indices outside the window are clamped there)
+    const float gsc = a.g_scale;
+#pragma unroll 4
+    for (int e = threadIdx.x; e < a.L + 2; e += 256) {
+        unsigned w = 0u;
+        if (e >= 1 && e <= a.L) {
+            unsigned h, lw;
+            split_f16(win[e - 1].x * gsc, h, lw);
+            w = h | (lw << 16);
+        }
+        gpk[e] = w;
+    }
 
     // Frames of this call whose window reaches the tile.
     int mlo = tile_lo - M > 0 ? (tile_lo - M + H - 1) / H : 0;
@@ -1365,20 +1416,34 @@ __global__ __launch_bounds__(256, 8) void inv_kernel(InvLaunch l)
     const int wm_lo = w_lo - M > 0 ? (w_lo - M + H - 1) / H : 0;
     const int wm_hi = (w_lo + 63 + M) / H;
     const v2 *__restrict__ Trow = reinterpret_cast<const v2 *>(a.T) + (int64_t)(mlo - frame0) * a.n_dst;
+    const unsigned short *aph = ahi + col * kInvKBP + 8 * half;   // this lane's A row and k chunk
+    const unsigned short *apl = alo + col * kInvKBP + 8 * half;
     float y0 = 0.f, y1 = 0.f;
     for (int d0 = d_lo; d0 <= d_hi; d0 += 16) {
-        f32x16 acc0 = {}, acc1 = {};
-        for (int kb = 0; kb < K; kb += kInvKB) {
+        f32x16 acc0, acc1;
+        if constexpr (!ONE) {
+            acc0 = f32x16{};
+            acc1 = f32x16{};
+        }
+        int sc = 0;   // accumulators hold Z 2^(sc + tg)
+        for (int kb = 0; kb < (ONE ? 1 : K); kb += kInvKB) {
             const int kn = K - kb < kInvKB ? K - kb : kInvKB;
-            const int knp = (kn + 1) & ~1;
-            __syncthreads();   // bst of the previous block consumed
-            // c~[m, d] of this block: 16 destinations, real and imaginary rows
-            for (int e = threadIdx.x; e < knp * 16; e += 256) {
+            const int kn16 = (kn + 15) & ~15;
+            // an opaque copy of the thread index keeps the compiler from
+            // hoisting the staging indices out of the loops (and spilling them)
+            int tid = threadIdx.x;
+            asm volatile("" : "+v"(tid));
+            // c~[m, d] of this block in registers: 16 destinations per frame
+            float cre[kInvStage], cim[kInvStage];
+            float amax = 0.f;
+#pragma unroll
+            for (int i = 0; i < kInvStage; ++i) {
+                const int e = tid + 256 * i;
                 const int kk = e >> 4, dd = e & 15;
                 const int k = kb + kk;
                 const int ld = d0 + dd;
                 v2 c = mk(0.f, 0.f);
-                const int r = k < K ? rid[k] : -1;
+                const int r = (kk < kn && k < K) ? rid[k] : -1;
                 if (r >= 0 && ld <= d_hi && ld >= r - a.hw && ld <= r + a.hw) {
                     const int b = zk1 + ld;   // < z (k2 + 1) <= G
                     const float wgt = (b == 0 || 2 * b == Gi) ? 1.f : 2.f;
@@ -1390,32 +1455,90 @@ __global__ __launch_bounds__(256, 8) void inv_kernel(InvLaunch l)
                     const v2 ph = phasor(tlo, thi, bm, a.lo_bits);   // e^{+i 2 pi b m H / G}
                     c = (wgt * a.inv_nfft) * cmul(t, conjv(ph));
                 }
-                bst[kk * 32 + 2 * dd] = c.x;
-                bst[kk * 32 + 2 * dd + 1] = c.y;
+                cre[i] = c.x;
+                cim[i] = c.y;
+                amax = fmaxf(amax, fmaxf(fabsf(c.x), fabsf(c.y)));
+            }
+            // the block's power of two: largest |c~| 2^s in [2^13, 2^14)
+            amax = wave_reduce63(amax, 0.f, [](float p, float r) { return fmaxf(p, r); });
+            if (lane == 63)
+                fred[wave] = amax;
+            __syncthreads();   // maxima in; the previous block's halves consumed
+            const float bmax = fmaxf(fmaxf(fred[0], fred[1]), fmaxf(fred[2], fred[3]));
+            int ex = 0;
+            (void)frexpf(bmax, &ex);   // bmax < 2^ex (ex = 0 for bmax = 0)
+            int sb = 14 - ex;
+            sb = sb > 100 ? 100 : (sb < -100 ? -100 : sb);   // 2^sb stays a normal float
+            if (kb == 0) {
+                sc = sb;
+                if constexpr (ONE) {
+                    acc0 = f32x16{};
+                    acc1 = f32x16{};
+                }
+            } else if (sb < sc) {
+                // a later block needs a smaller power: rescale the sums (exact)
+                const float f = ldexpf(1.f, sb - sc);
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    acc0[i] *= f;
+                    acc1[i] *= f;
+                }
+                sc = sb;
+            }
+            const float scl = ldexpf(1.f, sc);
+#pragma unroll
+            for (int i = 0; i < kInvStage; ++i) {
+                const int e = tid + 256 * i;
+                const int kk = e >> 4, dd = e & 15;
+                if (kk < kn16) {
+                    unsigned h, lw;
+                    split_f16(cre[i] * scl, h, lw);
+                    ahi[(2 * dd) * kInvKBP + kk] = (unsigned short)h;
+                    alo[(2 * dd) * kInvKBP + kk] = (unsigned short)lw;
+                    split_f16(cim[i] * scl, h, lw);
+                    ahi[(2 * dd + 1) * kInvKBP + kk] = (unsigned short)h;
+                    alo[(2 * dd + 1) * kInvKBP + kk] = (unsigned short)lw;
+                }
             }
             __syncthreads();
-            // j = n - m H for this lane's rows: (jb0 - (kb + kk) H), stepping by 2H
-            // this wave's frames within the block, from an even k0 (pairs k0, k0 + 1)
+            // this wave's frames within the block, in steps of 16 from a
+            // multiple of 16 (the staged rows are zero past kn)
             int kw0 = wm_lo - mlo - kb, kw1 = wm_hi - mlo - kb;
-            kw0 = kw0 > 0 ? kw0 & ~1 : 0;
-            kw1 = kw1 < knp - 1 ? kw1 : knp - 1;
-            int j0 = jb0 - (kb + kw0 + half) * H;
-            const unsigned span = 2u * (unsigned)M;
-            const float *gt = gtab + M;
-            const float *bp = bst + half * 32 + col;
-#pragma unroll 1
-            for (int k0 = kw0; k0 <= kw1; k0 += 2) {
-                const float av = bp[k0 * 32];
-                const int j1 = j0 + 32;
-                const float g0 = ((unsigned)(j0 + M) <= span) ? gt[j0] : 0.f;
-                const float g1 = ((unsigned)(j1 + M) <= span) ? gt[j1] : 0.f;
-                acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(av, g0, acc0, 0, 0, 0);
-                acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(av, g1, acc1, 0, 0, 0);
-                j0 -= 2 * H;
+            kw0 = kw0 > 0 ? kw0 & ~15 : 0;
+            kw1 = kw1 < kn - 1 ? kw1 : kn - 1;
+            // j = n - m H of the lane's first frame (k0 + 8 half) for column 0
+            int j0 = jb0 - (kb + kw0 + 8 * half) * H;
+            for (int k0 = kw0; k0 <= kw1; k0 += 16) {
+                const u4v_t a_hi = *reinterpret_cast<const u4v_t *>(aph + k0);
+                const u4v_t a_lo = *reinterpret_cast<const u4v_t *>(apl + k0);
+                const f16x8v ah = __builtin_bit_cast(f16x8v, a_hi), al = __builtin_bit_cast(f16x8v, a_lo);
+                // B of column c: g[n + 32 c - m H] for the lane's 8 frames
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    unsigned w[8];
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) {
+                        const int j = j0 + 32 * c - i * H;
+                        w[i] = gpk[min(max(j, -M - 1), M + 1) + M + 1];
+                    }
+                    u4v_t bh, bl;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        bh[i] = __builtin_amdgcn_perm(w[2 * i + 1], w[2 * i], 0x05040100u);
+                        bl[i] = __builtin_amdgcn_perm(w[2 * i + 1], w[2 * i], 0x07060302u);
+                    }
+                    const f16x8v fh = __builtin_bit_cast(f16x8v, bh), fl = __builtin_bit_cast(f16x8v, bl);
+                    f32x16 &acc = c ? acc1 : acc0;
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, fh, acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, fl, acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(al, fh, acc, 0, 0, 0);
+                }
+                j0 -= 16 * H;
             }
         }
         // rows 8 (i/4) + 4 half + i mod 4 = 2 dd + p: dd = 4 (i/4) + 2 half + (i mod 4) / 2
         const uint32_t bb = (uint32_t)(zk1 + d0 + 2 * half);
+        const float unscale = ldexpf(a.g_unscale, -sc);
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
             uint32_t nm = n0g + (uint32_t)(s0 + 32 * c);
@@ -1434,9 +1557,9 @@ __global__ __launch_bounds__(256, 8) void inv_kernel(InvLaunch l)
             }
             t += __shfl_xor(t, 32, 64);
             if (c)
-                y1 += t;
+                y1 += t * unscale;
             else
-                y0 += t;
+                y0 += t * unscale;
         }
     }
 
@@ -1457,8 +1580,8 @@ __global__ __launch_bounds__(256, 8) void inv_kernel(InvLaunch l)
                 dv = 0.f;
                 const int hi = fhi < nframes_all - 1 ? fhi : nframes_all - 1;
                 for (int m = flo; m <= hi; ++m)
-                    dv += gtab[n - m * H + M];
-                dv *= gtab[M];
+                    dv += win[n - m * H + M].x;
+                dv *= win[M].x;
             }
             xv = dv > 0.f ? (c ? y1 : y0) / dv : 0.f;
             float *out = a.xhat + (int64_t)q * a.n + n;
@@ -1803,8 +1926,7 @@ hipError_t launch_put_desc(const ChanDesc &d, ChanDesc *dst, bool clear_max, int
 
 size_t inv_lds_bytes(const InvLaunch &l)
 {
-    return sizeof(float2) * (size_t)l.max_tab + 4 * (size_t)l.max_L + 4 * (size_t)l.max_k +
-           4 * 32 * (size_t)kInvKB + 16;
+    return inv_lds_layout(l.max_tab, l.max_L, l.max_k).total;
 }
 
 hipError_t launch_inverse(const InvLaunch &l, int64_t blocks, bool clear_err, hipStream_t s)
@@ -1817,7 +1939,10 @@ hipError_t launch_inverse(const InvLaunch &l, int64_t blocks, bool clear_err, hi
     }
     if (blocks <= 0)
         return hipSuccess;
-    hipLaunchKernelGGL(inv_kernel, dim3((unsigned)blocks), dim3(256), inv_lds_bytes(l), s, l);
+    if (l.max_k <= kInvKB)
+        hipLaunchKernelGGL(inv_kernel<true>, dim3((unsigned)blocks), dim3(256), inv_lds_bytes(l), s, l);
+    else
+        hipLaunchKernelGGL(inv_kernel<false>, dim3((unsigned)blocks), dim3(256), inv_lds_bytes(l), s, l);
     return hipGetLastError();
 }
 
