@@ -201,6 +201,8 @@ sst::InvDesc inv_desc(const sst_plan_s *pl, const float *T, int64_t frame0, int6
     a.inv_nfft = (float)(1.0 / pl->p.nfft);
     a.g_scale = pl->inv_g_scale;
     a.g_unscale = pl->inv_g_unscale;
+    a.dec_reach = pl->M + 63 + 16 * pl->p.hop;
+    a.dec_row = (2 * a.dec_reach) / pl->p.hop + 2;
     a.accumulate = accumulate ? 1 : 0;
     if (frame0 == 0 && nframes == pl->n_frames) {
         a.span_lo = 0;
@@ -236,8 +238,10 @@ int inv_max_k(const sst_plan_s *pl)
     return (k + 1) & ~1;
 }
 
+// max_dec: the largest decimated window table of the list (inv_dec_words);
+// max_L: its longest window.
 sst::InvLaunch inv_launch(const sst::InvDesc *dev, int n_ch, int64_t blk_begin, int max_k,
-                          int max_tab, int max_L)
+                          int max_tab, int max_L, int max_dec)
 {
     sst::InvLaunch l{};
     l.ch = dev;
@@ -245,7 +249,8 @@ sst::InvLaunch inv_launch(const sst::InvDesc *dev, int n_ch, int64_t blk_begin, 
     l.blk_begin = blk_begin;
     l.max_k = max_k;
     l.max_tab = max_tab;
-    l.max_L = (max_L + 3) & ~3;
+    l.dec = max_dec <= sst::kInvDecMax ? 1 : 0;
+    l.max_gtab = ((l.dec ? max_dec : max_L + 2) + 3) & ~3;
     return l;
 }
 
@@ -798,7 +803,7 @@ sst_status sst_inverse(sst_plan_t pl, const float *T, int64_t frame0, int64_t nf
     if (a.blk_end >= (int64_t(1) << 31))
         return fail(SST_E_UNSUPPORTED, "n_comp * ceil(span / 256) must be below 2^31");
     sst::InvLaunch l = inv_launch(slot, 1, a.blk0, inv_max_k(pl), pl->n_lo + pl->n_hi,
-                                  pl->p.win_len);
+                                  pl->p.win_len, pl->p.hop * a.dec_row);
     if (sst::inv_lds_bytes(l) > 64 * 1024)
         return fail(SST_E_UNSUPPORTED, "inverse tiles need more than 64 KiB of LDS "
                                        "(window too long for the hop)");
@@ -1148,7 +1153,7 @@ sst_status sst_batch_inverse(sst_batch_t b, int32_t c_begin, int32_t c_end, void
         return fail(SST_E_STATE, "batch not bound or buffers not committed");
     if (c_begin < 0 || c_end > (int32_t)b->plans.size() || c_begin >= c_end)
         return fail(SST_E_ARG, "channel range empty or outside [0, n_channels)");
-    int max_k = 2, max_tab = 1, max_L = 1;
+    int max_k = 2, max_tab = 1, max_L = 1, max_dec = 1;
     bool any_err = false;
     for (int c = c_begin; c < c_end; ++c) {
         const sst_batch_s::Io &o = b->io[(size_t)c];
@@ -1160,11 +1165,12 @@ sst_status sst_batch_inverse(sst_batch_t b, int32_t c_begin, int32_t c_end, void
         max_k = std::max(max_k, inv_max_k(pl));
         max_tab = std::max(max_tab, pl->n_lo + pl->n_hi);
         max_L = std::max(max_L, pl->p.win_len);
+        max_dec = std::max(max_dec, pl->p.hop * b->idesc[(size_t)c].dec_row);
         any_err = any_err || o.err;
     }
     const sst::InvDesc *dev = reinterpret_cast<const sst::InvDesc *>(b->ws + b->off_idesc);
     sst::InvLaunch l = inv_launch(dev + c_begin, c_end - c_begin, b->idesc[(size_t)c_begin].blk0,
-                                  max_k, max_tab, max_L);
+                                  max_k, max_tab, max_L, max_dec);
     if (sst::inv_lds_bytes(l) > 64 * 1024)
         return fail(SST_E_UNSUPPORTED, "inverse tiles need more than 64 KiB of LDS "
                                        "(window too long for the hop)");

@@ -88,6 +88,8 @@ struct InvDesc {
     float inv_nfft;
     float g_scale;          // 2^tg: the window's largest |g[j]| 2^tg lies in [2^13, 2^14)
     float g_unscale;        // 2^-tg
+    int dec_reach;          // JL = M + 63 + 16 H: window indices of the decimated table
+    int dec_row;            // (2 JL) / H + 2: words per residue row of that table
     int accumulate;         // add into xhat
     int pad_;
 };
@@ -99,8 +101,14 @@ struct InvLaunch {
     int max_k;              // most frames one output tile meets
     int64_t blk_begin;      // ch[0].blk0
     int max_tab;            // LDS float2 entries of the largest phase tables in the list
-    int max_L;              // longest window in the list
+    int max_gtab;           // LDS words of the largest window table in the list
+    int dec;                // window tables decimated by the hop (inv_gtab_words)
 };
+
+// Words of a channel's inverse window table: decimated by the hop,
+// H dec_row, when that is at most kInvDecMax; otherwise L + 2 (indices
+// clamped).
+constexpr int kInvDecMax = 10240;
 
 constexpr int kInvTileSamples = 256;   // output samples per inverse workgroup
 

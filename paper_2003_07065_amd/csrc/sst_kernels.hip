@@ -1284,6 +1284,7 @@ constexpr int kInvKBP = kInvKB + 8;            // padded row of staged halves
 constexpr int kInvStage = kInvKB * 16 / 256;   // staged coefficients per thread and block
 
 typedef _Float16 f16x8v __attribute__((ext_vector_type(8)));
+
 typedef unsigned u4v_t __attribute__((ext_vector_type(4)));
 
 // v ~ hi + lo in FP16 (|v| < 2^15), as bit patterns
@@ -1302,11 +1303,11 @@ __host__ __device__ inline size_t inv_align16(size_t v)
 {
     return (v + 15) & ~(size_t)15;
 }
-__host__ __device__ inline InvLds inv_lds_layout(int max_tab, int max_L, int max_k)
+__host__ __device__ inline InvLds inv_lds_layout(int max_tab, int max_gtab, int max_k)
 {
     InvLds o;
     o.gpk = inv_align16(8 * (size_t)max_tab);
-    o.rid = inv_align16(o.gpk + 4 * ((size_t)max_L + 2));
+    o.rid = inv_align16(o.gpk + 4 * (size_t)max_gtab);
     o.ahi = inv_align16(o.rid + 4 * (size_t)max_k);
     o.alo = o.ahi + 2 * 32 * (size_t)kInvKBP;
     o.fred = inv_align16(o.alo + 2 * 32 * (size_t)kInvKBP);
@@ -1316,8 +1317,10 @@ __host__ __device__ inline InvLds inv_lds_layout(int max_tab, int max_L, int max
 }
 
 // ONE: every tile's frames fit one staged block (K <= KB), so the sums start
-// after the staging and need no registers during it.
-template <bool ONE>
+// after the staging and need no registers during it.  DEC: the window table is
+// decimated by the hop, so a lane's 8 window values are consecutive words;
+// otherwise they are gathered with clamped indices.
+template <bool ONE, bool DEC>
 __global__ __launch_bounds__(256, ONE ? 5 : 4) void inv_kernel(InvLaunch l)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -1326,7 +1329,7 @@ __global__ __launch_bounds__(256, ONE ? 5 : 4) void inv_kernel(InvLaunch l)
     const CA InvDesc &a = chs[inv_chan_of(chs, l.n_ch, blk)];
     const int nlo = 1 << a.lo_bits;
     const int nhi = (a.G + nlo - 1) >> a.lo_bits;
-    const InvLds lay = inv_lds_layout(l.max_tab, l.max_L, l.max_k);
+    const InvLds lay = inv_lds_layout(l.max_tab, l.max_gtab, l.max_k);
     v2 *tlo = reinterpret_cast<v2 *>(smem);
     v2 *thi = tlo + nlo;
     unsigned *gpk = reinterpret_cast<unsigned *>(smem + lay.gpk);   // [L + 2]: window, packed
@@ -1356,15 +1359,27 @@ __global__ __launch_bounds__(256, ONE ? 5 : 4) void inv_kernel(InvLaunch l)
 #pragma unroll 2
     for (int e = threadIdx.x; e < nhi; e += 256)
         thi[e] = reinterpret_cast<const v2 *>(a.ph_hi)[e];
-    // gpk[j + M + 1] = g[j] 2^tg as FP16 hi | lo << 16 for |j| <= M, zero at
-    // j = -M - 1 and M + 1 (indices outside the window are clamped there)
+    // Window table, g[j] 2^tg as FP16 hi | lo << 16, zero for |j| > M.  DEC:
+    // gpk[r TR + t] holds j = r + t H - JL (r = residue mod H); otherwise
+    // gpk[j + M + 1] for |j| <= M + 1 (indices outside are clamped onto the
+    // zero ends).
     const float gsc = a.g_scale;
+    const int JL = DEC ? a.dec_reach : 0;
+    const int TR = DEC ? a.dec_row : 0;
+    const int n_tab = DEC ? H * TR : a.L + 2;
 #pragma unroll 4
-    for (int e = threadIdx.x; e < a.L + 2; e += 256) {
+    for (int e = threadIdx.x; e < n_tab; e += 256) {
+        int j;
+        if constexpr (DEC) {
+            const int r = e / TR;
+            j = r + (e - r * TR) * H - JL;
+        } else {
+            j = e - M - 1;
+        }
         unsigned w = 0u;
-        if (e >= 1 && e <= a.L) {
+        if (j >= -M && j <= M) {
             unsigned h, lw;
-            split_f16(win[e - 1].x * gsc, h, lw);
+            split_f16(win[j + M].x * gsc, h, lw);
             w = h | (lw << 16);
         }
         gpk[e] = w;
@@ -1508,6 +1523,17 @@ __global__ __launch_bounds__(256, ONE ? 5 : 4) void inv_kernel(InvLaunch l)
             kw1 = kw1 < kn - 1 ? kw1 : kn - 1;
             // j = n - m H of the lane's first frame (k0 + 8 half) for column 0
             int j0 = jb0 - (kb + kw0 + 8 * half) * H;
+            // DEC: the lane's 8 values g[j - i H], i = 0..7, are the words
+            // p[7 - i] of its residue row; a step of 16 frames moves p by -16.
+            // Every j a step reaches lies within JL of 0: the steps start up to
+            // 15 frames before the wave's first frame and end up to 15 after
+            // its last, and a wave spans 64 samples, so |j| <= M + 63 + 15 H.
+            const unsigned *pc0 = gpk, *pc1 = gpk;
+            if constexpr (DEC) {
+                const int u0 = j0 + JL, u1 = u0 + 32;
+                pc0 = gpk + (u0 % H) * TR + u0 / H - 7;
+                pc1 = gpk + (u1 % H) * TR + u1 / H - 7;
+            }
             for (int k0 = kw0; k0 <= kw1; k0 += 16) {
                 const u4v_t a_hi = *reinterpret_cast<const u4v_t *>(aph + k0);
                 const u4v_t a_lo = *reinterpret_cast<const u4v_t *>(apl + k0);
@@ -1516,10 +1542,17 @@ __global__ __launch_bounds__(256, ONE ? 5 : 4) void inv_kernel(InvLaunch l)
 #pragma unroll
                 for (int c = 0; c < 2; ++c) {
                     unsigned w[8];
+                    if constexpr (DEC) {
+                        const unsigned *pc = c ? pc1 : pc0;
 #pragma unroll
-                    for (int i = 0; i < 8; ++i) {
-                        const int j = j0 + 32 * c - i * H;
-                        w[i] = gpk[min(max(j, -M - 1), M + 1) + M + 1];
+                        for (int i = 0; i < 8; ++i)
+                            w[i] = pc[7 - i];
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < 8; ++i) {
+                            const int j = j0 + 32 * c - i * H;
+                            w[i] = gpk[min(max(j, -M - 1), M + 1) + M + 1];
+                        }
                     }
                     u4v_t bh, bl;
 #pragma unroll
@@ -1534,6 +1567,8 @@ __global__ __launch_bounds__(256, ONE ? 5 : 4) void inv_kernel(InvLaunch l)
                     acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(al, fh, acc, 0, 0, 0);
                 }
                 j0 -= 16 * H;
+                pc0 -= 16;
+                pc1 -= 16;
             }
         }
         // rows 8 (i/4) + 4 half + i mod 4 = 2 dd + p: dd = 4 (i/4) + 2 half + (i mod 4) / 2
@@ -1926,7 +1961,7 @@ hipError_t launch_put_desc(const ChanDesc &d, ChanDesc *dst, bool clear_max, int
 
 size_t inv_lds_bytes(const InvLaunch &l)
 {
-    return inv_lds_layout(l.max_tab, l.max_L, l.max_k).total;
+    return inv_lds_layout(l.max_tab, l.max_gtab, l.max_k).total;
 }
 
 hipError_t launch_inverse(const InvLaunch &l, int64_t blocks, bool clear_err, hipStream_t s)
@@ -1939,10 +1974,16 @@ hipError_t launch_inverse(const InvLaunch &l, int64_t blocks, bool clear_err, hi
     }
     if (blocks <= 0)
         return hipSuccess;
-    if (l.max_k <= kInvKB)
-        hipLaunchKernelGGL(inv_kernel<true>, dim3((unsigned)blocks), dim3(256), inv_lds_bytes(l), s, l);
+    const size_t lds = inv_lds_bytes(l);
+    const dim3 g((unsigned)blocks), b(256);
+    if (l.max_k <= kInvKB && l.dec)
+        hipLaunchKernelGGL((inv_kernel<true, true>), g, b, lds, s, l);
+    else if (l.max_k <= kInvKB)
+        hipLaunchKernelGGL((inv_kernel<true, false>), g, b, lds, s, l);
+    else if (l.dec)
+        hipLaunchKernelGGL((inv_kernel<false, true>), g, b, lds, s, l);
     else
-        hipLaunchKernelGGL(inv_kernel<false>, dim3((unsigned)blocks), dim3(256), inv_lds_bytes(l), s, l);
+        hipLaunchKernelGGL((inv_kernel<false, false>), g, b, lds, s, l);
     return hipGetLastError();
 }
 
