@@ -229,10 +229,18 @@ def test_inverse_pipeline_snr(sst):
         assert abs(err[q, 1] - np.sum(ref[M:w.n - M] ** 2)) <= 1e-9 * np.sum(ref[M:w.n - M] ** 2)
 
 
-@pytest.mark.parametrize("name,n,cfg", [CASES[2], CASES[4], CASES[1]],
-                         ids=["nf1024", "nf2048-z3-k1", "c3-shape"])
+INV_CASES = [CASES[2], CASES[4], CASES[1], CASES[6],
+             ("hop512", 50000, SSTConfig(25600.0, 1023, 128.0, 512, 4096, 0.0, 6400.0, 4, "rel",
+                                         1e-3, 6))]
+
+
+@pytest.mark.parametrize("name,n,cfg", INV_CASES,
+                         ids=["nf1024", "nf2048-z3-k1", "c3-shape", "nf8192-L8191-H64", "hop512"])
 def test_inverse_configs(sst, name, n, cfg):
-    """Inverse parity on identical T across DFT sizes, non power-of-two z, k1 > 0."""
+    """Inverse parity on identical T across DFT sizes, non power-of-two z, k1 > 0,
+    tiles whose frames span several staged blocks (hop 5, and L 8191 with hop 64)
+    and window tables too large to decimate by the hop (L 8191 with hop 64, and
+    hop 512), which take the clamped window gather."""
     x = _signal(name, n, cfg.fs)
     o = oracle.forward(x.astype(np.float64), cfg)
     plan = sst.Plan.from_config(n, cfg, device="cuda")
