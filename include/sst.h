@@ -221,6 +221,10 @@ sst_status sst_ridge(sst_plan_t plan, const float *T, int64_t nframes, const int
  * chunked calls with SST_INV_ACCUMULATE sum to the whole-signal result.
  * Without SST_INV_ACCUMULATE the samples the chunk reaches are overwritten.
  * With SST_INV_EQ15 (hop 1 only): xhat_q[m] = (1/(N_f g[0])) sum_zone a_l Re T[m,l].
+ * Arithmetic: the sum over frames runs on the matrix cores with both operands
+ * split into FP16 hi + lo parts (22 significant bits each, power-of-two scaled)
+ * and FP32 accumulation; phases, weights and the denominator are FP32/FP64 as
+ * above.  Measured against an FP64 evaluation: about 3e-7 relative.
  *   T        device complex float [nframes][n_dst]
  *   ridge    device int32 [n_comp][nframes]; -1 = no contribution from that frame
  *   hw       zone half-width in destination bins, >= 0

@@ -6,9 +6,18 @@
 //                   threshold (Sec. 2.2, Eqs. 12-13), and the selective,
 //                   subdivided reassignment (Eq. 14; Sec. 2.4, Eqs. 27-29)
 //                   into an LDS histogram that is streamed to HBM as rows of T.
-//   max_kernel   -- max |S| over every frame for the relative threshold.
+//                   Modes: the plain forward (optionally at a speculative lower
+//                   bound of the relative threshold), the max-only pre-pass
+//                   for that threshold, and the fix-up pass over a list of
+//                   frame groups.
+//   spec_list_kernel -- gamma after a speculative forward and the list of
+//                   frame groups that the final gamma changes.
+//   max_kernel   -- max |S| over every frame, two frames per FFT (the GEMM
+//                   tiers' threshold pre-pass).
 //   inv_kernel   -- the direct downsampled inverse (Sec. 2.3, Eqs. 25-26, zN_f
-//                   phase grid of the band / subdivision remark of Sec. 2.5).
+//                   phase grid of the band / subdivision remark of Sec. 2.5),
+//                   its window contraction on the FP16 matrix cores with
+//                   hi/lo split operands.
 //   eq15_kernel  -- the standard hop-1 inverse (Sec. 2.2, Eq. 15).
 //   ridge_kernel -- per-frame argmax of |T| inside a band (zone M_q[m]).
 //
