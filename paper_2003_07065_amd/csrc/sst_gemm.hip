@@ -220,7 +220,6 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmArgs a)
             const u4v *ap = afrag + abase, *apl = afrag_lo + abase;
             const unsigned short *bp = xhi + col * a.hop + 8 * half;   // k = 0, column tile 0
             const int cstride = 32 * a.hop;                             // next column tile
-#pragma unroll 4
             for (int ks = 0; ks < a.ksteps; ++ks) {
                 const u4v ac = an, acl = anl;
                 if (ks + 1 < a.ksteps) {

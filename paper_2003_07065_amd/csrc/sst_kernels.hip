@@ -982,7 +982,7 @@ __global__ __launch_bounds__(Geo<NF>::NT, DEBUG ? 2 : ((NF == 8192 || (NF == 409
         if constexpr (DEBUG) {
             if (a.colstats) {
                 __syncthreads();
-                if (threadIdx.x < 3 * nvalid)
+                if ((int)threadIdx.x < 3 * nvalid)
                     a.colstats[m0 * 3 + threadIdx.x] = colacc[threadIdx.x];
                 if (threadIdx.x < 3 * F)
                     colacc[threadIdx.x] = 0.0;
