@@ -1328,9 +1328,10 @@ __host__ __device__ inline InvLds inv_lds_layout(int max_tab, int max_gtab, int 
 // ONE: every tile's frames fit one staged block (K <= KB), so the sums start
 // after the staging and need no registers during it.  DEC: the window table is
 // decimated by the hop, so a lane's 8 window values are consecutive words;
-// otherwise they are gathered with clamped indices.
+// otherwise they are gathered with clamped indices.  Waves per SIMD: the most
+// that each variant fits without spilling registers.
 template <bool ONE, bool DEC>
-__global__ __launch_bounds__(256, ONE ? 5 : 4) void inv_kernel(InvLaunch l)
+__global__ __launch_bounds__(256, ONE ? (DEC ? 6 : 5) : 4) void inv_kernel(InvLaunch l)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int64_t blk = l.blk_begin + (int64_t)blockIdx.x;
