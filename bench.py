@@ -2,14 +2,19 @@
 """Benchmark of the downsampled SST + direct inverse on one MI355X.
 
 One step = the whole hot path over one synthetic signal already resident in
-HBM: threshold pre-pass (max |S| over every frame), fused forward transform
-(framing, FFT pair, IF, selective subdivided reassignment, T rows), ridge
-argmax per component, and the direct inverse of every component.
+HBM: the threshold gamma = rho max|S| over every frame and the fused forward
+transform (framing, FFT pair, IF, selective subdivided reassignment, T rows) in
+one sst_forward call, the ridge argmax of every component, and the direct
+inverse of every component.
 
-Workload (default): N = 2^20 samples at 25.6 kHz, three AM-FM components plus
-white noise at 10 dB, Gaussian window of 1023 taps (sigma 128), hop 16,
-N_f = 4096, band [0, 6.4 kHz], subdivision 4, threshold 1e-3 max|S|, three
-reconstruction zones of half-width 6 bins.
+Workload (default, c3): the long run-up channel, N = 2^26 samples at 25.6 kHz,
+a fundamental sweeping 50 -> 600 Hz with 8 harmonics plus pink noise at 15 dB,
+Gaussian window of 2047 taps (sigma 256), hop 32, N_f = 8192, band [0, 5 kHz],
+subdivision 8, threshold 1e-3 max|S|; T (214.8 GB) stays resident in HBM; the
+ridges are searched within +-26 bins of each harmonic order of the sweep and
+the 8 harmonics are reconstructed with zones of half-width 26 bins.
+``--workload c2`` runs the N = 2^20 three-component channel; ``c4`` the
+batched uneven channels; ``c5`` the precision tiers.
 
 Prints ONE JSON line.  Per-kernel times come from HIP events recorded on the
 stream the library launches on.  The roofline object refers to the fused
@@ -54,26 +59,44 @@ def load_traffic(workload: str):
     return d
 
 
-def cpu_baseline(n_sample: int):
-    """The float64 oracle, as it stands, on the first n_sample samples of the workload:
-    threshold maximum, STFT pair, reassignment, and the inverse of the three components."""
+def log(msg: str):
+    """Progress of a long run, on stderr (the JSON line alone goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, n_sample: int, hw: int, ridge_fn):
+    """The float64 oracle, as it stands, on the first n_sample samples of the
+    workload's own signal (a bounded sample; the threshold maximum is taken over
+    that sample): STFT pair, threshold, reassignment, and the inverse of every
+    component along the closed-form ridges."""
     import numpy as np
     import oracle
-    from workloads import make_c2, ridge_bins
-    w = make_c2(n=n_sample)
     c = w.cfg
-    x = w.x.astype(np.float64)
+    x = w.x[:n_sample].astype(np.float64)
     t0 = time.perf_counter()
     o = oracle.forward(x, c)
-    ridge = ridge_bins(w.inst_freq(w.frame_times()), c.fs, c.nfft, o.band.k1, c.subdiv,
-                       o.band.n_dst)
+    ridge = ridge_fn(o.band.k1, o.band.n_dst, -(-n_sample // c.hop))
     for q in range(ridge.shape[0]):
-        oracle.inverse(o.T, ridge[q], c.hw, o.g, c.hop, c.nfft, o.band.k1, c.subdiv, w.n)
+        oracle.inverse(o.T, np.ascontiguousarray(ridge[q]), hw, o.g, c.hop, c.nfft, o.band.k1,
+                       c.subdiv, n_sample)
     dt = time.perf_counter() - t0
     return {"value": n_sample / dt / 1e6, "unit": "Msamples/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"first {n_sample} samples of the workload ({n_sample / (1 << 20):.3g} of "
-                      f"it), whole pipeline in float64, {dt:.2f} s"}
+            "kind": "oracle", "cpu_model": cpu_model(),
+            "sample": f"first {n_sample} samples of the workload's signal ({n_sample / w.n:.4g} "
+                      f"of it) as a signal of their own, whole pipeline (threshold, STFT pair, "
+                      f"reassignment, {ridge.shape[0]}-component inverse) in float64, "
+                      f"{dt:.2f} s"}
 
 
 def run_c4(args):
@@ -303,67 +326,51 @@ def run_c5(args):
     print(json.dumps(out), flush=True)
 
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", choices=["c2", "c4", "c5"], default="c2",
-                    help="c2: one long channel (default); c4: batched uneven channels; "
-                         "c5: precision tiers")
-    ap.add_argument("--c5-channels", type=int, default=512)
-    ap.add_argument("--c5-nfft", type=int, default=512, choices=[512, 1024])
-    ap.add_argument("--c4-channels", type=int, default=256)
-    ap.add_argument("--t-pool-gb", type=float, default=120.0,
-                    help="c4: device memory for T; channels are processed in passes that fit")
-    ap.add_argument("--n", type=int, default=1 << 20, help="signal length (default 2^20)")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=1 << 18)
-    ap.add_argument("--calib-copy-mib", type=int, default=0,
-                    help="also run one device copy of this many MiB (counter calibration)")
-    args = ap.parse_args()
-
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(sharding is described in DESIGN.md); use --gpus 1", file=sys.stderr)
-        sys.exit(2)
-
+def run_single(args):
+    """One long channel (c3 default, c2): a step is the whole hot path over the
+    resident signal -- threshold and fused forward (one sst_forward call),
+    ridges, and the direct inverse of every component."""
     import numpy as np
     import torch
     import paper_2003_07065_amd as sst
-    from workloads import make_c2, ridge_bins
+    from workloads import make_c2, make_c3, ridge_bins
 
-    if not torch.cuda.is_available():
-        print("bench.py needs a HIP device", file=sys.stderr)
-        sys.exit(2)
-    if args.workload == "c4":
-        run_c4(args)
-        return
-    if args.workload == "c5":
-        run_c5(args)
-        return
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-
-    w = make_c2(n=args.n)
+    t0 = time.perf_counter()
+    if args.workload == "c3":
+        w = make_c3(n=args.n or (1 << 26))
+    else:
+        w = make_c2(n=args.n or (1 << 20))
+    gen_s = time.perf_counter() - t0
+    log(f"{args.workload}: generated {w.n} samples in {gen_s:.1f} s")
     c = w.cfg
+    comps = w.comps
+    w.comps = None
     plan = sst.Plan.from_config(w.n, c, device=dev)
     xg = torch.from_numpy(w.x).to(dev)
     T = torch.empty((plan.n_frames, plan.n_dst), dtype=torch.complex64, device=dev)
     f_true = w.inst_freq(w.frame_times())
     ridge_true = ridge_bins(f_true, c.fs, c.nfft, plan.k1, c.subdiv, plan.n_dst)
     n_comp = ridge_true.shape[0]
-    # ridge search bands: +-8% around each component's nominal frequency
-    bands = []
-    for q in range(n_comp):
-        f0 = float(np.median(f_true[q]))
-        lo = int(math.floor(c.subdiv * (0.92 * f0 / c.delta_f - plan.k1)))
-        hi = int(math.ceil(c.subdiv * (1.08 * f0 / c.delta_f - plan.k1)))
-        bands.append((max(lo, 0), min(hi, plan.n_dst - 1)))
     ridge = torch.empty((n_comp, plan.n_frames), dtype=torch.int32, device=dev)
+    centre = None
+    if args.workload == "c3":
+        # run-up: the harmonics sweep over most of the band, so each ridge is
+        # searched within +-hw bins of its order of the (tacho-like) shaft speed
+        centre = torch.from_numpy(ridge_true).to(dev)
+        bands = [(-c.hw, c.hw)] * n_comp
+        ridge_desc = f"guided ridges (+-{c.hw} bins around each harmonic order)"
+    else:
+        # ridge search bands: +-8% around each component's nominal frequency
+        bands = []
+        for q in range(n_comp):
+            f0 = float(np.median(f_true[q]))
+            lo = int(math.floor(c.subdiv * (0.92 * f0 / c.delta_f - plan.k1)))
+            hi = int(math.ceil(c.subdiv * (1.08 * f0 / c.delta_f - plan.k1)))
+            bands.append((max(lo, 0), min(hi, plan.n_dst - 1)))
+        ridge_desc = "ridges in +-8% bands"
     xhat = torch.empty((n_comp, w.n), dtype=torch.float32, device=dev)
-    xref = torch.from_numpy(w.comps.astype(np.float32)).to(dev)
-    err = torch.zeros((n_comp, 2), dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream(dev)
 
     def step(evs=None):
@@ -374,7 +381,7 @@ def main():
         plan.forward(xg, T, kernel_events=(evs[1], evs[2]) if evs else None)
         if evs:
             evs[3].record(stream)
-        plan.ridge(T, bands, out=ridge)
+        plan.ridge(T, bands, out=ridge, centre=centre)
         if evs:
             evs[4].record(stream)
         plan.inverse(T, ridge, c.hw, xhat=xhat)
@@ -384,6 +391,7 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    log(f"{args.warmup} warm-up steps done")
 
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(args.steps)]
     for row in evs:
@@ -395,6 +403,7 @@ def main():
         step(evs[k])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    log(f"{args.steps} timed steps done in {wall:.2f} s")
 
     seg = np.array([[evs[k][i].elapsed_time(evs[k][i + 1]) for i in range(5)]
                     for k in range(args.steps)])          # ms
@@ -404,11 +413,14 @@ def main():
     value = w.n * args.steps / (total_ms / 1e3) / 1e6
 
     # Accuracy of the timed result: SNR of every component (Eq. 33, FP64 on the GPU).
+    xref = torch.from_numpy(comps.astype(np.float32)).to(dev)
+    err = torch.zeros((n_comp, 2), dtype=torch.float64, device=dev)
     plan.inverse(T, ridge, c.hw, xhat=xhat, xref=xref, err=err)
     torch.cuda.synchronize()
     e = err.cpu().numpy()
     snr = [float(10.0 * np.log10(e[q, 1] / e[q, 0])) for q in range(n_comp)]
     ridge_hit = float((ridge.cpu().numpy() == ridge_true).mean())
+    del xref
 
     calib = None
     if args.calib_copy_mib > 0:
@@ -419,17 +431,19 @@ def main():
         torch.neg(a, out=b)   # one elementwise kernel: reads nb bytes, writes nb bytes
         torch.cuda.synchronize()
         calib = {"copy_bytes_each_way": nb}
+        del a, b
 
     fwd_ms = float(np.mean(seg[:, 1]))                     # the fused forward kernel alone
-    thr_ms = float(np.mean(seg[:, 0] + seg[:, 2]))         # gamma pre-pass, gamma, fix-up pass
+    thr_ms = float(np.mean(seg[:, 0] + seg[:, 2]))         # gamma seed, gamma, fix-up pass
     ridge_ms = float(np.mean(seg[:, 3]))
     inv_ms = float(np.mean(seg[:, 4]))
     t_bytes = 8 * plan.n_dst * plan.n_frames
     x_bytes = 4 * w.n
     fwd_alg_bytes = t_bytes + x_bytes
     achieved = fwd_alg_bytes / (fwd_ms / 1e3) / 1e9
-    traffic = load_traffic("c2")
-    roof = {"kernel": "fwd_kernel (fused framing + FFT pair + IF + reassignment, N_f=4096)",
+    traffic = load_traffic(args.workload)
+    roof = {"kernel": f"fwd_kernel (fused framing + FFT pair + IF + reassignment, "
+                      f"N_f={c.nfft})",
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": (traffic or {}).get("bytes_per_launch"),
@@ -438,17 +452,23 @@ def main():
     # whole-step HBM roofline: every algorithmic byte of the step at peak bandwidth
     inv_bytes = n_comp * (8 * (2 * c.hw + 1) * plan.n_frames + 4 * w.n)
     step_bytes = fwd_alg_bytes + inv_bytes + x_bytes
+    if args.workload == "c3":
+        desc = (f"downsampled SST + direct inverse, one channel, N=2^26 at 25.6 kHz: run-up "
+                f"50->600 Hz with 8 harmonics (1/h, random phases) + pink noise 15 dB (seed 0), "
+                f"Gaussian L=2047 sigma=256, H=32, N_f=8192, band [0, 5 kHz], z=8, "
+                f"gamma=1e-3 max|S|, {ridge_desc}, 8-harmonic inverse hw={c.hw}")
+    else:
+        desc = (f"downsampled SST + direct inverse, one channel, N=2^20 at 25.6 kHz, 3 AM-FM "
+                f"components + white noise 10 dB (seed 0), Gaussian L=1023 sigma=128, H=16, "
+                f"N_f=4096, band [0, 6.4 kHz], z=4, gamma=1e-3 max|S|, {ridge_desc}, "
+                f"3-component inverse hw={c.hw}")
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "Msamples/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "downsampled SST + direct inverse, one channel, N=2^20 at "
-                               "25.6 kHz, 3 AM-FM components + white noise 10 dB (seed 0), "
-                               "Gaussian L=1023 sigma=128, H=16, N_f=4096, band [0, 6.4 kHz], "
-                               "z=4, gamma=1e-3 max|S|, 3 ridges hw=6",
-                   "n_samples": w.n, "n_frames": plan.n_frames, "n_dst": plan.n_dst,
-                   "T_bytes": t_bytes},
+        "config": {"workload": desc, "n_samples": w.n, "n_frames": plan.n_frames,
+                   "n_dst": plan.n_dst, "T_bytes": t_bytes, "generation_s": round(gen_s, 1)},
         "roofline": roof,
         "segments_ms": {"forward_kernel": round(fwd_ms, 4),
                         "threshold_and_fixup": round(thr_ms, 4),
@@ -461,8 +481,59 @@ def main():
     if calib:
         out["calibration"] = calib
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.cpu_sample)
+        del T
+        torch.cuda.empty_cache()
+        w.comps = comps
+        sample = args.cpu_sample or (1 << 20 if args.workload == "c3" else 1 << 18)
+
+        def ridge_fn(k1, n_dst, nfr):
+            t = np.arange(nfr, dtype=np.float64) * c.hop / c.fs
+            return ridge_bins(w.inst_freq(t), c.fs, c.nfft, k1, c.subdiv, n_dst)
+
+        log(f"oracle on the first {sample} samples")
+        out["cpu_baseline"] = cpu_baseline(w, sample, c.hw, ridge_fn)
     print(json.dumps(out), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", choices=["c3", "c2", "c4", "c5"], default="c3",
+                    help="c3: the long run-up channel, N=2^26 (default); c2: N=2^20; "
+                         "c4: batched uneven channels; c5: precision tiers")
+    ap.add_argument("--c5-channels", type=int, default=512)
+    ap.add_argument("--c5-nfft", type=int, default=512, choices=[512, 1024])
+    ap.add_argument("--c4-channels", type=int, default=256)
+    ap.add_argument("--t-pool-gb", type=float, default=120.0,
+                    help="c4: device memory for T; channels are processed in passes that fit")
+    ap.add_argument("--n", type=int, default=0,
+                    help="signal length (default: the workload's, 2^26 for c3, 2^20 for c2)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=0,
+                    help="oracle sample in samples (default 2^20 for c3, 2^18 for c2)")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="also run one device copy of this many MiB (counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(sharding is described in DESIGN.md); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2003_07065_amd  # noqa: F401  (fails loudly without the built library)
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        sys.exit(2)
+    if args.workload == "c4":
+        run_c4(args)
+    elif args.workload == "c5":
+        run_c5(args)
+    else:
+        run_single(args)
 
 
 if __name__ == "__main__":

@@ -212,6 +212,21 @@ sst_status sst_ridge(sst_plan_t plan, const float *T, int64_t nframes, const int
                      int32_t n_comp, int32_t *ridge, void *stream);
 
 /*
+ * sst_ridge_guided -- sst_ridge with a search band that follows a guide per
+ * frame (e.g. a harmonic order of a measured shaft speed): for frame m and
+ * component q the ridge is the first largest |T| in
+ * [centre[q][m] + band[2q], centre[q][m] + band[2q+1]] (clipped to [0, n_dst)),
+ * -1 when centre[q][m] < 0 or the range is all zero.
+ *   centre   device int32 [n_comp][nframes]: guide destination bins
+ *   band     host int32 [2 n_comp]: offsets relative to the guide, each in
+ *            [-n_dst, n_dst]
+ * Errors: as sst_ridge.
+ */
+sst_status sst_ridge_guided(sst_plan_t plan, const float *T, int64_t nframes,
+                            const int32_t *centre, const int32_t *band, int32_t n_comp,
+                            int32_t *ridge, void *stream);
+
+/*
  * sst_inverse -- direct downsampled inverse (Eqs. 25-26; zN_f grid for z > 1)
  * of n_comp components from the T rows of frames [frame0, frame0 + nframes):
  *   r[m,j] = (1/N_f) sum_{l in zone} a_l Re(T[m,l] e^{i 2 pi ((z k1 + l) j mod z N_f)/(z N_f)})

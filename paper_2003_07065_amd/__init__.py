@@ -39,7 +39,8 @@ SST_FWD_REUSE_GAMMA = 1
 SST_INV_ACCUMULATE = 1
 SST_INV_EQ15 = 2
 
-EXPORTED = ("sst_plan", "sst_plan_query", "sst_plan_bind", "sst_forward", "sst_ridge",
+EXPORTED = ("sst_plan", "sst_plan_query", "sst_plan_bind", "sst_forward",
+            "sst_ridge", "sst_ridge_guided",
             "sst_inverse", "sst_destroy", "sst_status_string", "sst_last_error",
             "sst_critical_hf", "sst_batch_plan", "sst_batch_query", "sst_batch_bind",
             "sst_batch_set_io", "sst_batch_commit", "sst_batch_forward", "sst_batch_inverse",
@@ -119,6 +120,7 @@ def lib():
     L.sst_plan_bind.argtypes = [vp, vp, ctypes.c_size_t, vp]
     L.sst_forward.argtypes = [vp, vp, i64, i64, vp, ctypes.POINTER(FwdAux), u32, vp]
     L.sst_ridge.argtypes = [vp, vp, i64, ctypes.POINTER(i32), i32, vp, vp]
+    L.sst_ridge_guided.argtypes = [vp, vp, i64, vp, ctypes.POINTER(i32), i32, vp, vp]
     L.sst_inverse.argtypes = [vp, vp, i64, i64, vp, i32, i32, vp, vp, vp, u32, vp]
     L.sst_destroy.argtypes = [vp]
     L.sst_destroy.restype = None
@@ -138,7 +140,8 @@ def lib():
     L.sst_batch_inverse.argtypes = [vp, i32, i32, vp]
     L.sst_batch_destroy.argtypes = [vp]
     L.sst_batch_destroy.restype = None
-    for name in ("sst_plan", "sst_plan_query", "sst_plan_bind", "sst_forward", "sst_ridge",
+    for name in ("sst_plan", "sst_plan_query", "sst_plan_bind", "sst_forward",
+                 "sst_ridge", "sst_ridge_guided",
                  "sst_inverse", "sst_critical_hf", "sst_batch_plan", "sst_batch_query",
                  "sst_batch_bind", "sst_batch_set_io", "sst_batch_commit", "sst_batch_forward",
                  "sst_batch_inverse"):
@@ -261,6 +264,17 @@ class Plan:
         if self.workspace is None:
             raise SSTError(SST_E_STATE, "Plan", "bind() the plan to a device first")
 
+    def _check_buf(self, t, dtype, numel: int, name: str):
+        """Every buffer handed to the C ABI: dtype, contiguity, device and size."""
+        if t is None:
+            return
+        if t.dtype != dtype or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous {dtype} tensor")
+        if t.device != self.device:
+            raise ValueError(f"{name} must live on the plan's device {self.device}")
+        if t.numel() < numel:
+            raise ValueError(f"{name} holds {t.numel()} elements, the call needs {numel}")
+
     def forward(self, x, T=None, frame0: int = 0, nframes: Optional[int] = None, *,
                 S=None, Sd=None, idx=None, colstats=None, gamma=None,
                 reuse_gamma: bool = False, kernel_events=None):
@@ -269,8 +283,13 @@ class Plan:
         kernel_events: optional pair of torch.cuda.Event, already recorded once
         (so that they exist); the library records them again right around the
         fused forward kernel."""
-        import torch
         self._need_bound()
+        return self._forward_call(lib().sst_forward, "sst_forward", x, T, frame0, nframes, S, Sd,
+                                  idx, colstats, gamma, reuse_gamma, kernel_events)
+
+    def _forward_call(self, fn, where, x, T, frame0, nframes, S, Sd, idx, colstats, gamma,
+                      reuse_gamma, kernel_events):
+        import torch
         if nframes is None:
             nframes = self.n_frames - frame0
         if x.dtype != torch.float32 or not x.is_contiguous() or x.device != self.device:
@@ -279,30 +298,30 @@ class Plan:
             raise ValueError("x length differs from the plan's n_samples")
         if T is None:
             T = torch.empty((nframes, self.n_dst), dtype=torch.complex64, device=self.device)
-        if T.dtype != torch.complex64 or not T.is_contiguous() or T.numel() < nframes * self.n_dst:
-            raise ValueError("T must be a contiguous complex64 tensor of nframes * n_dst")
-        for t, n, dt in ((S, self.n_src, torch.complex64), (Sd, self.n_src, torch.complex64),
-                         (idx, self.n_src, torch.int32), (colstats, 3, torch.float64)):
-            if t is not None and (t.dtype != dt or not t.is_contiguous()
-                                  or t.numel() < nframes * n):
-                raise ValueError("debug output has the wrong dtype or size")
-        if gamma is not None and (gamma.dtype != torch.float32 or gamma.numel() < 1):
-            raise ValueError("gamma must be a float32 tensor with one element")
+        self._check_buf(T, torch.complex64, nframes * self.n_dst, "T")
+        for t, n, dt, nm in ((S, self.n_src, torch.complex64, "S"),
+                             (Sd, self.n_src, torch.complex64, "Sd"),
+                             (idx, self.n_src, torch.int32, "idx"),
+                             (colstats, 3, torch.float64, "colstats")):
+            self._check_buf(t, dt, nframes * n, nm)
+        self._check_buf(gamma, torch.float32, 1, "gamma")
         aux = FwdAux(_ptr(S), _ptr(Sd), _ptr(idx), _ptr(colstats), _ptr(gamma))
         if kernel_events is not None:
             for i, ev in enumerate(kernel_events):
                 if not ev.cuda_event:
                     raise ValueError("kernel_events must have been recorded once")
                 aux.kernel_events[i] = ev.cuda_event
-        _check(lib().sst_forward(self._h, ctypes.c_void_p(x.data_ptr()), int(frame0),
-                                 int(nframes), ctypes.c_void_p(T.data_ptr()), ctypes.byref(aux),
-                                 SST_FWD_REUSE_GAMMA if reuse_gamma else 0,
-                                 ctypes.c_void_p(_stream_handle(self.device))), "sst_forward")
+        _check(fn(self._h, ctypes.c_void_p(x.data_ptr()), int(frame0), int(nframes),
+                  ctypes.c_void_p(T.data_ptr()), ctypes.byref(aux),
+                  SST_FWD_REUSE_GAMMA if reuse_gamma else 0,
+                  ctypes.c_void_p(_stream_handle(self.device))), where)
         return T
 
     def ridge(self, T, bands: Sequence[Sequence[int]], nframes: Optional[int] = None,
-              out=None):
-        """Per-frame argmax ridge of each component inside its destination-bin band."""
+              out=None, centre=None):
+        """Per-frame argmax ridge of each component inside its destination-bin band
+        (sst_ridge), or inside bands relative to a per-frame guide bin
+        centre[q, m] (sst_ridge_guided)."""
         import torch
         self._need_bound()
         if nframes is None:
@@ -311,9 +330,18 @@ class Plan:
         arr = (ctypes.c_int32 * (2 * n_comp))(*[int(v) for b in bands for v in b])
         if out is None:
             out = torch.empty((n_comp, nframes), dtype=torch.int32, device=self.device)
-        _check(lib().sst_ridge(self._h, ctypes.c_void_p(T.data_ptr()), int(nframes), arr,
-                               n_comp, ctypes.c_void_p(out.data_ptr()),
-                               ctypes.c_void_p(_stream_handle(self.device))), "sst_ridge")
+        self._check_buf(T, torch.complex64, nframes * self.n_dst, "T")
+        self._check_buf(out, torch.int32, n_comp * nframes, "out")
+        stream = ctypes.c_void_p(_stream_handle(self.device))
+        if centre is None:
+            _check(lib().sst_ridge(self._h, ctypes.c_void_p(T.data_ptr()), int(nframes), arr,
+                                   n_comp, ctypes.c_void_p(out.data_ptr()), stream), "sst_ridge")
+        else:
+            self._check_buf(centre, torch.int32, n_comp * nframes, "centre")
+            _check(lib().sst_ridge_guided(self._h, ctypes.c_void_p(T.data_ptr()), int(nframes),
+                                          ctypes.c_void_p(centre.data_ptr()), arr, n_comp,
+                                          ctypes.c_void_p(out.data_ptr()), stream),
+                   "sst_ridge_guided")
         return out
 
     def inverse(self, T, ridge, hw: int, xhat=None, frame0: int = 0,
@@ -324,20 +352,16 @@ class Plan:
         self._need_bound()
         if nframes is None:
             nframes = T.shape[0]
-        if ridge.dtype != torch.int32 or not ridge.is_contiguous():
-            raise ValueError("ridge must be a contiguous int32 tensor [n_comp, nframes]")
         n_comp = ridge.shape[0] if ridge.dim() == 2 else 1
         if ridge.numel() != n_comp * nframes:
             raise ValueError("ridge must hold n_comp * nframes entries")
+        self._check_buf(ridge, torch.int32, n_comp * nframes, "ridge")
+        self._check_buf(T, torch.complex64, nframes * self.n_dst, "T")
         if xhat is None:
             xhat = torch.empty((n_comp, self.n_samples), dtype=torch.float32, device=self.device)
-        if xhat.dtype != torch.float32 or xhat.numel() < n_comp * self.n_samples:
-            raise ValueError("xhat must be float32 [n_comp, n_samples]")
-        if xref is not None and (xref.dtype != torch.float32 or
-                                 xref.numel() < n_comp * self.n_samples):
-            raise ValueError("xref must be float32 [n_comp, n_samples]")
-        if err is not None and (err.dtype != torch.float64 or err.numel() < 2 * n_comp):
-            raise ValueError("err must be float64 [n_comp, 2]")
+        self._check_buf(xhat, torch.float32, n_comp * self.n_samples, "xhat")
+        self._check_buf(xref, torch.float32, n_comp * self.n_samples, "xref")
+        self._check_buf(err, torch.float64, 2 * n_comp, "err")
         flags = (SST_INV_ACCUMULATE if accumulate else 0) | (SST_INV_EQ15 if eq15 else 0)
         _check(lib().sst_inverse(self._h, ctypes.c_void_p(T.data_ptr()), int(frame0),
                                  int(nframes), ctypes.c_void_p(ridge.data_ptr()), int(n_comp),
@@ -401,6 +425,16 @@ class Batch:
         """Record channel c's buffers (kept alive by the batch until replaced)."""
         import torch
         sh = self.shapes[c]
+        for t, nm in ((x, "x"), (T, "T"), (ridge, "ridge"), (xhat, "xhat"), (xref, "xref"),
+                      (err, "err")):
+            if t is not None and (t.device != self.device or not t.is_contiguous()):
+                raise ValueError(f"channel {c}: {nm} must be contiguous on {self.device}")
+        if xref is not None and (xref.dtype != torch.float32 or xhat is None
+                                 or xref.numel() < xhat.numel()):
+            raise ValueError(f"channel {c}: xref must be float32 shaped like xhat")
+        if err is not None and (err.dtype != torch.float64 or ridge is None
+                                or err.numel() < 2 * (ridge.shape[0] if ridge.dim() == 2 else 1)):
+            raise ValueError(f"channel {c}: err must be float64 [n_comp, 2]")
         if x is None or x.dtype != torch.float32 or x.numel() != sh.n_samples:
             raise ValueError(f"channel {c}: x must be float32 with n_samples elements")
         if T is None or T.dtype != torch.complex64 or T.numel() < sh.n_frames * sh.n_dst:

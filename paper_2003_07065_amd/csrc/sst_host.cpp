@@ -57,6 +57,19 @@ bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 
 }  // namespace
 
+// A plan's device state: the workspace holding its tables and the launch
+// limits of the device it lives on.
+struct Bound {
+    unsigned char *ws = nullptr;
+    int device = -1;
+    int cus = 0;
+    int fwd_grid_cap = 0;
+    int max_grid_cap = 0;
+    // a thresholding forward has set gamma in this workspace (cleared by every
+    // bind, which leaves the control block unset)
+    bool gamma_valid = false;
+};
+
 struct sst_plan_s {
     sst_params p{};
     int M = 0, k1 = 0, k2 = 0, n_src = 0, n_dst = 0;
@@ -79,12 +92,7 @@ struct sst_plan_s {
     int64_t n_items = 0;
     size_t off_smin = 0, off_list = 0, off_list_n = 0;
     std::vector<unsigned char> blob;   // host image of [off_win, tables_end)
-    // bound state
-    unsigned char *ws = nullptr;
-    int device = -1;
-    int cus = 0;
-    int fwd_grid_cap = 0;
-    int max_grid_cap = 0;
+    Bound bd;                          // the workspace bound by sst_plan_bind
 };
 
 namespace {
@@ -134,8 +142,9 @@ sst_status validate(const sst_params *p)
 }
 
 // Descriptor of one channel for a forward call over frames [frame0, frame0 + nframes).
-sst::ChanDesc chan_desc(const sst_plan_s *pl, const float *x, int64_t frame0, int64_t nframes,
-                        float *T, const sst_fwd_aux *aux, sst::Ctrl *ctrl)
+sst::ChanDesc chan_desc(const sst_plan_s *pl, const unsigned char *ws, const float *x,
+                        int64_t frame0, int64_t nframes, float *T, const sst_fwd_aux *aux,
+                        sst::Ctrl *ctrl)
 {
     sst::ChanDesc d{};
     d.x = x;
@@ -143,7 +152,7 @@ sst::ChanDesc chan_desc(const sst_plan_s *pl, const float *x, int64_t frame0, in
     d.n_frames = pl->n_frames;
     d.frame0 = frame0;
     d.nframes = nframes;
-    d.win = reinterpret_cast<const float2 *>(pl->ws + pl->off_win);
+    d.win = reinterpret_cast<const float2 *>(ws + pl->off_win);
     d.ctrl = ctrl;
     d.T = reinterpret_cast<float2 *>(T);
     if (aux) {
@@ -177,10 +186,10 @@ sst::InvDesc inv_desc(const sst_plan_s *pl, const float *T, int64_t frame0, int6
     a.xhat = xhat;
     a.xref = xref;
     a.err = err;
-    a.win = reinterpret_cast<const float2 *>(pl->ws + pl->off_win);
-    a.ph_lo = reinterpret_cast<const float2 *>(pl->ws + pl->off_phlo);
-    a.ph_hi = reinterpret_cast<const float2 *>(pl->ws + pl->off_phhi);
-    a.den = reinterpret_cast<const float *>(pl->ws + pl->off_den);
+    a.win = reinterpret_cast<const float2 *>(pl->bd.ws + pl->off_win);
+    a.ph_lo = reinterpret_cast<const float2 *>(pl->bd.ws + pl->off_phlo);
+    a.ph_hi = reinterpret_cast<const float2 *>(pl->bd.ws + pl->off_phhi);
+    a.den = reinterpret_cast<const float *>(pl->bd.ws + pl->off_den);
     a.n = pl->p.n_samples;
     a.n_frames = pl->n_frames;
     a.frame0 = frame0;
@@ -326,6 +335,46 @@ void build_afrag(sst_plan_s *pl, const std::vector<double> &g, const std::vector
                         hi[o] = to_bf16((float)v);
                     }
                 }
+}
+
+
+// Device state of a binding to the workspace `ws` on the current device:
+// launch limits from the device attributes, then the plan's tables uploaded
+// with one asynchronous copy on `s` (no allocation).
+sst_status bind_impl(sst_plan_s *pl, Bound &bd, unsigned char *ws, hipStream_t s)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return hip_fail(e, "hipGetDevice");
+    int cus = 0;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess)
+        return hip_fail(e, "hipDeviceGetAttribute");
+    int max_lds = 0;
+    e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    if (e != hipSuccess)
+        return hip_fail(e, "hipDeviceGetAttribute(shared memory)");
+    const size_t need = sst::fwd_lds_bytes(pl->p.nfft);
+    if (need == 0 || need > (size_t)max_lds)
+        return fail(SST_E_UNSUPPORTED, "forward kernel needs " + std::to_string(need) +
+                                           " bytes of LDS, the device offers " +
+                                           std::to_string(max_lds));
+    e = hipMemcpyAsync(ws + pl->off_win, pl->blob.data(), pl->blob.size(),
+                       hipMemcpyHostToDevice, s);
+    if (e != hipSuccess)
+        return hip_fail(e, "hipMemcpyAsync(tables)");
+    bd.ws = ws;
+    bd.device = dev;
+    bd.cus = cus;
+    bd.gamma_valid = false;
+    bd.fwd_grid_cap = cus * sst::fwd_occupancy(pl->p.nfft, pl->p.win_len);
+    if (pl->gemm_ft)
+        bd.fwd_grid_cap = cus * sst::gemm_occupancy(
+            pl->p.precision, pl->gemm_ft,
+            sst::gemm_lds_bytes(pl->p.precision, pl->gemm_ft, pl->n_dst, pl->slab, pl->p.win_len));
+    bd.max_grid_cap = cus * sst::max_occupancy(pl->p.nfft, pl->p.win_len);
+    return SST_OK;
 }
 
 }  // namespace
@@ -536,59 +585,42 @@ sst_status sst_plan_bind(sst_plan_t pl, void *workspace, size_t bytes, void *str
     if (!workspace || bytes < pl->ws_bytes || (reinterpret_cast<uintptr_t>(workspace) % kAlign))
         return fail(SST_E_WORKSPACE, "workspace NULL, not 256-byte aligned, or smaller than "
                                      "sst_shape.workspace_bytes");
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess)
-        return hip_fail(e, "hipGetDevice");
-    int cus = 0;
-    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e != hipSuccess)
-        return hip_fail(e, "hipDeviceGetAttribute");
-    unsigned char *ws = static_cast<unsigned char *>(workspace);
-    e = hipMemcpyAsync(ws + pl->off_win, pl->blob.data(), pl->blob.size(),
-                       hipMemcpyHostToDevice, s);
-    if (e != hipSuccess)
-        return hip_fail(e, "hipMemcpyAsync(tables)");
-    int max_lds = 0;
-    e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
-    if (e != hipSuccess)
-        return hip_fail(e, "hipDeviceGetAttribute(shared memory)");
-    const size_t need = sst::fwd_lds_bytes(pl->p.nfft);
-    if (need == 0 || need > (size_t)max_lds)
-        return fail(SST_E_UNSUPPORTED, "forward kernel needs " + std::to_string(need) +
-                                           " bytes of LDS, the device offers " +
-                                           std::to_string(max_lds));
-    pl->ws = ws;
-    pl->device = dev;
-    pl->cus = cus;
-    pl->fwd_grid_cap = cus * sst::fwd_occupancy(pl->p.nfft, pl->p.win_len);
-    if (pl->gemm_ft)
-        pl->fwd_grid_cap = cus * sst::gemm_occupancy(
-            pl->p.precision, pl->gemm_ft,
-            sst::gemm_lds_bytes(pl->p.precision, pl->gemm_ft, pl->n_dst, pl->slab, pl->p.win_len));
-    pl->max_grid_cap = cus * sst::max_occupancy(pl->p.nfft, pl->p.win_len);
-    return SST_OK;
+    return bind_impl(pl, pl->bd, static_cast<unsigned char *>(workspace),
+                     reinterpret_cast<hipStream_t>(stream));
 }
+
+static sst_status forward_impl(sst_plan_s *pl, Bound &bd, const float *x, int64_t frame0,
+                               int64_t nframes, float *T, const sst_fwd_aux *aux, uint32_t flags,
+                               void *stream);
 
 sst_status sst_forward(sst_plan_t pl, const float *x, int64_t frame0, int64_t nframes, float *T,
                        const sst_fwd_aux *aux, uint32_t flags, void *stream)
 {
     if (!pl)
         return fail(SST_E_ARG, "plan is NULL");
-    if (!pl->ws)
+    if (!pl->bd.ws)
         return fail(SST_E_STATE, "plan is not bound to a workspace");
+    return forward_impl(pl, pl->bd, x, frame0, nframes, T, aux, flags, stream);
+}
+
+static sst_status forward_impl(sst_plan_s *pl, Bound &bd, const float *x, int64_t frame0,
+                               int64_t nframes, float *T, const sst_fwd_aux *aux, uint32_t flags,
+                               void *stream)
+{
     if (!x || !T)
         return fail(SST_E_ARG, "x and T must not be NULL");
     if (frame0 < 0 || nframes < 0 || frame0 + nframes > pl->n_frames)
         return fail(SST_E_ARG, "frame range outside [0, n_frames)");
     if (flags & ~SST_FWD_REUSE_GAMMA)
         return fail(SST_E_ARG, "unknown forward flags");
+    if ((flags & SST_FWD_REUSE_GAMMA) && !bd.gamma_valid)
+        return fail(SST_E_STATE, "SST_FWD_REUSE_GAMMA before any thresholding forward call on "
+                                 "this binding");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const int NF = pl->p.nfft;
     const int F = sst::fwd_frames_per_iter(NF);
-    sst::Ctrl *ctrl = reinterpret_cast<sst::Ctrl *>(pl->ws);
-    sst::ChanDesc *slot = reinterpret_cast<sst::ChanDesc *>(pl->ws + pl->off_desc);
+    sst::Ctrl *ctrl = reinterpret_cast<sst::Ctrl *>(bd.ws);
+    sst::ChanDesc *slot = reinterpret_cast<sst::ChanDesc *>(bd.ws + pl->off_desc);
     const bool threshold = !(flags & SST_FWD_REUSE_GAMMA);
     const bool rel = pl->p.thr_mode == SST_THR_REL_MAX;
     const bool fft = !pl->gemm_ft;
@@ -598,7 +630,7 @@ sst_status sst_forward(sst_plan_t pl, const float *x, int64_t frame0, int64_t nf
     // decisions the final gamma changes.
     const bool spec = threshold && rel && fft && !debug && frame0 == 0 &&
                       nframes == pl->n_frames && nframes > 0;
-    sst::ChanDesc d = chan_desc(pl, x, frame0, nframes, T, aux, ctrl);
+    sst::ChanDesc d = chan_desc(pl, bd.ws, x, frame0, nframes, T, aux, ctrl);
     d.item0 = 0;
     d.item_end = (nframes + F - 1) / F;
     d.mitem0 = 0;
@@ -606,8 +638,8 @@ sst_status sst_forward(sst_plan_t pl, const float *x, int64_t frame0, int64_t nf
     // pairs (the GEMM tiers' two-frames-per-FFT pre-pass)
     d.mitem_end = !(threshold && rel) ? 0
                   : fft ? (pl->n_frames + F - 1) / F : ((pl->n_frames + 1) / 2 + F - 1) / F;
-    int32_t *list = fft ? reinterpret_cast<int32_t *>(pl->ws + pl->off_list) : nullptr;
-    int32_t *list_n = fft ? reinterpret_cast<int32_t *>(pl->ws + pl->off_list_n) : nullptr;
+    int32_t *list = fft ? reinterpret_cast<int32_t *>(bd.ws + pl->off_list) : nullptr;
+    int32_t *list_n = fft ? reinterpret_cast<int32_t *>(bd.ws + pl->off_list_n) : nullptr;
     // the upload also clears the running maximum (and the fix-up count)
     hipError_t e = sst::launch_put_desc(d, slot, threshold && fft, spec ? list_n : nullptr, s);
     if (e != hipSuccess)
@@ -615,26 +647,30 @@ sst_status sst_forward(sst_plan_t pl, const float *x, int64_t frame0, int64_t nf
     sst::GroupLaunch g{};
     g.ch = slot;
     g.n_ch = 1;
-    g.twid = reinterpret_cast<const float2 *>(pl->ws + pl->off_twid);
+    g.twid = reinterpret_cast<const float2 *>(bd.ws + pl->off_twid);
     if (threshold && !fft) {
         g.item_begin = 0;
         g.item_stop = d.mitem_end;
-        const int grid = (int)(d.mitem_end < pl->max_grid_cap ? d.mitem_end : pl->max_grid_cap);
+        const int grid = (int)(d.mitem_end < bd.max_grid_cap ? d.mitem_end : bd.max_grid_cap);
         e = sst::launch_threshold(NF, pl->p.win_len, g, grid, s);
         if (e != hipSuccess)
             return hip_fail(e, "threshold launch");
+        bd.gamma_valid = true;
     } else if (threshold) {
         g.item_begin = 0;
         g.item_stop = d.mitem_end;
-        g.step = spec ? (int)seed_step(d.mitem_end, pl->fwd_grid_cap) : 1;
+        g.step = spec ? (int)seed_step(d.mitem_end, bd.fwd_grid_cap) : 1;
         const int64_t visits = (d.mitem_end + g.step - 1) / g.step;
-        const int grid = (int)(visits < pl->fwd_grid_cap ? visits : pl->fwd_grid_cap);
+        const int grid = (int)(visits < bd.fwd_grid_cap ? visits : bd.fwd_grid_cap);
         e = sst::launch_max_prepass(NF, pl->p.win_len, g, grid, s);
         g.step = 0;
         if (e == hipSuccess && !spec)
             e = sst::launch_gamma(g, s);
         if (e != hipSuccess)
             return hip_fail(e, "threshold launch");
+        // the speculative path sets gamma in spec_list_kernel, launched below
+        // in the same call (an error there returns before anything reuses it)
+        bd.gamma_valid = !spec;
     }
     if (aux && aux->gamma && !spec) {
         e = hipMemcpyAsync(aux->gamma, &ctrl->gamma, sizeof(float), hipMemcpyDeviceToDevice, s);
@@ -651,9 +687,9 @@ sst_status sst_forward(sst_plan_t pl, const float *x, int64_t frame0, int64_t nf
         ga.n = pl->p.n_samples;
         ga.frame0 = frame0;
         ga.nframes = nframes;
-        ga.afrag = pl->ws + pl->off_afrag;
-        ga.afrag_lo = pl->off_afrag_lo ? pl->ws + pl->off_afrag_lo : nullptr;
-        ga.win = reinterpret_cast<const float2 *>(pl->ws + pl->off_win);
+        ga.afrag = bd.ws + pl->off_afrag;
+        ga.afrag_lo = pl->off_afrag_lo ? bd.ws + pl->off_afrag_lo : nullptr;
+        ga.win = reinterpret_cast<const float2 *>(bd.ws + pl->off_win);
         ga.ctrl = ctrl;
         ga.T = reinterpret_cast<float2 *>(T);
         if (aux) {
@@ -677,7 +713,7 @@ sst_status sst_forward(sst_plan_t pl, const float *x, int64_t frame0, int64_t nf
         ga.bound_c = (float)(1.1 * std::sqrt(2.0 * pl->n_src * pl->p.nfft));
         ga.gmax2 = pl->gmax2;
         const int64_t tiles = (nframes + pl->gemm_ft - 1) / pl->gemm_ft;
-        const int grid = (int)(tiles < pl->fwd_grid_cap ? tiles : pl->fwd_grid_cap);
+        const int grid = (int)(tiles < bd.fwd_grid_cap ? tiles : bd.fwd_grid_cap);
         const bool dbg = aux && (aux->S || aux->Sd || aux->idx);
         e = record_event(aux, 0, s);
         if (e == hipSuccess)
@@ -690,7 +726,7 @@ sst_status sst_forward(sst_plan_t pl, const float *x, int64_t frame0, int64_t nf
     }
     g.item_begin = 0;
     g.item_stop = d.item_end;
-    const int grid = (int)(d.item_end < pl->fwd_grid_cap ? d.item_end : pl->fwd_grid_cap);
+    const int grid = (int)(d.item_end < bd.fwd_grid_cap ? d.item_end : bd.fwd_grid_cap);
     if (!spec) {
         e = record_event(aux, 0, s);
         if (e == hipSuccess)
@@ -702,7 +738,7 @@ sst_status sst_forward(sst_plan_t pl, const float *x, int64_t frame0, int64_t nf
         return SST_OK;
     }
     g.spec = 1;
-    g.smin = reinterpret_cast<float *>(pl->ws + pl->off_smin);
+    g.smin = reinterpret_cast<float *>(bd.ws + pl->off_smin);
     e = record_event(aux, 0, s);
     if (e == hipSuccess)
         e = sst::launch_forward(NF, pl->p.win_len, pl->n_src, pl->n_dst, false, g, grid, s);
@@ -713,6 +749,8 @@ sst_status sst_forward(sst_plan_t pl, const float *x, int64_t frame0, int64_t nf
     g.list_n = list_n;
     if (e == hipSuccess)
         e = sst::launch_spec_list(g, s);   // gamma, then the fix-up list
+    if (e == hipSuccess)
+        bd.gamma_valid = true;
     g.smin = nullptr;
     if (e == hipSuccess)
         e = sst::launch_forward(NF, pl->p.win_len, pl->n_src, pl->n_dst, false, g, grid, s);
@@ -726,12 +764,12 @@ sst_status sst_forward(sst_plan_t pl, const float *x, int64_t frame0, int64_t nf
     return SST_OK;
 }
 
-sst_status sst_ridge(sst_plan_t pl, const float *T, int64_t nframes, const int32_t *band,
-                     int32_t n_comp, int32_t *ridge, void *stream)
+static sst_status ridge_impl(sst_plan_t pl, const float *T, int64_t nframes, const int32_t *band,
+                             const int32_t *centre, int32_t n_comp, int32_t *ridge, void *stream)
 {
     if (!pl)
         return fail(SST_E_ARG, "plan is NULL");
-    if (!pl->ws)
+    if (!pl->bd.ws)
         return fail(SST_E_STATE, "plan is not bound to a workspace");
     if (!T || !band || !ridge)
         return fail(SST_E_ARG, "T, band and ridge must not be NULL");
@@ -739,6 +777,9 @@ sst_status sst_ridge(sst_plan_t pl, const float *T, int64_t nframes, const int32
         return fail(SST_E_ARG, "n_comp must lie in [1, 16]");
     if (nframes < 0 || nframes > pl->n_frames)
         return fail(SST_E_ARG, "nframes outside [0, n_frames]");
+    for (int q = 0; q < n_comp; ++q)
+        if (centre && (band[2 * q] < -pl->n_dst || band[2 * q + 1] > pl->n_dst))
+            return fail(SST_E_ARG, "relative band outside [-n_dst, n_dst]");
     if (nframes == 0)
         return SST_OK;
     sst::RidgeArgs a{};
@@ -750,11 +791,26 @@ sst_status sst_ridge(sst_plan_t pl, const float *T, int64_t nframes, const int32
         a.band[2 * q] = band[2 * q];
         a.band[2 * q + 1] = band[2 * q + 1];
     }
+    a.centre = centre;
     a.ridge = ridge;
     hipError_t e = sst::launch_ridge(a, reinterpret_cast<hipStream_t>(stream));
     if (e != hipSuccess)
         return hip_fail(e, "ridge launch");
     return SST_OK;
+}
+
+sst_status sst_ridge(sst_plan_t pl, const float *T, int64_t nframes, const int32_t *band,
+                     int32_t n_comp, int32_t *ridge, void *stream)
+{
+    return ridge_impl(pl, T, nframes, band, nullptr, n_comp, ridge, stream);
+}
+
+sst_status sst_ridge_guided(sst_plan_t pl, const float *T, int64_t nframes, const int32_t *centre,
+                            const int32_t *band, int32_t n_comp, int32_t *ridge, void *stream)
+{
+    if (!centre)
+        return fail(SST_E_ARG, "centre must not be NULL");
+    return ridge_impl(pl, T, nframes, band, centre, n_comp, ridge, stream);
 }
 
 sst_status sst_inverse(sst_plan_t pl, const float *T, int64_t frame0, int64_t nframes,
@@ -763,7 +819,7 @@ sst_status sst_inverse(sst_plan_t pl, const float *T, int64_t frame0, int64_t nf
 {
     if (!pl)
         return fail(SST_E_ARG, "plan is NULL");
-    if (!pl->ws)
+    if (!pl->bd.ws)
         return fail(SST_E_STATE, "plan is not bound to a workspace");
     if (!T || !ridge || !xhat)
         return fail(SST_E_ARG, "T, ridge and xhat must not be NULL");
@@ -784,7 +840,7 @@ sst_status sst_inverse(sst_plan_t pl, const float *T, int64_t frame0, int64_t nf
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     sst::InvDesc a = inv_desc(pl, T, frame0, nframes, ridge, n_comp, hw, xhat, xref, err,
                               accumulate);
-    sst::InvDesc *slot = reinterpret_cast<sst::InvDesc *>(pl->ws + pl->off_idesc);
+    sst::InvDesc *slot = reinterpret_cast<sst::InvDesc *>(pl->bd.ws + pl->off_idesc);
 
     if (flags & SST_INV_EQ15) {
         if (pl->p.hop != 1)
@@ -855,6 +911,8 @@ struct sst_batch_s {
     std::vector<sst::InvDesc> idesc;   // one per channel, channel order
     unsigned char *ws = nullptr;
     bool committed = false;
+    // per channel: a thresholding batched forward has set its gamma since the bind
+    std::vector<char> gamma_valid;
     ~sst_batch_s()
     {
         for (sst_plan_s *p : plans)
@@ -973,15 +1031,16 @@ sst_status sst_batch_bind(sst_batch_t b, void *workspace, size_t bytes, void *st
     }
     for (auto &gr : b->groups) {
         const sst_plan_s *p0 = b->plans[(size_t)gr.chans[0]];
-        gr.fwd_grid_cap = p0->fwd_grid_cap;
-        gr.max_grid_cap = p0->max_grid_cap;
+        gr.fwd_grid_cap = p0->bd.fwd_grid_cap;
+        gr.max_grid_cap = p0->bd.max_grid_cap;
         for (int c : gr.chans) {
-            gr.fwd_grid_cap = std::max(gr.fwd_grid_cap, b->plans[(size_t)c]->fwd_grid_cap);
-            gr.max_grid_cap = std::max(gr.max_grid_cap, b->plans[(size_t)c]->max_grid_cap);
+            gr.fwd_grid_cap = std::max(gr.fwd_grid_cap, b->plans[(size_t)c]->bd.fwd_grid_cap);
+            gr.max_grid_cap = std::max(gr.max_grid_cap, b->plans[(size_t)c]->bd.max_grid_cap);
         }
     }
     b->ws = ws;
     b->committed = false;
+    b->gamma_valid.assign(b->plans.size(), 0);
     return SST_OK;
 }
 
@@ -1025,8 +1084,8 @@ sst_status sst_batch_commit(sst_batch_t b, void *stream)
             const sst_plan_s *pl = b->plans[(size_t)c];
             const sst_batch_s::Io &o = b->io[(size_t)c];
             const int F = sst::fwd_frames_per_iter(pl->p.nfft);
-            sst::ChanDesc d = chan_desc(pl, o.x, 0, pl->n_frames, o.T, nullptr,
-                                        reinterpret_cast<sst::Ctrl *>(pl->ws));
+            sst::ChanDesc d = chan_desc(pl, pl->bd.ws, o.x, 0, pl->n_frames, o.T, nullptr,
+                                        reinterpret_cast<sst::Ctrl *>(pl->bd.ws));
             d.item0 = items;
             items += (pl->n_frames + F - 1) / F;
             d.item_end = items;
@@ -1076,9 +1135,16 @@ sst_status sst_batch_forward(sst_batch_t b, int32_t c_begin, int32_t c_end, uint
         return fail(SST_E_ARG, "channel range empty or outside [0, n_channels)");
     if (flags & ~SST_FWD_REUSE_GAMMA)
         return fail(SST_E_ARG, "unknown forward flags");
-    for (int c = c_begin; c < c_end; ++c)
+    for (int c = c_begin; c < c_end; ++c) {
         if (!b->io[(size_t)c].x || !b->io[(size_t)c].T)
             return fail(SST_E_ARG, "channel " + std::to_string(c) + " has no x or T");
+        if ((flags & SST_FWD_REUSE_GAMMA) && !b->gamma_valid[(size_t)c])
+            return fail(SST_E_STATE, "channel " + std::to_string(c) + ": SST_FWD_REUSE_GAMMA "
+                                     "before any thresholding forward call on this binding");
+    }
+    if (!(flags & SST_FWD_REUSE_GAMMA))
+        for (int c = c_begin; c < c_end; ++c)
+            b->gamma_valid[(size_t)c] = 0;   // set again once every launch is queued
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     for (const auto &gr : b->groups) {
         size_t i0 = 0, i1 = 0;
@@ -1093,7 +1159,7 @@ sst_status sst_batch_forward(sst_batch_t b, int32_t c_begin, int32_t c_end, uint
         sst::GroupLaunch g{};
         g.ch = reinterpret_cast<const sst::ChanDesc *>(b->ws + gr.off_desc) + i0;
         g.n_ch = (int)(i1 - i0);
-        g.twid = reinterpret_cast<const float2 *>(p0->ws + p0->off_twid);
+        g.twid = reinterpret_cast<const float2 *>(p0->bd.ws + p0->off_twid);
         // Speculative forward (see sst_forward): the maximum over every
         // kSeedStep-th item, the forward at the lower bound of gamma it gives,
         // gamma, then the items whose decisions the final gamma changes.
@@ -1142,6 +1208,9 @@ sst_status sst_batch_forward(sst_batch_t b, int32_t c_begin, int32_t c_end, uint
         if (e != hipSuccess)
             return hip_fail(e, "batched forward launch");
     }
+    if (!(flags & SST_FWD_REUSE_GAMMA))
+        for (int c = c_begin; c < c_end; ++c)
+            b->gamma_valid[(size_t)c] = 1;
     return SST_OK;
 }
 

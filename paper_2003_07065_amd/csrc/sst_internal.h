@@ -146,7 +146,9 @@ struct RidgeArgs {
     int64_t nframes;
     int n_dst;
     int n_comp;
-    int band[2 * 16];       // inclusive [lo, hi] per component (at most 16)
+    int band[2 * 16];       // inclusive [lo, hi] per component (at most 16); relative
+                            // to centre[q][m] when centre is given
+    const int32_t *centre;  // optional [n_comp][nframes] guide bins (-1: no ridge)
     int32_t *ridge;         // [n_comp][nframes]
 };
 

@@ -1740,11 +1740,6 @@ constexpr int kRidgeFrames = 64;   // frames per workgroup
 __global__ __launch_bounds__(256) void ridge_kernel(RidgeArgs a)
 {
     const int q = blockIdx.y;
-    int lo = a.band[2 * q], hi = a.band[2 * q + 1];
-    if (lo < 0)
-        lo = 0;
-    if (hi > a.n_dst - 1)
-        hi = a.n_dst - 1;
     const int sub = threadIdx.x & 15;
     const int64_t m0 = (int64_t)blockIdx.x * kRidgeFrames + (threadIdx.x >> 4);
     unsigned long long key[4];
@@ -1752,6 +1747,18 @@ __global__ __launch_bounds__(256) void ridge_kernel(RidgeArgs a)
     for (int p = 0; p < 4; ++p) {
         const int64_t m = m0 + 16 * p;
         key[p] = 0ull;
+        // the band, relative to the frame's guide bin when one is given
+        int lo = a.band[2 * q], hi = a.band[2 * q + 1];
+        int ctr = 0;
+        bool none = false;
+        if (a.centre && m < a.nframes) {
+            ctr = a.centre[(int64_t)q * a.nframes + m];
+            none = ctr < 0;   // no guide: no ridge in this frame
+        }
+        lo = lo + ctr < 0 ? 0 : lo + ctr;
+        hi = hi + ctr > a.n_dst - 1 ? a.n_dst - 1 : hi + ctr;
+        if (none)
+            hi = -1;
         if (m < a.nframes) {
             const v2 *__restrict__ row = reinterpret_cast<const v2 *>(a.T) + m * a.n_dst;
             for (int l = lo + sub; l <= hi; l += 16) {

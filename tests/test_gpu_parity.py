@@ -332,6 +332,59 @@ def test_ridge_matches_oracle(sst):
         assert len(diff) <= 2
 
 
+def test_ridge_guided_matches_oracle(sst):
+    """Ridges searched around a per-frame guide bin (sst_ridge_guided): the
+    oracle's ridge of each frame's own band, frames without a guide give -1, and
+    bands reaching past either end of the grid are clipped."""
+    w = make_c2(n=1 << 15)
+    o = oracle.forward(w.x.astype(np.float64), w.cfg)
+    plan = sst.Plan.from_config(w.n, w.cfg, device="cuda")
+    T32 = o.T.astype(np.complex64)
+    nfr = T32.shape[0]
+    rng = np.random.default_rng(7)
+    centre = np.stack([
+        np.full(nfr, 80, dtype=np.int32),
+        rng.integers(0, plan.n_dst, nfr).astype(np.int32),     # clipped at both ends
+        np.where(np.arange(nfr) % 5 == 0, -1, 385).astype(np.int32)])
+    rel = [(-12, 12), (-30, 30), (-3, 9)]
+    r_g = plan.ridge(torch.from_numpy(T32).cuda(), rel,
+                     centre=torch.from_numpy(centre).cuda()).cpu().numpy()
+    T64 = T32.astype(np.complex128)
+    mag = np.abs(T64) ** 2
+    for q, (a, b) in enumerate(rel):
+        for m in range(nfr):
+            c = int(centre[q, m])
+            if c < 0:
+                assert r_g[q, m] == -1
+                continue
+            la, lb = max(c + a, 0), min(c + b, plan.n_dst - 1)
+            r_o = int(oracle.ridge(T64[m:m + 1], la, lb)[0])
+            if r_g[q, m] != r_o:   # only near-ties may differ (FP32 vs FP64 |T|^2)
+                assert la <= r_g[q, m] <= lb
+                x, y = mag[m, r_g[q, m]], mag[m, r_o]
+                assert abs(x - y) <= 1e-6 * max(x, y), (q, m)
+
+
+def test_reuse_gamma_needs_a_threshold_since_bind(sst):
+    """SST_FWD_REUSE_GAMMA before any thresholding call on a binding (fresh, or
+    after a rebind) is refused with SST_E_STATE instead of thresholding against
+    an unset control block."""
+    cfg = CASES[2][2]
+    x = torch.from_numpy(_signal("reuse", 10007, cfg.fs)).cuda()
+    plan = sst.Plan.from_config(10007, cfg, device="cuda")
+    with pytest.raises(sst.SSTError) as e:
+        plan.forward(x, None, 0, 16, reuse_gamma=True)
+    assert e.value.status == sst.SST_E_STATE
+    T = plan.forward(x)
+    Tc = plan.forward(x, None, 5, 16, reuse_gamma=True)
+    torch.cuda.synchronize()
+    assert torch.equal(torch.view_as_real(Tc), torch.view_as_real(T[5:21]))
+    plan.bind("cuda")
+    with pytest.raises(sst.SSTError) as e:
+        plan.forward(x, None, 0, 16, reuse_gamma=True)
+    assert e.value.status == sst.SST_E_STATE
+
+
 REPRO = [
     ("c2-shape", 1 << 15, CASES[0][2]),
     ("c3-short", 12345, SSTConfig(25600.0, 2047, 256.0, 32, 8192, 0.0, 5000.0, 8, "rel", 1e-3, 26)),
