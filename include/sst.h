@@ -199,6 +199,31 @@ sst_status sst_forward(sst_plan_t plan, const float *x, int64_t frame0, int64_t 
                        float *T, const sst_fwd_aux *aux, uint32_t flags, void *stream);
 
 /*
+ * sst_forward_static -- sst_forward for callers that cannot allocate device
+ * memory at all: code under stream capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  The plan needs no sst_plan_bind: its workspace is a
+ * fixed array of SST_STATIC_SCRATCH_BYTES inside the library, one per device,
+ * held from the library's first use on that device until the process ends.
+ * The call allocates nothing (no hipMalloc / hipFree, no allocating library
+ * routine); the caller still passes x, T and the optional aux buffers, with
+ * the same layout and meaning as for sst_forward.  The first call of a plan
+ * on a device (or after another plan used that device's scratch) uploads the
+ * plan's tables into the scratch with one asynchronous host-to-device copy
+ * on `stream`.
+ *   Shared state: every sst_forward_static call on a device uses that
+ * device's one scratch array, which keeps the last call's contents (the
+ * kernels clear the counters they need).  Calls that overlap in time on one
+ * device race, whatever their plans and streams; SST_FWD_REUSE_GAMMA needs
+ * the previous static call on the device to have been a thresholding call of
+ * the same plan.
+ * Errors: as sst_forward; SST_E_UNSUPPORTED when the plan's workspace_bytes
+ * exceed SST_STATIC_SCRATCH_BYTES (checked before any device call).
+ */
+#define SST_STATIC_SCRATCH_BYTES (32u << 20)
+sst_status sst_forward_static(sst_plan_t plan, const float *x, int64_t frame0, int64_t nframes,
+                              float *T, const sst_fwd_aux *aux, uint32_t flags, void *stream);
+
+/*
  * sst_ridge -- ridge of each component (Sec. 2.2, zone M_q[m]): for every
  * frame of the chunk and component q, the destination bin of largest |T| in
  * [band[2q], band[2q+1]] (clipped to [0, n_dst)); ties go to the smallest l;

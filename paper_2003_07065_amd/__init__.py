@@ -39,7 +39,7 @@ SST_FWD_REUSE_GAMMA = 1
 SST_INV_ACCUMULATE = 1
 SST_INV_EQ15 = 2
 
-EXPORTED = ("sst_plan", "sst_plan_query", "sst_plan_bind", "sst_forward",
+EXPORTED = ("sst_plan", "sst_plan_query", "sst_plan_bind", "sst_forward", "sst_forward_static",
             "sst_ridge", "sst_ridge_guided",
             "sst_inverse", "sst_destroy", "sst_status_string", "sst_last_error",
             "sst_critical_hf", "sst_batch_plan", "sst_batch_query", "sst_batch_bind",
@@ -119,6 +119,7 @@ def lib():
     L.sst_plan_query.argtypes = [vp, ctypes.POINTER(Shape)]
     L.sst_plan_bind.argtypes = [vp, vp, ctypes.c_size_t, vp]
     L.sst_forward.argtypes = [vp, vp, i64, i64, vp, ctypes.POINTER(FwdAux), u32, vp]
+    L.sst_forward_static.argtypes = [vp, vp, i64, i64, vp, ctypes.POINTER(FwdAux), u32, vp]
     L.sst_ridge.argtypes = [vp, vp, i64, ctypes.POINTER(i32), i32, vp, vp]
     L.sst_ridge_guided.argtypes = [vp, vp, i64, vp, ctypes.POINTER(i32), i32, vp, vp]
     L.sst_inverse.argtypes = [vp, vp, i64, i64, vp, i32, i32, vp, vp, vp, u32, vp]
@@ -141,7 +142,7 @@ def lib():
     L.sst_batch_destroy.argtypes = [vp]
     L.sst_batch_destroy.restype = None
     for name in ("sst_plan", "sst_plan_query", "sst_plan_bind", "sst_forward",
-                 "sst_ridge", "sst_ridge_guided",
+                 "sst_forward_static", "sst_ridge", "sst_ridge_guided",
                  "sst_inverse", "sst_critical_hf", "sst_batch_plan", "sst_batch_query",
                  "sst_batch_bind", "sst_batch_set_io", "sst_batch_commit", "sst_batch_forward",
                  "sst_batch_inverse"):
@@ -286,6 +287,21 @@ class Plan:
         self._need_bound()
         return self._forward_call(lib().sst_forward, "sst_forward", x, T, frame0, nframes, S, Sd,
                                   idx, colstats, gamma, reuse_gamma, kernel_events)
+
+    def forward_static(self, x, T=None, frame0: int = 0, nframes: Optional[int] = None, *,
+                       S=None, Sd=None, idx=None, colstats=None, gamma=None,
+                       reuse_gamma: bool = False, kernel_events=None):
+        """sst_forward_static: as forward(), with the library's fixed per-device
+        scratch as the workspace (no bind, no device allocation by the call;
+        T must then be given)."""
+        import torch
+        if T is None:
+            raise ValueError("forward_static needs a caller-allocated T")
+        if self.device is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        return self._forward_call(lib().sst_forward_static, "sst_forward_static", x, T, frame0,
+                                  nframes, S, Sd, idx, colstats, gamma, reuse_gamma,
+                                  kernel_events)
 
     def _forward_call(self, fn, where, x, T, frame0, nframes, S, Sd, idx, colstats, gamma,
                       reuse_gamma, kernel_events):

@@ -16,6 +16,8 @@
 #include <cmath>
 #include <cstring>
 #include <algorithm>
+#include <atomic>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -26,6 +28,8 @@
 namespace {
 
 thread_local std::string g_err;
+
+std::atomic<uint64_t> g_plan_serial{0};
 
 sst_status fail(sst_status s, const std::string &msg)
 {
@@ -92,6 +96,7 @@ struct sst_plan_s {
     int64_t n_items = 0;
     size_t off_smin = 0, off_list = 0, off_list_n = 0;
     std::vector<unsigned char> blob;   // host image of [off_win, tables_end)
+    uint64_t serial = 0;               // unique per plan (owner of the static scratch)
     Bound bd;                          // the workspace bound by sst_plan_bind
 };
 
@@ -395,6 +400,7 @@ sst_status sst_plan(const sst_params *params, sst_plan_t *out)
     pl->p = *params;
     pl->p.window = nullptr;
     pl->p.dwindow = nullptr;
+    pl->serial = g_plan_serial.fetch_add(1) + 1;
     const sst_params &p = *params;
     const int L = p.win_len, NF = p.nfft, z = p.subdiv;
     pl->M = (L - 1) / 2;
@@ -601,6 +607,44 @@ sst_status sst_forward(sst_plan_t pl, const float *x, int64_t frame0, int64_t nf
     if (!pl->bd.ws)
         return fail(SST_E_STATE, "plan is not bound to a workspace");
     return forward_impl(pl, pl->bd, x, frame0, nframes, T, aux, flags, stream);
+}
+
+// The plan whose tables the static scratch of each device holds (serial 0:
+// none), and that binding's state.  One lock serialises the static calls.
+struct StaticOwner {
+    uint64_t serial = 0;
+    Bound bd;
+};
+static std::mutex g_static_mu;
+static StaticOwner g_static_owner[sst::kMaxDevices];
+
+sst_status sst_forward_static(sst_plan_t pl, const float *x, int64_t frame0, int64_t nframes,
+                              float *T, const sst_fwd_aux *aux, uint32_t flags, void *stream)
+{
+    if (!pl)
+        return fail(SST_E_ARG, "plan is NULL");
+    if (pl->ws_bytes > sst::kStaticScratchBytes)
+        return fail(SST_E_UNSUPPORTED, "the plan needs " + std::to_string(pl->ws_bytes) +
+                                           " bytes of workspace; the static scratch holds " +
+                                           std::to_string(sst::kStaticScratchBytes));
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return hip_fail(e, "hipGetDevice");
+    unsigned char *ptr = nullptr;
+    e = sst::static_scratch(dev, &ptr);
+    if (e != hipSuccess)
+        return hip_fail(e, "hipGetSymbolAddress(static scratch)");
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    StaticOwner &o = g_static_owner[dev];
+    if (o.serial != pl->serial) {
+        o.serial = 0;
+        const sst_status st = bind_impl(pl, o.bd, ptr, reinterpret_cast<hipStream_t>(stream));
+        if (st != SST_OK)
+            return st;
+        o.serial = pl->serial;
+    }
+    return forward_impl(pl, o.bd, x, frame0, nframes, T, aux, flags, stream);
 }
 
 static sst_status forward_impl(sst_plan_s *pl, Bound &bd, const float *x, int64_t frame0,

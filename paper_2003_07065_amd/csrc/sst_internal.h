@@ -191,6 +191,13 @@ hipError_t launch_put_inv_desc(const InvDesc &d, InvDesc *dst, hipStream_t s);
 size_t inv_lds_bytes(const InvLaunch &l);
 hipError_t launch_ridge(const RidgeArgs &a, hipStream_t s);
 
+// Static scratch of sst_forward_static: the device address of this device's
+// copy of a fixed array of kStaticScratchBytes (looked up once per device,
+// with `dev` current).  kMaxDevices bounds the device ordinals served.
+constexpr size_t kStaticScratchBytes = size_t(32) << 20;
+constexpr int kMaxDevices = 64;
+hipError_t static_scratch(int dev, unsigned char **out);
+
 // Kernel geometry, shared so the host can size grids and workspaces.
 int fwd_frames_per_iter(int nfft);   // F
 int fwd_threads(int nfft);           // threads per workgroup

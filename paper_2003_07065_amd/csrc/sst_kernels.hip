@@ -43,6 +43,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "sst_internal.h"
 
 namespace sst {
@@ -2071,6 +2073,34 @@ int max_occupancy(int nfft, int L)
 {
     SST_DISPATCH_NF(nfft, return occ_max_t<NFv>(L))
     return 1;
+}
+
+// ---------------------------------------------------------------------------
+// Fixed device scratch for callers that cannot allocate (sst_forward_static).
+// Each device holds its own copy of the array for the life of the process.
+// Host code never passes `scratch` itself to a kernel: its host-side name is a
+// stand-in, not a device address.  The device address is looked up once per
+// device, with that device current, and cached.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+hipError_t static_scratch(int dev, unsigned char **out)
+{
+    static std::mutex mu;
+    static unsigned char *ptr[kMaxDevices] = {};
+    *out = nullptr;
+    if (dev < 0 || dev >= kMaxDevices)
+        return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return e;
+        ptr[dev] = static_cast<unsigned char *>(p);
+    }
+    *out = ptr[dev];
+    return hipSuccess;
 }
 
 }  // namespace sst

@@ -237,3 +237,14 @@ def test_gemm_precision_validation():
     wide = sst._params(1 << 15, 25600.0, 1023, 128.0, 8, 2048, 0.0, 12800.0, 4, "rel", 1e-3, None,
                        None, keep, "bf16")
     assert L.sst_plan(ctypes.byref(wide), ctypes.byref(h)) == sst.SST_E_UNSUPPORTED
+
+
+def test_forward_static_rejects_oversized_workspace():
+    """sst_forward_static refuses, before any device call, a plan whose workspace
+    exceeds the fixed scratch (2^26 samples at hop 8: 8 bytes per frame of
+    threshold state alone is 67 MB)."""
+    p = sst.Plan(**_params(n_samples=1 << 26, hop=8))
+    assert p.shape.workspace_bytes > 32 << 20
+    st = sst.lib().sst_forward_static(p._h, None, 0, 0, None, None, 0, None)
+    assert st == sst.SST_E_UNSUPPORTED
+    assert b"static scratch" in sst.lib().sst_last_error()
