@@ -373,6 +373,20 @@ def run_single(args):
     xhat = torch.empty((n_comp, w.n), dtype=torch.float32, device=dev)
     stream = torch.cuda.current_stream(dev)
 
+    # launch choices: the library's autotuner on these buffers (before the timed
+    # region), or the defaults
+    t0 = time.perf_counter()
+    if args.no_tune:
+        tuning = dict(plan.get_tuning(), source="default")
+    else:
+        rt = torch.from_numpy(ridge_true).to(dev)
+        tuning = dict(plan.autotune(xg, T, rt, c.hw, xhat, reps=3), source="autotuned")
+        del rt
+        if os.environ.get("SST_TUNE_CACHE"):
+            plan.tuning_save(os.environ["SST_TUNE_CACHE"])
+    tuning["search_s"] = round(time.perf_counter() - t0, 2)
+    log(f"tuning {tuning}")
+
     def step(evs=None):
         if evs:
             evs[0].record(stream)
@@ -470,6 +484,7 @@ def run_single(args):
         "config": {"workload": desc, "n_samples": w.n, "n_frames": plan.n_frames,
                    "n_dst": plan.n_dst, "T_bytes": t_bytes, "generation_s": round(gen_s, 1)},
         "roofline": roof,
+        "tuning": tuning,
         "segments_ms": {"forward_kernel": round(fwd_ms, 4),
                         "threshold_and_fixup": round(thr_ms, 4),
                         "ridge": round(ridge_ms, 4), "inverse": round(inv_ms, 4)},
@@ -511,6 +526,8 @@ def main():
     ap.add_argument("--n", type=int, default=0,
                     help="signal length (default: the workload's, 2^26 for c3, 2^20 for c2)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="use the library's default launch choices instead of autotuning")
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="oracle sample in samples (default 2^20 for c3, 2^18 for c2)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,

@@ -352,6 +352,86 @@ sst_status sst_batch_inverse(sst_batch_t batch, int32_t c_begin, int32_t c_end, 
 /* sst_batch_destroy -- release the batch's host memory. */
 void sst_batch_destroy(sst_batch_t batch);
 
+/*
+ * Launch choices of a plan.  None of them changes T (every forward variant
+ * computes each row with the same arithmetic); the inverse tile width changes
+ * xhat only at the rounding level (about 1e-7 relative).  0 = the library's
+ * default.
+ *   fwd_wg_per_cu  forward workgroups kept resident per CU (1 .. what fits;
+ *                  larger values are capped)
+ *   seed_step      speculative relative threshold: seed the running maximum
+ *                  with every seed_step-th frame group (>= 1)
+ *   inv_tf         inverse: groups of 256 output samples per workgroup, 1 or 4
+ *                  (4 only when the frames 1024 samples meet fit the staged
+ *                  block; SST_E_UNSUPPORTED otherwise)
+ */
+typedef struct {
+    int32_t fwd_wg_per_cu;
+    int32_t seed_step;
+    int32_t inv_tf;
+    int32_t reserved;
+} sst_tuning;
+
+/* sst_plan_get_tuning -- the choices in effect (defaults resolved where known:
+ * fwd_wg_per_cu after bind, inv_tf always; seed_step 0 = automatic). */
+sst_status sst_plan_get_tuning(sst_plan_t plan, sst_tuning *out);
+
+/* sst_plan_set_tuning -- set the launch choices (before or after bind).
+ * Errors: SST_E_ARG (negative values, reserved != 0), SST_E_UNSUPPORTED. */
+sst_status sst_plan_set_tuning(sst_plan_t plan, const sst_tuning *tuning);
+
+/*
+ * sst_autotune -- search the launch choices of a bound plan on the caller's
+ * buffers and keep the fastest: every forward choice (workgroups per CU,
+ * threshold seed step) is timed over the whole signal with HIP events, then,
+ * when ridge and xhat are given, every inverse tile width.  Each candidate
+ * runs once untimed and `reps` times timed (reps >= 1).  Blocks until done
+ * (a set-up call); T and xhat hold the last candidate's results.
+ *   x, T           as for sst_forward over all frames
+ *   ridge, n_comp, hw, xhat   as for sst_inverse (optional: NULL ridge skips
+ *                  the inverse choices)
+ *   best           optional: receives the chosen values
+ * Errors: SST_E_ARG, SST_E_STATE (not bound), SST_E_DEVICE.
+ */
+sst_status sst_autotune(sst_plan_t plan, const float *x, float *T, const int32_t *ridge,
+                        int32_t n_comp, int32_t hw, float *xhat, int32_t reps, void *stream,
+                        sst_tuning *best);
+
+/*
+ * sst_tuning_save / sst_tuning_load -- a JSON cache of tuned choices keyed by
+ * the device architecture and the plan's shape ("gfx950 nfft=.. L=.. H=..
+ * n_src=.. n_dst=.. prec=.."), one entry per line.  save inserts or replaces
+ * the plan's entry with its current choices; load applies the plan's entry
+ * (SST_E_ARG when the file or the entry is missing).  sst_plan and
+ * sst_batch_plan apply the entry of each plan from the file named by the
+ * environment variable SST_TUNE_CACHE, when it holds one.  Host only.
+ */
+sst_status sst_tuning_save(sst_plan_t plan, const char *path);
+sst_status sst_tuning_load(sst_plan_t plan, const char *path);
+
+/*
+ * sst_renyi -- Renyi entropy (Sec. 3, Eq. 32) of a time-frequency
+ * representation, the paper's measure of TF concentration, with P = |C|^2:
+ *   R = 1/(1 - alpha) log2( sum over the grid of (P / sum P)^alpha )
+ * (discrete form: the constant log2 of the cell area is left out, so one
+ * occupied cell gives 0 and K equal cells log2 K).  Plan-independent.
+ *   C      device array [rows][ld] of kind SST_RENYI_COMPLEX64 (complex float,
+ *          e.g. T or S rows), SST_RENYI_MAG_F32 (float |C|) or SST_RENYI_MAG_F16
+ *          (half |C|); only the first cols of each row are read
+ *   alpha  integer order, 2 <= alpha <= 4 (the paper uses 3)
+ *   work   device double [SST_RENYI_WORK_DOUBLES] (per-workgroup partial sums)
+ *   out    device double [3]: sum P, sum P^alpha (float64), R in bits
+ *          (NaN when every P is 0)
+ * The float64 sums are reduced in a fixed order: the result does not depend
+ * on scheduling.  Asynchronous on `stream`.  Errors: SST_E_ARG.
+ */
+#define SST_RENYI_COMPLEX64 0
+#define SST_RENYI_MAG_F32 1
+#define SST_RENYI_MAG_F16 2
+#define SST_RENYI_WORK_DOUBLES 2048
+sst_status sst_renyi(const void *C, int32_t kind, int64_t rows, int32_t cols, int64_t ld,
+                     int32_t alpha, double *work, double *out, void *stream);
+
 /* sst_destroy -- release the plan's host memory (the workspace stays the caller's). */
 void sst_destroy(sst_plan_t plan);
 

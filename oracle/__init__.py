@@ -55,6 +55,8 @@ def _load():
     lib.sso_inverse_eq15.restype = None
     lib.sso_stft_synthesis.argtypes = [_D, _I64, _D, _I, _I, _I, _I64, _D]
     lib.sso_stft_synthesis.restype = None
+    lib.sso_renyi.argtypes = [_D, _I64, _I64, ctypes.c_double]
+    lib.sso_renyi.restype = ctypes.c_double
     lib.sso_num_threads.argtypes = []
     lib.sso_num_threads.restype = _I
     _lib = lib
@@ -197,6 +199,15 @@ def stft_synthesis(S_full, g, hop: int, nfft: int, n: int) -> np.ndarray:
     _load().sso_stft_synthesis(_dp(S_full.view(np.float64)), nframes, _dp(g), g.shape[0],
                                int(hop), int(nfft), int(n), _dp(out))
     return out
+
+
+def renyi(C, alpha: float = 3.0) -> float:
+    """Renyi entropy (bits) of P = |C|^2 over the grid of C (Sec. 3, Eq. 32)."""
+    C = _c128(C)
+    if C.ndim == 1:
+        C = C[None, :]
+    return float(_load().sso_renyi(_dp(C.view(np.float64)), C.shape[0], C.shape[1],
+                                   float(alpha)))
 
 
 @dataclass

@@ -431,6 +431,38 @@ void sso_stft_synthesis(const double *S, int64_t nframes, const double *g, int L
     free(cim);
 }
 
+/* ---------------------------------------------------------------------------
+ * Renyi entropy of a time-frequency representation (Sec. 3, Eq. 32), used by
+ * the paper to measure the concentration of SST and STFT.  Discrete form over
+ * the rows x cols grid of complex coefficients C with P = |C|^2 (the paper does
+ * not define P; reading: the energy of each coefficient):
+ *   R = 1/(1 - alpha) log2( sum_cells (P / sum_cells P)^alpha ),
+ * alpha > 0, alpha != 1.  The integral of Eq. 32 over a grid of cells would add
+ * the constant log2 of the cell area; the discrete form leaves it out, so one
+ * occupied cell gives 0 and K equal cells give log2 K.  Returns NaN for an
+ * all-zero C or an invalid alpha.
+ * ------------------------------------------------------------------------- */
+double sso_renyi(const double *C, int64_t rows, int64_t cols, double alpha)
+{
+    if (!(alpha > 0.0) || alpha == 1.0)
+        return NAN;
+    int64_t n = rows * cols;
+    double tot = 0.0;
+#pragma omp parallel for reduction(+ : tot) schedule(static)
+    for (int64_t i = 0; i < n; ++i)
+        tot += C[2 * i] * C[2 * i] + C[2 * i + 1] * C[2 * i + 1];
+    if (!(tot > 0.0))
+        return NAN;
+    double acc = 0.0;
+#pragma omp parallel for reduction(+ : acc) schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double p = (C[2 * i] * C[2 * i] + C[2 * i + 1] * C[2 * i + 1]) / tot;
+        if (p > 0.0)
+            acc += pow(p, alpha);
+    }
+    return log2(acc) / (1.0 - alpha);
+}
+
 /* Number of OpenMP threads a parallel region of this library uses. */
 int sso_num_threads(void)
 {

@@ -44,7 +44,8 @@ EXPORTED = ("sst_plan", "sst_plan_query", "sst_plan_bind", "sst_forward", "sst_f
             "sst_inverse", "sst_destroy", "sst_status_string", "sst_last_error",
             "sst_critical_hf", "sst_batch_plan", "sst_batch_query", "sst_batch_bind",
             "sst_batch_set_io", "sst_batch_commit", "sst_batch_forward", "sst_batch_inverse",
-            "sst_batch_destroy")
+            "sst_batch_destroy", "sst_plan_get_tuning", "sst_plan_set_tuning", "sst_autotune",
+            "sst_tuning_save", "sst_tuning_load", "sst_renyi")
 
 
 class SSTError(RuntimeError):
@@ -89,6 +90,19 @@ class Shape(ctypes.Structure):
         ("workspace_bytes", ctypes.c_size_t),
         ("t_row_bytes", ctypes.c_size_t),
     ]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [
+        ("fwd_wg_per_cu", ctypes.c_int32),
+        ("seed_step", ctypes.c_int32),
+        ("inv_tf", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+    def as_dict(self):
+        return {"fwd_wg_per_cu": self.fwd_wg_per_cu, "seed_step": self.seed_step,
+                "inv_tf": self.inv_tf}
 
 
 class FwdAux(ctypes.Structure):
@@ -141,11 +155,18 @@ def lib():
     L.sst_batch_inverse.argtypes = [vp, i32, i32, vp]
     L.sst_batch_destroy.argtypes = [vp]
     L.sst_batch_destroy.restype = None
+    L.sst_plan_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+    L.sst_plan_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+    L.sst_autotune.argtypes = [vp, vp, vp, vp, i32, i32, vp, i32, vp, ctypes.POINTER(Tuning)]
+    L.sst_tuning_save.argtypes = [vp, ctypes.c_char_p]
+    L.sst_tuning_load.argtypes = [vp, ctypes.c_char_p]
+    L.sst_renyi.argtypes = [vp, i32, i64, i32, i64, i32, vp, vp, vp]
     for name in ("sst_plan", "sst_plan_query", "sst_plan_bind", "sst_forward",
                  "sst_forward_static", "sst_ridge", "sst_ridge_guided",
                  "sst_inverse", "sst_critical_hf", "sst_batch_plan", "sst_batch_query",
                  "sst_batch_bind", "sst_batch_set_io", "sst_batch_commit", "sst_batch_forward",
-                 "sst_batch_inverse"):
+                 "sst_batch_inverse", "sst_plan_get_tuning", "sst_plan_set_tuning",
+                 "sst_autotune", "sst_tuning_save", "sst_tuning_load", "sst_renyi"):
         getattr(L, name).restype = i32
     _lib = L
     return L
@@ -167,6 +188,32 @@ def critical_hf(n: float, sigma_s: float, fs: float):
     _check(lib().sst_critical_hf(float(n), float(sigma_s), float(fs), ctypes.byref(a),
                                  ctypes.byref(b)), "sst_critical_hf")
     return a.value, b.value
+
+
+SST_RENYI_WORK_DOUBLES = 2048
+_RENYI_KIND = {"complex64": 0, "float32": 1, "float16": 2}
+
+
+def renyi(C, alpha: int = 3, cols: Optional[int] = None, out=None):
+    """sst_renyi: Renyi entropy (bits) of P = |C|^2 over a 2-D device tensor
+    (complex64 coefficients, or float32 / float16 magnitudes).  Returns the
+    device tensor out = [sum P, sum P^alpha, R] (float64)."""
+    import torch
+    if C.dim() != 2 or C.stride(1) != 1:
+        raise ValueError("C must be a 2-D tensor with contiguous rows")
+    kind = {torch.complex64: 0, torch.float32: 1, torch.float16: 2}.get(C.dtype)
+    if kind is None:
+        raise ValueError("C must be complex64, float32 or float16")
+    rows, n = C.shape
+    cols = n if cols is None else int(cols)
+    work = torch.empty(SST_RENYI_WORK_DOUBLES, dtype=torch.float64, device=C.device)
+    if out is None:
+        out = torch.empty(3, dtype=torch.float64, device=C.device)
+    _check(lib().sst_renyi(ctypes.c_void_p(C.data_ptr()), kind, int(rows), cols,
+                           int(C.stride(0)), int(alpha), ctypes.c_void_p(work.data_ptr()),
+                           ctypes.c_void_p(out.data_ptr()),
+                           ctypes.c_void_p(_stream_handle(C.device))), "sst_renyi")
+    return out
 
 
 def _ptr(t) -> Optional[int]:
@@ -385,6 +432,42 @@ class Plan:
                                  ctypes.c_void_p(_ptr(xref)), ctypes.c_void_p(_ptr(err)), flags,
                                  ctypes.c_void_p(_stream_handle(self.device))), "sst_inverse")
         return xhat
+
+    # -- launch choices (sst_plan_get_tuning / sst_plan_set_tuning / sst_autotune) --
+
+    def get_tuning(self) -> dict:
+        t = Tuning()
+        _check(lib().sst_plan_get_tuning(self._h, ctypes.byref(t)), "sst_plan_get_tuning")
+        return t.as_dict()
+
+    def set_tuning(self, fwd_wg_per_cu: int = 0, seed_step: int = 0, inv_tf: int = 0):
+        t = Tuning(int(fwd_wg_per_cu), int(seed_step), int(inv_tf), 0)
+        _check(lib().sst_plan_set_tuning(self._h, ctypes.byref(t)), "sst_plan_set_tuning")
+
+    def autotune(self, x, T, ridge=None, hw: int = 0, xhat=None, reps: int = 3) -> dict:
+        """Time the launch choices on these buffers and keep the fastest."""
+        import torch
+        self._need_bound()
+        self._check_buf(x, torch.float32, self.n_samples, "x")
+        self._check_buf(T, torch.complex64, self.n_frames * self.n_dst, "T")
+        n_comp = 0
+        if ridge is not None:
+            n_comp = ridge.shape[0] if ridge.dim() == 2 else 1
+            self._check_buf(ridge, torch.int32, n_comp * self.n_frames, "ridge")
+            self._check_buf(xhat, torch.float32, n_comp * self.n_samples, "xhat")
+        t = Tuning()
+        _check(lib().sst_autotune(self._h, ctypes.c_void_p(x.data_ptr()),
+                                  ctypes.c_void_p(T.data_ptr()), ctypes.c_void_p(_ptr(ridge)),
+                                  int(n_comp), int(hw), ctypes.c_void_p(_ptr(xhat)), int(reps),
+                                  ctypes.c_void_p(_stream_handle(self.device)), ctypes.byref(t)),
+               "sst_autotune")
+        return t.as_dict()
+
+    def tuning_save(self, path: str):
+        _check(lib().sst_tuning_save(self._h, os.fsencode(path)), "sst_tuning_save")
+
+    def tuning_load(self, path: str):
+        _check(lib().sst_tuning_load(self._h, os.fsencode(path)), "sst_tuning_load")
 
     def close(self):
         if self._h is not None and _lib is not None:

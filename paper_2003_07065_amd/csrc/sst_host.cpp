@@ -14,6 +14,8 @@
 #include <hip/hip_runtime_api.h>
 
 #include <cmath>
+#include <cstdlib>
+#include <cstdio>
 #include <cstring>
 #include <algorithm>
 #include <atomic>
@@ -49,8 +51,10 @@ constexpr size_t kAlign = 256;
 // k = max(kSeedStep, items / workgroups): one round of the grid at most.
 constexpr int kSeedStep = 32;
 
-int64_t seed_step(int64_t items, int grid_cap)
+int64_t seed_step(int64_t items, int grid_cap, int tuned)
 {
+    if (tuned > 0)
+        return tuned;
     const int64_t k = grid_cap > 0 ? (items + grid_cap - 1) / grid_cap : 1;
     return k > kSeedStep ? k : kSeedStep;
 }
@@ -67,7 +71,8 @@ struct Bound {
     unsigned char *ws = nullptr;
     int device = -1;
     int cus = 0;
-    int fwd_grid_cap = 0;
+    int fwd_occ = 0;        // forward workgroups that fit one CU
+    int fwd_grid_cap = 0;   // persistent forward grid: CUs x min(fwd_occ, tuned count)
     int max_grid_cap = 0;
     // a thresholding forward has set gamma in this workspace (cleared by every
     // bind, which leaves the control block unset)
@@ -86,6 +91,10 @@ struct sst_plan_s {
     float unscale_g = 1.f, unscale_gd = 1.f, gmax2 = 0.f;
     // inverse: power of two that puts the window's largest |g| in [2^13, 2^14)
     float inv_g_scale = 1.f, inv_g_unscale = 1.f;
+    // inverse: groups of 256 output samples per workgroup (1 or kInvWideTF)
+    int inv_tf = 1;
+    // launch choices set by sst_plan_set_tuning / the autotuner (0 = default)
+    sst_tuning tune{};
     size_t off_afrag = 0, off_afrag_lo = 0, afrag_bytes = 0;
     // workspace layout (bytes): control block, descriptor slot, tables
     size_t off_desc = 0, off_idesc = 0, off_win = 0, off_twid = 0, off_phlo = 0, off_phhi = 0;
@@ -231,7 +240,8 @@ sst::InvDesc inv_desc(const sst_plan_s *pl, const float *T, int64_t frame0, int6
         a.span_lo = lo;
         a.span_len = hi >= lo ? hi - lo + 1 : 0;
     }
-    a.tiles = (a.span_len + sst::kInvTileSamples - 1) / sst::kInvTileSamples;
+    const int64_t tile = (int64_t)sst::kInvTileSamples * pl->inv_tf;
+    a.tiles = (a.span_len + tile - 1) / tile;
     a.blk0 = 0;
     a.blk_end = (int64_t)n_comp * a.tiles;
     return a;
@@ -245,21 +255,27 @@ hipError_t record_event(const sst_fwd_aux *aux, int i, hipStream_t s)
     return hipEventRecord(reinterpret_cast<hipEvent_t>(aux->kernel_events[i]), s);
 }
 
-// Frames of one call that a tile of output samples can meet (even).
-int inv_max_k(const sst_plan_s *pl)
+// Frames of one call that a tile of tf x 256 output samples can meet (even).
+int inv_max_k(int M, int hop, int tf)
 {
-    const int k = (sst::kInvTileSamples - 1 + 2 * pl->M) / pl->p.hop + 2;
+    const int k = (sst::kInvTileSamples * tf - 1 + 2 * M) / hop + 2;
     return (k + 1) & ~1;
+}
+int inv_max_k(const sst_plan_s *pl) { return inv_max_k(pl->M, pl->p.hop, pl->inv_tf); }
+bool inv_wide_fits(const sst_plan_s *pl)
+{
+    return inv_max_k(pl->M, pl->p.hop, sst::kInvWideTF) <= sst::kInvWideKB;
 }
 
 // max_dec: the largest decimated window table of the list (inv_dec_words);
-// max_L: its longest window.
+// max_L: its longest window; tf: sample groups per workgroup of every channel.
 sst::InvLaunch inv_launch(const sst::InvDesc *dev, int n_ch, int64_t blk_begin, int max_k,
-                          int max_tab, int max_L, int max_dec)
+                          int max_tab, int max_L, int max_dec, int tf)
 {
     sst::InvLaunch l{};
     l.ch = dev;
     l.n_ch = n_ch;
+    l.tf = tf;
     l.blk_begin = blk_begin;
     l.max_k = max_k;
     l.max_tab = max_tab;
@@ -343,6 +359,16 @@ void build_afrag(sst_plan_s *pl, const std::vector<double> &g, const std::vector
 }
 
 
+// Forward grid of a binding: CUs x the resident workgroups, capped by the
+// tuned count when one is set.
+void apply_grid(const sst_plan_s *pl, Bound &bd)
+{
+    int wg = bd.fwd_occ > 0 ? bd.fwd_occ : 1;
+    if (pl->tune.fwd_wg_per_cu > 0 && pl->tune.fwd_wg_per_cu < wg)
+        wg = pl->tune.fwd_wg_per_cu;
+    bd.fwd_grid_cap = bd.cus * wg;
+}
+
 // Device state of a binding to the workspace `ws` on the current device:
 // launch limits from the device attributes, then the plan's tables uploaded
 // with one asynchronous copy on `s` (no allocation).
@@ -373,11 +399,12 @@ sst_status bind_impl(sst_plan_s *pl, Bound &bd, unsigned char *ws, hipStream_t s
     bd.device = dev;
     bd.cus = cus;
     bd.gamma_valid = false;
-    bd.fwd_grid_cap = cus * sst::fwd_occupancy(pl->p.nfft, pl->p.win_len);
+    bd.fwd_occ = sst::fwd_occupancy(pl->p.nfft, pl->p.win_len);
     if (pl->gemm_ft)
-        bd.fwd_grid_cap = cus * sst::gemm_occupancy(
+        bd.fwd_occ = sst::gemm_occupancy(
             pl->p.precision, pl->gemm_ft,
             sst::gemm_lds_bytes(pl->p.precision, pl->gemm_ft, pl->n_dst, pl->slab, pl->p.win_len));
+    apply_grid(pl, bd);
     bd.max_grid_cap = cus * sst::max_occupancy(pl->p.nfft, pl->p.win_len);
     return SST_OK;
 }
@@ -460,6 +487,8 @@ sst_status sst_plan(const sst_params *params, sst_plan_t *out)
     pl->lo_bits = (bits + 1) / 2;
     pl->n_lo = 1 << pl->lo_bits;
     pl->n_hi = (pl->G + pl->n_lo - 1) >> pl->lo_bits;
+    // Wide inverse tiles whenever their frames fit one staged block.
+    pl->inv_tf = inv_wide_fits(pl) ? sst::kInvWideTF : 1;
 
     // Workspace layout.
     size_t off = align_up(sizeof(sst::Ctrl));
@@ -561,6 +590,12 @@ sst_status sst_plan(const sst_params *params, sst_plan_t *out)
     }
     if (gemm)
         build_afrag(pl, g, gd);
+    if (const char *cache = std::getenv("SST_TUNE_CACHE")) {
+        // a matching cache entry, if any (a missing file or entry is no error)
+        const std::string keep = g_err;
+        if (sst_tuning_load(pl, cache) != SST_OK)
+            g_err = keep;
+    }
     *out = pl;
     return SST_OK;
 }
@@ -644,6 +679,7 @@ sst_status sst_forward_static(sst_plan_t pl, const float *x, int64_t frame0, int
             return st;
         o.serial = pl->serial;
     }
+    apply_grid(pl, o.bd);   // tuning set since the tables were uploaded
     return forward_impl(pl, o.bd, x, frame0, nframes, T, aux, flags, stream);
 }
 
@@ -703,7 +739,7 @@ static sst_status forward_impl(sst_plan_s *pl, Bound &bd, const float *x, int64_
     } else if (threshold) {
         g.item_begin = 0;
         g.item_stop = d.mitem_end;
-        g.step = spec ? (int)seed_step(d.mitem_end, bd.fwd_grid_cap) : 1;
+        g.step = spec ? (int)seed_step(d.mitem_end, bd.fwd_grid_cap, pl->tune.seed_step) : 1;
         const int64_t visits = (d.mitem_end + g.step - 1) / g.step;
         const int grid = (int)(visits < bd.fwd_grid_cap ? visits : bd.fwd_grid_cap);
         e = sst::launch_max_prepass(NF, pl->p.win_len, g, grid, s);
@@ -903,7 +939,7 @@ sst_status sst_inverse(sst_plan_t pl, const float *T, int64_t frame0, int64_t nf
     if (a.blk_end >= (int64_t(1) << 31))
         return fail(SST_E_UNSUPPORTED, "n_comp * ceil(span / 256) must be below 2^31");
     sst::InvLaunch l = inv_launch(slot, 1, a.blk0, inv_max_k(pl), pl->n_lo + pl->n_hi,
-                                  pl->p.win_len, pl->p.hop * a.dec_row);
+                                  pl->p.win_len, pl->p.hop * a.dec_row, pl->inv_tf);
     if (sst::inv_lds_bytes(l) > 64 * 1024)
         return fail(SST_E_UNSUPPORTED, "inverse tiles need more than 64 KiB of LDS "
                                        "(window too long for the hop)");
@@ -916,6 +952,248 @@ sst_status sst_inverse(sst_plan_t pl, const float *T, int64_t frame0, int64_t nf
 }
 
 void sst_destroy(sst_plan_t pl) { delete pl; }
+
+}  // extern "C"
+
+
+// ---------------------------------------------------------------------------
+// Tuning: launch choices, their measured search and a JSON cache.
+// ---------------------------------------------------------------------------
+
+namespace {
+
+std::string tuning_key(const sst_plan_s *pl)
+{
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "gfx950 nfft=%d L=%d H=%d n_src=%d n_dst=%d prec=%d",
+                  pl->p.nfft, pl->p.win_len, pl->p.hop, pl->n_src, pl->n_dst, pl->p.precision);
+    return buf;
+}
+
+sst_status apply_tuning(sst_plan_s *pl, const sst_tuning &t)
+{
+    if (t.fwd_wg_per_cu < 0 || t.seed_step < 0 || t.reserved != 0)
+        return fail(SST_E_ARG, "tuning values must be >= 0 and reserved 0");
+    if (t.inv_tf != 0 && t.inv_tf != 1 && t.inv_tf != sst::kInvWideTF)
+        return fail(SST_E_ARG, "inv_tf must be 0, 1 or 4");
+    if (t.inv_tf == sst::kInvWideTF && !inv_wide_fits(pl))
+        return fail(SST_E_UNSUPPORTED, "inv_tf 4: the frames 1024 output samples meet exceed "
+                                       "the staged block");
+    pl->tune = t;
+    pl->inv_tf = t.inv_tf ? t.inv_tf : (inv_wide_fits(pl) ? sst::kInvWideTF : 1);
+    if (pl->bd.ws)
+        apply_grid(pl, pl->bd);
+    return SST_OK;
+}
+
+// One cache line: "key": {"fwd_wg_per_cu": a, "seed_step": b, "inv_tf": c}
+bool parse_entry(const std::string &line, std::string &key, sst_tuning &t)
+{
+    const size_t q0 = line.find('"');
+    if (q0 == std::string::npos)
+        return false;
+    const size_t q1 = line.find('"', q0 + 1);
+    if (q1 == std::string::npos || line.find('{', q1) == std::string::npos)
+        return false;
+    key = line.substr(q0 + 1, q1 - q0 - 1);
+    t = sst_tuning{};
+    auto field = [&](const char *name, int32_t &v) {
+        const size_t at = line.find(std::string("\"") + name + "\"", q1);
+        if (at == std::string::npos)
+            return false;
+        const size_t colon = line.find(':', at);
+        if (colon == std::string::npos)
+            return false;
+        v = (int32_t)std::strtol(line.c_str() + colon + 1, nullptr, 10);
+        return true;
+    };
+    return field("fwd_wg_per_cu", t.fwd_wg_per_cu) && field("seed_step", t.seed_step) &&
+           field("inv_tf", t.inv_tf);
+}
+
+bool read_cache(const char *path, std::vector<std::pair<std::string, sst_tuning>> &out)
+{
+    std::FILE *f = std::fopen(path, "r");
+    if (!f)
+        return false;
+    char buf[1024];
+    while (std::fgets(buf, sizeof buf, f)) {
+        std::string key;
+        sst_tuning t;
+        if (parse_entry(buf, key, t))
+            out.emplace_back(key, t);
+    }
+    std::fclose(f);
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+sst_status sst_plan_get_tuning(sst_plan_t pl, sst_tuning *out)
+{
+    if (!pl || !out)
+        return fail(SST_E_ARG, "plan or out is NULL");
+    *out = pl->tune;
+    if (pl->bd.ws && pl->bd.cus > 0)
+        out->fwd_wg_per_cu = pl->bd.fwd_grid_cap / pl->bd.cus;
+    out->inv_tf = pl->inv_tf;
+    return SST_OK;
+}
+
+sst_status sst_plan_set_tuning(sst_plan_t pl, const sst_tuning *t)
+{
+    if (!pl || !t)
+        return fail(SST_E_ARG, "plan or tuning is NULL");
+    return apply_tuning(pl, *t);
+}
+
+sst_status sst_tuning_load(sst_plan_t pl, const char *path)
+{
+    if (!pl || !path)
+        return fail(SST_E_ARG, "plan or path is NULL");
+    std::vector<std::pair<std::string, sst_tuning>> entries;
+    if (!read_cache(path, entries))
+        return fail(SST_E_ARG, std::string("cannot read tuning cache ") + path);
+    const std::string key = tuning_key(pl);
+    for (const auto &e : entries)
+        if (e.first == key)
+            return apply_tuning(pl, e.second);
+    return fail(SST_E_ARG, "no tuning entry for " + key);
+}
+
+sst_status sst_tuning_save(sst_plan_t pl, const char *path)
+{
+    if (!pl || !path)
+        return fail(SST_E_ARG, "plan or path is NULL");
+    std::vector<std::pair<std::string, sst_tuning>> entries;
+    read_cache(path, entries);   // a missing file starts an empty cache
+    sst_tuning cur{};
+    sst_plan_get_tuning(pl, &cur);
+    cur.reserved = 0;
+    const std::string key = tuning_key(pl);
+    bool found = false;
+    for (auto &e : entries)
+        if (e.first == key) {
+            e.second = cur;
+            found = true;
+        }
+    if (!found)
+        entries.emplace_back(key, cur);
+    const std::string tmp = std::string(path) + ".tmp";
+    std::FILE *f = std::fopen(tmp.c_str(), "w");
+    if (!f)
+        return fail(SST_E_ARG, std::string("cannot write ") + tmp);
+    std::fprintf(f, "{\n");
+    for (size_t i = 0; i < entries.size(); ++i)
+        std::fprintf(f, "  \"%s\": {\"fwd_wg_per_cu\": %d, \"seed_step\": %d, \"inv_tf\": %d}%s\n",
+                     entries[i].first.c_str(), entries[i].second.fwd_wg_per_cu,
+                     entries[i].second.seed_step, entries[i].second.inv_tf,
+                     i + 1 < entries.size() ? "," : "");
+    std::fprintf(f, "}\n");
+    const bool ok = std::fclose(f) == 0 && std::rename(tmp.c_str(), path) == 0;
+    return ok ? SST_OK : fail(SST_E_ARG, std::string("cannot write ") + path);
+}
+
+sst_status sst_autotune(sst_plan_t pl, const float *x, float *T, const int32_t *ridge,
+                        int32_t n_comp, int32_t hw, float *xhat, int32_t reps, void *stream,
+                        sst_tuning *best)
+{
+    if (!pl)
+        return fail(SST_E_ARG, "plan is NULL");
+    if (!pl->bd.ws)
+        return fail(SST_E_STATE, "plan is not bound to a workspace");
+    if (!x || !T || reps < 1)
+        return fail(SST_E_ARG, "x and T must not be NULL and reps >= 1");
+    if (ridge && !xhat)
+        return fail(SST_E_ARG, "the inverse choices need xhat");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipError_t e = hipEventCreate(&ev[0]);
+    if (e == hipSuccess)
+        e = hipEventCreate(&ev[1]);
+    if (e != hipSuccess) {
+        if (ev[0])
+            hipEventDestroy(ev[0]);
+        return hip_fail(e, "hipEventCreate");
+    }
+    sst_status st = SST_OK;
+    // time reps calls of fn after one untimed call; ms per call, < 0 on error
+    auto timed = [&](auto fn) -> float {
+        if ((st = fn()) != SST_OK)
+            return -1.f;
+        hipError_t he = hipEventRecord(ev[0], s);
+        for (int r = 0; r < reps && st == SST_OK && he == hipSuccess; ++r)
+            st = fn();
+        if (he == hipSuccess)
+            he = hipEventRecord(ev[1], s);
+        if (he == hipSuccess)
+            he = hipEventSynchronize(ev[1]);
+        float ms = 0.f;
+        if (he == hipSuccess)
+            he = hipEventElapsedTime(&ms, ev[0], ev[1]);
+        if (he != hipSuccess && st == SST_OK)
+            st = hip_fail(he, "autotune timing");
+        return st == SST_OK ? ms / reps : -1.f;
+    };
+    sst_tuning cur = pl->tune;
+    cur.reserved = 0;
+    sst_tuning chosen = cur;
+    // forward: resident workgroups per CU x seed step of the speculative threshold
+    const int occ = pl->bd.fwd_occ > 0 ? pl->bd.fwd_occ : 1;
+    float best_ms = -1.f;
+    for (int wg = occ; wg >= 1 && wg >= occ - 2 && st == SST_OK; --wg)
+        for (int seed : {0, 16, 128}) {
+            sst_tuning t = cur;
+            t.fwd_wg_per_cu = wg;
+            t.seed_step = seed;
+            if ((st = apply_tuning(pl, t)) != SST_OK)
+                break;
+            const float ms = timed([&] {
+                return forward_impl(pl, pl->bd, x, 0, pl->n_frames, T, nullptr, 0, stream);
+            });
+            if (ms < 0.f)
+                break;
+            if (best_ms < 0.f || ms < best_ms) {
+                best_ms = ms;
+                chosen.fwd_wg_per_cu = wg;
+                chosen.seed_step = seed;
+            }
+        }
+    // inverse: tile width
+    if (st == SST_OK && ridge) {
+        float best_inv = -1.f;
+        for (int tf : {1, sst::kInvWideTF}) {
+            if (tf > 1 && !inv_wide_fits(pl))
+                continue;
+            sst_tuning t = chosen;
+            t.inv_tf = tf;
+            if ((st = apply_tuning(pl, t)) != SST_OK)
+                break;
+            const float ms = timed([&] {
+                return sst_inverse(pl, T, 0, pl->n_frames, ridge, n_comp, hw, xhat, nullptr,
+                                   nullptr, 0, stream);
+            });
+            if (ms < 0.f)
+                break;
+            if (best_inv < 0.f || ms < best_inv) {
+                best_inv = ms;
+                chosen.inv_tf = tf;
+            }
+        }
+    }
+    hipEventDestroy(ev[0]);
+    hipEventDestroy(ev[1]);
+    const sst_status st_apply = apply_tuning(pl, st == SST_OK ? chosen : cur);
+    if (st != SST_OK)
+        return st;
+    if (st_apply != SST_OK)
+        return st_apply;
+    if (best)
+        sst_plan_get_tuning(pl, best);
+    return SST_OK;
+}
 
 }  // extern "C"
 
@@ -952,7 +1230,11 @@ struct sst_batch_s {
     std::vector<Group> groups;
     std::vector<size_t> off_chan;
     size_t off_idesc = 0, ws_bytes = 0;
-    std::vector<sst::InvDesc> idesc;   // one per channel, channel order
+    // one per channel: the channels with one sample group per inverse
+    // workgroup first, then those with wide tiles, each in channel order
+    // (every inverse launch covers a contiguous run of one kind)
+    std::vector<sst::InvDesc> idesc;
+    std::vector<int> inv_pos;          // channel -> index in idesc
     unsigned char *ws = nullptr;
     bool committed = false;
     // per channel: a thresholding batched forward has set its gamma since the bind
@@ -1146,16 +1428,23 @@ sst_status sst_batch_commit(sst_batch_t b, void *stream)
             return hip_fail(e, "hipMemcpyAsync(descriptors)");
     }
     b->idesc.assign(b->plans.size(), sst::InvDesc{});
-    int64_t blk = 0;
-    for (size_t c = 0; c < b->plans.size(); ++c) {
-        const sst_plan_s *pl = b->plans[c];
-        const sst_batch_s::Io &o = b->io[c];
-        sst::InvDesc a = inv_desc(pl, o.T, 0, pl->n_frames, o.ridge, o.ridge ? o.n_comp : 0, o.hw,
-                                  o.xhat, o.xref, o.err, false);
-        a.blk0 = blk;
-        blk += o.ridge ? (int64_t)o.n_comp * a.tiles : 0;
-        a.blk_end = blk;
-        b->idesc[c] = a;
+    b->inv_pos.assign(b->plans.size(), 0);
+    size_t pos = 0;
+    for (int wide = 0; wide < 2; ++wide) {
+        int64_t blk = 0;
+        for (size_t c = 0; c < b->plans.size(); ++c) {
+            const sst_plan_s *pl = b->plans[c];
+            if ((pl->inv_tf > 1) != (wide == 1))
+                continue;
+            const sst_batch_s::Io &o = b->io[c];
+            sst::InvDesc a = inv_desc(pl, o.T, 0, pl->n_frames, o.ridge, o.ridge ? o.n_comp : 0,
+                                      o.hw, o.xhat, o.xref, o.err, false);
+            a.blk0 = blk;
+            blk += o.ridge ? (int64_t)o.n_comp * a.tiles : 0;
+            a.blk_end = blk;
+            b->idesc[pos] = a;
+            b->inv_pos[c] = (int)pos++;
+        }
     }
     hipError_t e = hipMemcpyAsync(b->ws + b->off_idesc, b->idesc.data(),
                                   sizeof(sst::InvDesc) * b->idesc.size(), hipMemcpyHostToDevice, s);
@@ -1217,7 +1506,8 @@ sst_status sst_batch_forward(sst_batch_t b, int32_t c_begin, int32_t c_end, uint
             g.list_n = nullptr;
             g.item_begin = gr.desc[i0].mitem0;
             g.item_stop = gr.desc[i1 - 1].mitem_end;
-            g.step = (int)seed_step(g.item_stop - g.item_begin, gr.fwd_grid_cap);
+            g.step = (int)seed_step(g.item_stop - g.item_begin, gr.fwd_grid_cap,
+                                    b->plans[(size_t)gr.chans[i0]]->tune.seed_step);
             const int64_t visits = (g.item_stop - g.item_begin + g.step - 1) / g.step;
             const int grid = (int)(visits < gr.fwd_grid_cap ? visits : gr.fwd_grid_cap);
             if (e == hipSuccess)
@@ -1266,42 +1556,84 @@ sst_status sst_batch_inverse(sst_batch_t b, int32_t c_begin, int32_t c_end, void
         return fail(SST_E_STATE, "batch not bound or buffers not committed");
     if (c_begin < 0 || c_end > (int32_t)b->plans.size() || c_begin >= c_end)
         return fail(SST_E_ARG, "channel range empty or outside [0, n_channels)");
-    int max_k = 2, max_tab = 1, max_L = 1, max_dec = 1;
-    bool any_err = false;
     for (int c = c_begin; c < c_end; ++c) {
         const sst_batch_s::Io &o = b->io[(size_t)c];
-        const sst_plan_s *pl = b->plans[(size_t)c];
         if (!o.T || !o.ridge || !o.xhat)
             return fail(SST_E_ARG, "channel " + std::to_string(c) + " has no T, ridge or xhat");
-        if (pl->G > 65536)
+        if (b->plans[(size_t)c]->G > 65536)
             return fail(SST_E_UNSUPPORTED, "inverse needs subdiv * nfft <= 65536");
-        max_k = std::max(max_k, inv_max_k(pl));
-        max_tab = std::max(max_tab, pl->n_lo + pl->n_hi);
-        max_L = std::max(max_L, pl->p.win_len);
-        max_dec = std::max(max_dec, pl->p.hop * b->idesc[(size_t)c].dec_row);
-        any_err = any_err || o.err;
+        if (b->idesc[(size_t)b->inv_pos[(size_t)c]].blk_end -
+                b->idesc[(size_t)b->inv_pos[(size_t)c]].blk0 >= (int64_t(1) << 31))
+            return fail(SST_E_UNSUPPORTED, "n_comp * ceil(n_samples / 256) must be below 2^31");
     }
     const sst::InvDesc *dev = reinterpret_cast<const sst::InvDesc *>(b->ws + b->off_idesc);
-    sst::InvLaunch l = inv_launch(dev + c_begin, c_end - c_begin, b->idesc[(size_t)c_begin].blk0,
-                                  max_k, max_tab, max_L, max_dec);
-    if (sst::inv_lds_bytes(l) > 64 * 1024)
-        return fail(SST_E_UNSUPPORTED, "inverse tiles need more than 64 KiB of LDS "
-                                       "(window too long for the hop)");
-    const int64_t blocks = b->idesc[(size_t)c_end - 1].blk_end - l.blk_begin;
-    for (int c = c_begin; c < c_end; ++c)
-        if (b->idesc[(size_t)c].blk_end - b->idesc[(size_t)c].blk0 >= (int64_t(1) << 31))
-            return fail(SST_E_UNSUPPORTED, "n_comp * ceil(n_samples / 256) must be below 2^31");
-    if (blocks >= (int64_t(1) << 31))
-        return fail(SST_E_UNSUPPORTED, "the channel range needs 2^31 or more inverse tiles; "
-                                       "split it over several calls");
-    hipError_t e = sst::launch_inverse(l, blocks, any_err, reinterpret_cast<hipStream_t>(stream));
-    if (e != hipSuccess)
-        return hip_fail(e, "batched inverse launch");
+    // one launch per kind of tile: the range's channels of that kind are a
+    // contiguous run of the descriptor array
+    for (int wide = 0; wide < 2; ++wide) {
+        int p0 = -1, p1 = -1;
+        int max_k = 2, max_tab = 1, max_L = 1, max_dec = 1;
+        bool any_err = false;
+        for (int c = c_begin; c < c_end; ++c) {
+            const sst_plan_s *pl = b->plans[(size_t)c];
+            if ((pl->inv_tf > 1) != (wide == 1))
+                continue;
+            const int pos = b->inv_pos[(size_t)c];
+            if (p0 < 0)
+                p0 = pos;
+            p1 = pos;
+            max_k = std::max(max_k, inv_max_k(pl));
+            max_tab = std::max(max_tab, pl->n_lo + pl->n_hi);
+            max_L = std::max(max_L, pl->p.win_len);
+            max_dec = std::max(max_dec, pl->p.hop * b->idesc[(size_t)pos].dec_row);
+            any_err = any_err || b->io[(size_t)c].err;
+        }
+        if (p0 < 0)
+            continue;
+        sst::InvLaunch l = inv_launch(dev + p0, p1 - p0 + 1, b->idesc[(size_t)p0].blk0, max_k,
+                                      max_tab, max_L, max_dec, wide ? sst::kInvWideTF : 1);
+        if (sst::inv_lds_bytes(l) > 64 * 1024)
+            return fail(SST_E_UNSUPPORTED, "inverse tiles need more than 64 KiB of LDS "
+                                           "(window too long for the hop)");
+        const int64_t blocks = b->idesc[(size_t)p1].blk_end - l.blk_begin;
+        if (blocks >= (int64_t(1) << 31))
+            return fail(SST_E_UNSUPPORTED, "the channel range needs 2^31 or more inverse tiles; "
+                                           "split it over several calls");
+        hipError_t e = sst::launch_inverse(l, blocks, any_err,
+                                           reinterpret_cast<hipStream_t>(stream));
+        if (e != hipSuccess)
+            return hip_fail(e, "batched inverse launch");
+    }
     return SST_OK;
 }
 
 void sst_batch_destroy(sst_batch_t b) { delete b; }
 
+
+sst_status sst_renyi(const void *C, int32_t kind, int64_t rows, int32_t cols, int64_t ld,
+                     int32_t alpha, double *work, double *out, void *stream)
+{
+    if (!C || !work || !out)
+        return fail(SST_E_ARG, "C, work and out must not be NULL");
+    if (kind < SST_RENYI_COMPLEX64 || kind > SST_RENYI_MAG_F16)
+        return fail(SST_E_ARG, "unknown kind");
+    if (rows < 1 || cols < 1 || ld < cols)
+        return fail(SST_E_ARG, "need rows >= 1, cols >= 1 and ld >= cols");
+    if (alpha < 2 || alpha > 4)
+        return fail(SST_E_ARG, "alpha must be an integer in [2, 4]");
+    static_assert(2 * sst::kRenyiParts <= SST_RENYI_WORK_DOUBLES, "work holds the partials");
+    sst::RenyiArgs a{};
+    a.C = C;
+    a.rows = rows;
+    a.ld = ld;
+    a.cols = cols;
+    a.alpha = alpha;
+    a.work = work;
+    a.out = out;
+    hipError_t e = sst::launch_renyi(a, kind, reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess)
+        return hip_fail(e, "Renyi launch");
+    return SST_OK;
+}
 
 const char *sst_status_string(sst_status s)
 {

@@ -103,6 +103,7 @@ struct InvLaunch {
     int max_tab;            // LDS float2 entries of the largest phase tables in the list
     int max_gtab;           // LDS words of the largest window table in the list
     int dec;                // window tables decimated by the hop (inv_gtab_words)
+    int tf;                 // groups of kInvTileSamples per workgroup (1 or kInvWideTF)
 };
 
 // Words of a channel's inverse window table: decimated by the hop,
@@ -110,7 +111,9 @@ struct InvLaunch {
 // clamped).
 constexpr int kInvDecMax = 10240;
 
-constexpr int kInvTileSamples = 256;   // output samples per inverse workgroup
+constexpr int kInvTileSamples = 256;   // output samples per group of four inverse waves
+constexpr int kInvWideTF = 4;          // groups per workgroup of the wide inverse tiles
+constexpr int kInvWideKB = 144;        // frames a wide tile may meet (one staged block)
 
 // Precision tiers of the DFT-as-GEMM forward (values of sst_params.precision).
 constexpr int SST_GEMM_BF16 = 1;
@@ -151,6 +154,20 @@ struct RidgeArgs {
     const int32_t *centre;  // optional [n_comp][nframes] guide bins (-1: no ridge)
     int32_t *ridge;         // [n_comp][nframes]
 };
+
+// Arguments of the Renyi-entropy reduction (sst_analysis.hip).
+constexpr int kRenyiParts = 1024;   // per-workgroup partial sums (work holds 2 per part)
+struct RenyiArgs {
+    const void *C;          // [rows][ld] complex float, float or half magnitudes
+    int64_t rows;
+    int64_t ld;             // row stride in elements
+    int64_t rows_per;       // rows per workgroup (set by the launcher)
+    int cols;
+    int alpha;              // integer order >= 2
+    double *work;           // [2 kRenyiParts]
+    double *out;            // [3]: sum P, sum P^alpha, R in bits
+};
+hipError_t launch_renyi(const RenyiArgs &a, int kind, hipStream_t s);
 
 // Launchers (sst_kernels.hip).  Each returns the hipError_t of its launch.
 // Threshold of the GEMM tiers: clears maxbits of the launch's channels, runs

@@ -216,57 +216,22 @@ struct Geo {
     static constexpr bool P4 = NF == 8192;            // radix-2 pass 4
 };
 
-// w^r for r = 0 .. R-1 from the bases w^(4^c) (c = 0, 1, ..., each the
-// correctly rounded value of a double-precision table, `stride` apart): the
-// odd powers of two w^(2 4^c) are squares of the stored bases, and every other
-// power is the product of the powers of two of its set bits, formed as
-// w^(2^p) w^(r - 2^p) with 2^p the top bit of r.  Each power is a few products
-// deep and its error does not grow with r (powering a single rounded base
-// would multiply that base's rounding error by r).
-template <int R>
-__device__ __forceinline__ void powers(const v2 *bases, int stride, v2 (&p)[R])
-{
-    p[0] = mk(1.f, 0.f);
-#pragma unroll
-    for (int r = 1; r < R; ++r) {
-        const int lb = 31 - __builtin_clz(r);
-        const int hb = 1 << lb;
-        if (hb == r)
-            p[r] = (lb & 1) ? cmul(p[r / 2], p[r / 2]) : bases[(lb >> 1) * stride];
-        else
-            p[r] = cmul(p[hb], p[r - hb]);
-    }
-}
-
 template <int R>
 constexpr int log2i() { return R <= 1 ? 0 : 1 + log2i<R / 2>(); }
 
-// One Stockham pass of radix R and stride NS over the F frames in LDS.  The
-// twiddles W_{NS R}^{k r} with k = (j mod N_f/R) mod NS = tid mod NS (every
-// butterfly of a thread has the same k, as NS divides both N_f/R and the
-// thread count) are formed from the bases W_{NS R}^{k 4^c}, staged once in LDS
-// as [c][k] (TW entries) so that they hold no registers between passes.
+// One Stockham pass of radix R and stride NS over the F frames in LDS.  Every
+// butterfly of a thread has the same twiddle index k = (j mod N_f/R) mod NS =
+// tid mod NS (NS divides both N_f/R and the thread count), so the caller
+// supplies the thread's R twiddles W_{NS R}^{k r}, r = 0 .. R-1 (w[0] = 1),
+// each the correctly rounded value of a float64 table entry.
 template <int NF, int R, int NS>
 struct Pass {
     using G = Geo<NF>;
     static constexpr int NR = NF / R;
     static constexpr int NB = (NF * G::F / R) / G::NT;   // butterflies per thread
-    static constexpr int NBITS = log2i<R>();
-    static constexpr int NSTORE = (NBITS + 1) / 2;         // stored bases w^(4^c)
-    static constexpr int TW = NS > 1 ? NS * NSTORE : 0;    // LDS table entries
     static_assert(NS == 1 || (G::NT % NS == 0 && NR % NS == 0), "one twiddle set per thread");
 
-    // tbl[c NS + k] = W_{NS R}^{k 4^c} = W_{N_f}^{(N_f / (NS R)) k 4^c}; the
-    // exponent stays below N_f / 2.
-    static __device__ __forceinline__ void stage(v2 *tbl, const v2 *__restrict__ twid)
-    {
-        for (int e = threadIdx.x; e < TW; e += G::NT) {
-            const int c = e / NS, k = e % NS;
-            tbl[e] = twid[(unsigned)((NF / (NS * R)) * (k << (2 * c)))];
-        }
-    }
-
-    static __device__ __forceinline__ void run(v2 *lds, const v2 *tbl)
+    static __device__ __forceinline__ void run(v2 *lds, const v2 (&w)[R])
     {
         // LDS addresses depend only on the thread index; an opaque copy per
         // call keeps them from being hoisted out of the frame loop and spilled
@@ -282,13 +247,11 @@ struct Pass {
                 v[b][r] = lds[pad16(f * NF + jj) + r * padded_stride(NR)];
         }
         if constexpr (NS > 1) {
-            v2 p[R];
-            powers<R>(tbl + tid % NS, NS, p);
 #pragma unroll
             for (int b = 0; b < NB; ++b)
 #pragma unroll
                 for (int r = 1; r < R; ++r)
-                    v[b][r] = cmul(v[b][r], p[r]);
+                    v[b][r] = cmul(v[b][r], w[r]);
         }
 #pragma unroll
         for (int b = 0; b < NB; ++b)
@@ -308,36 +271,50 @@ struct Pass {
     }
 };
 
-// Twiddles of passes 2 and 3 come from bases staged in LDS (TW entries);
-// the radix-2 pass 4 of N_f = 8192 needs only w itself, which each thread
-// keeps in registers for its butterflies.
+// Twiddles of the passes after the first, every one read from the float64-
+// built table W_{N_f}^t (correctly rounded), none formed by products:
+//   pass 2 (radix 16, stride 16): W_256^{k r} = W_{N_f}^{(N_f/256) k r}, k < 16,
+//     staged once in LDS as tbl[(r - 1) 16 + k] (TW entries; a wave's lanes
+//     read 16 distinct words, broadcast to the others);
+//   pass 3 (radix R3, stride 256): W_{256 R3}^{k r}, k = tid mod 256, held in
+//     registers for the life of the workgroup;
+//   pass 4 (radix 2, N_f = 8192 only): W_8192^j for the thread's butterflies,
+//     read from the table (L1/L2) at the start of the pass.
 template <int NF>
 struct Twiddles {
     using G = Geo<NF>;
     using P2 = Pass<NF, 16, 16>;
     using P3 = Pass<NF, G::R3, 256>;
-    static constexpr int TW = P2::TW + P3::TW;
+    static constexpr int TW = 15 * 16;
     static constexpr int NB4 = G::P4 ? (NF / 2) / G::NT : 1;   // pass-4 butterflies per thread
-    v2 t4[NB4];
+    v2 t3[G::R3];
+    const v2 *tw4;   // the table, for pass 4
 
-    // Stage the pass 2/3 bases into tbl (TW entries, visible after the next
-    // barrier) and load the pass-4 twiddles.
+    // Stage the pass-2 table into tbl (visible after the next barrier) and
+    // load the pass-3 and pass-4 twiddles.
     __device__ __forceinline__ void load(v2 *tbl, const v2 *__restrict__ twid)
     {
-        P2::stage(tbl, twid);
-        P3::stage(tbl + P2::TW, twid);
-        if constexpr (G::P4) {
-#pragma unroll
-            for (int b = 0; b < NB4; ++b) {
-                const int j = threadIdx.x + b * G::NT;
-                t4[b] = twid[(unsigned)j];
-            }
+        for (int e = threadIdx.x; e < TW; e += G::NT) {
+            const int r = e / 16 + 1, k = e % 16;
+            tbl[e] = twid[(unsigned)((NF / 256) * k * r)];
         }
+        const int k3 = threadIdx.x % 256;
+        t3[0] = mk(1.f, 0.f);
+#pragma unroll
+        for (int r = 1; r < G::R3; ++r)
+            t3[r] = twid[(unsigned)((NF / (256 * G::R3)) * k3 * r)];
+        tw4 = twid;
     }
     __device__ __forceinline__ void passes(v2 *lds, const v2 *tbl) const
     {
-        P2::run(lds, tbl);
-        P3::run(lds, tbl + P2::TW);
+        v2 w2[16];
+        w2[0] = mk(1.f, 0.f);
+        const int k2 = threadIdx.x % 16;
+#pragma unroll
+        for (int r = 1; r < 16; ++r)
+            w2[r] = tbl[(r - 1) * 16 + k2];
+        P2::run(lds, w2);
+        P3::run(lds, t3);
         if constexpr (G::P4)
             pass4(lds);
     }
@@ -347,6 +324,10 @@ struct Twiddles {
     {
         int tid = threadIdx.x;
         asm volatile("" : "+v"(tid));
+        v2 t4[NB4];
+#pragma unroll
+        for (int b = 0; b < NB4; ++b)
+            t4[b] = tw4[(unsigned)(tid + b * G::NT)];
         v2 v[NB4][2];
 #pragma unroll
         for (int b = 0; b < NB4; ++b) {
@@ -910,11 +891,21 @@ __global__ __launch_bounds__(Geo<NF>::NT, DEBUG ? 2 : ((NF == 8192 || (NF == 409
                 B += bpart[wv][ff];
             scf[ff] = fixed_scale(B * 1.001f);
         }
-        for (int c0 = 0; c0 < (CHUNKED ? EH : 1); c0 += HB) {
-            const int cn = CHUNKED ? ((EH - c0) < HB ? (EH - c0) : HB) : EH;
+        // Rows longer than the buffer go in chunks of equal size, a multiple of
+        // NT (at most HB), so that no pass clears or stores bins past the row
+        // beyond the last partial round: nst rounds of NT bins per chunk.
+        int CH = HB;
+        if constexpr (CHUNKED) {
+            const int nch = (EH + HB - 1) / HB;
+            CH = ((EH + nch - 1) / nch + NT - 1) / NT * NT;
+        }
+        for (int c0 = 0; c0 < (CHUNKED ? EH : 1); c0 += CH) {
+            const int cn = CHUNKED ? ((EH - c0) < CH ? (EH - c0) : CH) : EH;
+            const int nst = CHUNKED ? (cn + NT - 1) / NT : NST;
 #pragma unroll
             for (int i = 0; i < NST; ++i)
-                reinterpret_cast<unsigned long long *>(hq)[threadIdx.x + i * NT] = 0ull;
+                if (!CHUNKED || i < nst)
+                    reinterpret_cast<unsigned long long *>(hq)[threadIdx.x + i * NT] = 0ull;
             __syncthreads();
             // scatter phase (Eq. 28)
 #pragma unroll
@@ -943,14 +934,16 @@ __global__ __launch_bounds__(Geo<NF>::NT, DEBUG ? 2 : ((NF == 8192 || (NF == 409
 #pragma unroll
             for (int g0 = 0; g0 < NST; g0 += SG) {
                 __builtin_amdgcn_sched_barrier(0);
+                if (CHUNKED && g0 >= nst)
+                    break;
                 unsigned long long hv[SG];
 #pragma unroll
                 for (int i = 0; i < SG; ++i)
-                    if (g0 + i < NST)
+                    if (g0 + i < NST && (!CHUNKED || g0 + i < nst))
                         hv[i] = reinterpret_cast<const unsigned long long *>(hq)[threadIdx.x + (g0 + i) * NT];
 #pragma unroll
                 for (int i = 0; i < SG; ++i) {
-                    if (g0 + i >= NST)
+                    if (g0 + i >= NST || (CHUNKED && g0 + i >= nst))
                         continue;
                     const int e = threadIdx.x + (g0 + i) * NT;
                     float isc = 1.0f / scf[0];   // exact: a power of two
@@ -978,7 +971,7 @@ __global__ __launch_bounds__(Geo<NF>::NT, DEBUG ? 2 : ((NF == 8192 || (NF == 409
                     }
                 }
             }
-            if (CHUNKED && c0 + HB < EH)
+            if (CHUNKED && c0 + CH < EH)
                 __syncthreads();   // store reads done before the next chunk is cleared
         }
         if constexpr (DEBUG) {
@@ -1289,10 +1282,19 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 // Denominator: for samples whose frames all exist it depends on n mod H only
 // and comes from a table built on the host in float64; near the ends of the
 // signal it is summed here.
-constexpr int kInvTile = 256;                  // output samples per workgroup (4 waves x 2 x 32)
-constexpr int kInvKB = 96;                     // frames staged per block (a multiple of 16)
-constexpr int kInvKBP = kInvKB + 8;            // padded row of staged halves
-constexpr int kInvStage = kInvKB * 16 / 256;   // staged coefficients per thread and block
+// Wide tiles.  A workgroup covers TF x 256 consecutive output samples (each
+// wave TF groups of 64): the zone coefficients of the tile's frames are
+// staged once per group of 16 bins and serve every sample group, and the
+// tables are built once per TF x 256 samples.  Frames a tile meets grow by
+// 256 TF / H, so a wide tile stages (256 TF + 2M) / H frames where TF narrow
+// ones stage TF (256 + 2M) / H.
+constexpr int kInvTile = 256;                  // samples per group of four waves (4 x 2 x 32)
+template <int TF>
+struct InvGeo {
+    static constexpr int KB = TF == 1 ? 96 : 144;   // frames staged per block (multiple of 16)
+    static constexpr int KBP = KB + 8;              // padded row of staged halves
+    static constexpr int STAGE = KB * 16 / 256;     // staged coefficients per thread and block
+};
 
 typedef _Float16 f16x8v __attribute__((ext_vector_type(8)));
 
@@ -1314,37 +1316,111 @@ __host__ __device__ inline size_t inv_align16(size_t v)
 {
     return (v + 15) & ~(size_t)15;
 }
-__host__ __device__ inline InvLds inv_lds_layout(int max_tab, int max_gtab, int max_k)
+__host__ __device__ inline InvLds inv_lds_layout(int max_tab, int max_gtab, int max_k, int kbp)
 {
     InvLds o;
     o.gpk = inv_align16(8 * (size_t)max_tab);
     o.rid = inv_align16(o.gpk + 4 * (size_t)max_gtab);
     o.ahi = inv_align16(o.rid + 4 * (size_t)max_k);
-    o.alo = o.ahi + 2 * 32 * (size_t)kInvKBP;
-    o.fred = inv_align16(o.alo + 2 * 32 * (size_t)kInvKBP);
+    o.alo = o.ahi + 2 * 32 * (size_t)kbp;
+    o.fred = inv_align16(o.alo + 2 * 32 * (size_t)kbp);
     o.red = o.fred + 16;
     o.total = o.red + 16;
     return o;
 }
 
+// Window contraction of one wave's 64 samples (sample group cg of the tile)
+// over the staged frames [kb, kb + kn) of the tile: acc0 and acc1 (columns
+// 0..31 and 32..63) accumulate Z 2^(sc + tg) = sum_m c~[m, d] g[n - mH].
+// Only the frames whose windows reach the wave's samples are visited (the
+// others meet g = 0 in every column of the wave), in steps of 16 from a
+// multiple of 16 (the staged rows are zero past kn).
+template <bool DEC, int KBP>
+__device__ __forceinline__ void wave_mfma(f32x16 &acc0, f32x16 &acc1, const unsigned short *aph,
+                                          const unsigned short *apl, const unsigned *gpk,
+                                          int tile_lo, int cg, int wave, int col, int half, int mlo,
+                                          int kb, int kn, int M, int H, int JL, int TR)
+{
+    const int w_lo = tile_lo + 256 * cg + 64 * __builtin_amdgcn_readfirstlane(wave);
+    const int wm_lo = w_lo - M > 0 ? (w_lo - M + H - 1) / H : 0;
+    const int wm_hi = (w_lo + 63 + M) / H;
+    int kw0 = wm_lo - mlo - kb, kw1 = wm_hi - mlo - kb;
+    kw0 = kw0 > 0 ? kw0 & ~15 : 0;
+    kw1 = kw1 < kn - 1 ? kw1 : kn - 1;
+    // j = n - m H of the lane's first frame (k0 + 8 half) for column 0
+    int j0 = w_lo + col - mlo * H - (kb + kw0 + 8 * half) * H;
+    // DEC: the lane's 8 values g[j - i H], i = 0..7, are the words p[7 - i] of
+    // its residue row; a step of 16 frames moves p by -16.  Every j a step
+    // reaches lies within JL of 0: the steps start up to 15 frames before the
+    // wave's first frame and end up to 15 after its last, and a wave spans 64
+    // samples, so |j| <= M + 63 + 15 H.
+    const unsigned *pc0 = gpk, *pc1 = gpk;
+    if constexpr (DEC) {
+        const int u0 = j0 + JL, u1 = u0 + 32;
+        pc0 = gpk + (u0 % H) * TR + u0 / H - 7;
+        pc1 = gpk + (u1 % H) * TR + u1 / H - 7;
+    }
+    for (int k0 = kw0; k0 <= kw1; k0 += 16) {
+        const u4v_t a_hi = *reinterpret_cast<const u4v_t *>(aph + k0);
+        const u4v_t a_lo = *reinterpret_cast<const u4v_t *>(apl + k0);
+        const f16x8v ah = __builtin_bit_cast(f16x8v, a_hi), al = __builtin_bit_cast(f16x8v, a_lo);
+        // B of column c: g[n + 32 c - m H] for the lane's 8 frames
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            unsigned w[8];
+            if constexpr (DEC) {
+                const unsigned *pc = c ? pc1 : pc0;
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+                    w[i] = pc[7 - i];
+            } else {
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const int j = j0 + 32 * c - i * H;
+                    w[i] = gpk[min(max(j, -M - 1), M + 1) + M + 1];
+                }
+            }
+            u4v_t bh, bl;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                bh[i] = __builtin_amdgcn_perm(w[2 * i + 1], w[2 * i], 0x05040100u);
+                bl[i] = __builtin_amdgcn_perm(w[2 * i + 1], w[2 * i], 0x07060302u);
+            }
+            const f16x8v fh = __builtin_bit_cast(f16x8v, bh), fl = __builtin_bit_cast(f16x8v, bl);
+            f32x16 &acc = c ? acc1 : acc0;
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, fh, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, fl, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(al, fh, acc, 0, 0, 0);
+        }
+        j0 -= 16 * H;
+        pc0 -= 16;
+        pc1 -= 16;
+    }
+}
+
 // ONE: every tile's frames fit one staged block (K <= KB), so the sums start
 // after the staging and need no registers during it.  DEC: the window table is
 // decimated by the hop, so a lane's 8 window values are consecutive words;
-// otherwise they are gathered with clamped indices.  Waves per SIMD: the most
-// that each variant fits without spilling registers.
-template <bool ONE, bool DEC>
-__global__ __launch_bounds__(256, ONE ? (DEC ? 6 : 5) : 4) void inv_kernel(InvLaunch l)
+// otherwise they are gathered with clamped indices.  TF: sample groups of 256
+// per workgroup (1, or 4 with ONE).  Waves per SIMD: the most that each
+// variant fits without spilling registers.
+template <bool ONE, bool DEC, int TF>
+__global__ __launch_bounds__(256, TF > 1 ? 4 : (ONE ? (DEC ? 6 : 5) : 4)) void inv_kernel(InvLaunch l)
 {
+    using IG = InvGeo<TF>;
+    constexpr int KB = IG::KB, KBP = IG::KBP, STAGE = IG::STAGE;
+    static_assert(TF == 1 || ONE, "wide tiles stage every frame in one block");
+    static_assert(TF == 1 || KB == kInvWideKB, "host and kernel agree on the wide block");
     extern __shared__ __align__(16) unsigned char smem[];
     const int64_t blk = l.blk_begin + (int64_t)blockIdx.x;
     const CA InvDesc *chs = (const CA InvDesc *)l.ch;
     const CA InvDesc &a = chs[inv_chan_of(chs, l.n_ch, blk)];
     const int nlo = 1 << a.lo_bits;
     const int nhi = (a.G + nlo - 1) >> a.lo_bits;
-    const InvLds lay = inv_lds_layout(l.max_tab, l.max_gtab, l.max_k);
+    const InvLds lay = inv_lds_layout(l.max_tab, l.max_gtab, l.max_k, KBP);
     v2 *tlo = reinterpret_cast<v2 *>(smem);
     v2 *thi = tlo + nlo;
-    unsigned *gpk = reinterpret_cast<unsigned *>(smem + lay.gpk);   // [L + 2]: window, packed
+    unsigned *gpk = reinterpret_cast<unsigned *>(smem + lay.gpk);   // window, packed
     int *rid = reinterpret_cast<int *>(smem + lay.rid);             // [max_k]
     unsigned short *ahi = reinterpret_cast<unsigned short *>(smem + lay.ahi);   // [32][KBP]
     unsigned short *alo = reinterpret_cast<unsigned short *>(smem + lay.alo);   // [32][KBP]
@@ -1359,8 +1435,8 @@ __global__ __launch_bounds__(256, ONE ? (DEC ? 6 : 5) : 4) void inv_kernel(InvLa
     const unsigned tiles = (unsigned)a.tiles;
     const int q = (int)(local / tiles);
     const int span_lo = (int)a.span_lo, span_end = (int)(a.span_lo + a.span_len - 1);
-    const int tile_lo = span_lo + (int)(local - (unsigned)q * tiles) * kInvTile;
-    const int tile_hi = tile_lo + kInvTile - 1 < span_end ? tile_lo + kInvTile - 1 : span_end;
+    const int tile_lo = span_lo + (int)(local - (unsigned)q * tiles) * (kInvTile * TF);
+    const int tile_hi = tile_lo + kInvTile * TF - 1 < span_end ? tile_lo + kInvTile * TF - 1 : span_end;
     const int M = a.M, H = a.hop, Gi = a.G;
     const int frame0 = (int)a.frame0, nfr = (int)a.nframes, nframes_all = (int)a.n_frames;
     const v2 *__restrict__ win = reinterpret_cast<const v2 *>(a.win);
@@ -1434,18 +1510,13 @@ __global__ __launch_bounds__(256, ONE ? (DEC ? 6 : 5) : 4) void inv_kernel(InvLa
     const uint32_t n0g = (uint32_t)tile_lo % G;      // tile_lo mod G
     const uint32_t hg = (uint32_t)H % G;             // H mod G
 
-    // the two sample columns of this lane and their offsets to the first frame
-    const int s0 = wave * 64 + col;                  // sample within the tile
-    const int jb0 = tile_lo - mlo * H + s0;          // n - m_lo H for column 0; column 1 is +32
-    // frames whose windows reach this wave's samples [w_lo, w_lo + 63]; the
-    // other frames of the tile meet g = 0 in every column of the wave
-    const int w_lo = tile_lo + 64 * __builtin_amdgcn_readfirstlane(wave);
-    const int wm_lo = w_lo - M > 0 ? (w_lo - M + H - 1) / H : 0;
-    const int wm_hi = (w_lo + 63 + M) / H;
     const v2 *__restrict__ Trow = reinterpret_cast<const v2 *>(a.T) + (int64_t)(mlo - frame0) * a.n_dst;
-    const unsigned short *aph = ahi + col * kInvKBP + 8 * half;   // this lane's A row and k chunk
-    const unsigned short *apl = alo + col * kInvKBP + 8 * half;
-    float y0 = 0.f, y1 = 0.f;
+    const unsigned short *aph = ahi + col * KBP + 8 * half;   // this lane's A row and k chunk
+    const unsigned short *apl = alo + col * KBP + 8 * half;
+    float y[TF][2];
+#pragma unroll
+    for (int cg = 0; cg < TF; ++cg)
+        y[cg][0] = y[cg][1] = 0.f;
     for (int d0 = d_lo; d0 <= d_hi; d0 += 16) {
         f32x16 acc0, acc1;
         if constexpr (!ONE) {
@@ -1453,18 +1524,18 @@ __global__ __launch_bounds__(256, ONE ? (DEC ? 6 : 5) : 4) void inv_kernel(InvLa
             acc1 = f32x16{};
         }
         int sc = 0;   // accumulators hold Z 2^(sc + tg)
-        for (int kb = 0; kb < (ONE ? 1 : K); kb += kInvKB) {
-            const int kn = K - kb < kInvKB ? K - kb : kInvKB;
+        for (int kb = 0; kb < (ONE ? 1 : K); kb += KB) {
+            const int kn = K - kb < KB ? K - kb : KB;
             const int kn16 = (kn + 15) & ~15;
             // an opaque copy of the thread index keeps the compiler from
             // hoisting the staging indices out of the loops (and spilling them)
             int tid = threadIdx.x;
             asm volatile("" : "+v"(tid));
             // c~[m, d] of this block in registers: 16 destinations per frame
-            float cre[kInvStage], cim[kInvStage];
+            float cre[STAGE], cim[STAGE];
             float amax = 0.f;
 #pragma unroll
-            for (int i = 0; i < kInvStage; ++i) {
+            for (int i = 0; i < STAGE; ++i) {
                 const int e = tid + 256 * i;
                 const int kk = e >> 4, dd = e & 15;
                 const int k = kb + kk;
@@ -1514,107 +1585,67 @@ __global__ __launch_bounds__(256, ONE ? (DEC ? 6 : 5) : 4) void inv_kernel(InvLa
             }
             const float scl = ldexpf(1.f, sc);
 #pragma unroll
-            for (int i = 0; i < kInvStage; ++i) {
+            for (int i = 0; i < STAGE; ++i) {
                 const int e = tid + 256 * i;
                 const int kk = e >> 4, dd = e & 15;
                 if (kk < kn16) {
                     unsigned h, lw;
                     split_f16(cre[i] * scl, h, lw);
-                    ahi[(2 * dd) * kInvKBP + kk] = (unsigned short)h;
-                    alo[(2 * dd) * kInvKBP + kk] = (unsigned short)lw;
+                    ahi[(2 * dd) * KBP + kk] = (unsigned short)h;
+                    alo[(2 * dd) * KBP + kk] = (unsigned short)lw;
                     split_f16(cim[i] * scl, h, lw);
-                    ahi[(2 * dd + 1) * kInvKBP + kk] = (unsigned short)h;
-                    alo[(2 * dd + 1) * kInvKBP + kk] = (unsigned short)lw;
+                    ahi[(2 * dd + 1) * KBP + kk] = (unsigned short)h;
+                    alo[(2 * dd + 1) * KBP + kk] = (unsigned short)lw;
                 }
             }
             __syncthreads();
-            // this wave's frames within the block, in steps of 16 from a
-            // multiple of 16 (the staged rows are zero past kn)
-            int kw0 = wm_lo - mlo - kb, kw1 = wm_hi - mlo - kb;
-            kw0 = kw0 > 0 ? kw0 & ~15 : 0;
-            kw1 = kw1 < kn - 1 ? kw1 : kn - 1;
-            // j = n - m H of the lane's first frame (k0 + 8 half) for column 0
-            int j0 = jb0 - (kb + kw0 + 8 * half) * H;
-            // DEC: the lane's 8 values g[j - i H], i = 0..7, are the words
-            // p[7 - i] of its residue row; a step of 16 frames moves p by -16.
-            // Every j a step reaches lies within JL of 0: the steps start up to
-            // 15 frames before the wave's first frame and end up to 15 after
-            // its last, and a wave spans 64 samples, so |j| <= M + 63 + 15 H.
-            const unsigned *pc0 = gpk, *pc1 = gpk;
-            if constexpr (DEC) {
-                const int u0 = j0 + JL, u1 = u0 + 32;
-                pc0 = gpk + (u0 % H) * TR + u0 / H - 7;
-                pc1 = gpk + (u1 % H) * TR + u1 / H - 7;
-            }
-            for (int k0 = kw0; k0 <= kw1; k0 += 16) {
-                const u4v_t a_hi = *reinterpret_cast<const u4v_t *>(aph + k0);
-                const u4v_t a_lo = *reinterpret_cast<const u4v_t *>(apl + k0);
-                const f16x8v ah = __builtin_bit_cast(f16x8v, a_hi), al = __builtin_bit_cast(f16x8v, a_lo);
-                // B of column c: g[n + 32 c - m H] for the lane's 8 frames
-#pragma unroll
-                for (int c = 0; c < 2; ++c) {
-                    unsigned w[8];
-                    if constexpr (DEC) {
-                        const unsigned *pc = c ? pc1 : pc0;
-#pragma unroll
-                        for (int i = 0; i < 8; ++i)
-                            w[i] = pc[7 - i];
-                    } else {
-#pragma unroll
-                        for (int i = 0; i < 8; ++i) {
-                            const int j = j0 + 32 * c - i * H;
-                            w[i] = gpk[min(max(j, -M - 1), M + 1) + M + 1];
-                        }
-                    }
-                    u4v_t bh, bl;
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        bh[i] = __builtin_amdgcn_perm(w[2 * i + 1], w[2 * i], 0x05040100u);
-                        bl[i] = __builtin_amdgcn_perm(w[2 * i + 1], w[2 * i], 0x07060302u);
-                    }
-                    const f16x8v fh = __builtin_bit_cast(f16x8v, bh), fl = __builtin_bit_cast(f16x8v, bl);
-                    f32x16 &acc = c ? acc1 : acc0;
-                    acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, fh, acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, fl, acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(al, fh, acc, 0, 0, 0);
-                }
-                j0 -= 16 * H;
-                pc0 -= 16;
-                pc1 -= 16;
+            if constexpr (!ONE) {
+                wave_mfma<DEC, KBP>(acc0, acc1, aph, apl, gpk, tile_lo, 0, wave, col, half, mlo,
+                                    kb, kn, M, H, JL, TR);
             }
         }
         // rows 8 (i/4) + 4 half + i mod 4 = 2 dd + p: dd = 4 (i/4) + 2 half + (i mod 4) / 2
         const uint32_t bb = (uint32_t)(zk1 + d0 + 2 * half);
         const float unscale = ldexpf(a.g_unscale, -sc);
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            uint32_t nm = n0g + (uint32_t)(s0 + 32 * c);
-            nm = nm >= G ? nm - G : nm;   // G >= 512 > 255
-            const v2 w = phasor(tlo, thi, nm, a.lo_bits);                                  // e^{i 2 pi n/G}
-            v2 e = phasor(tlo, thi, mulmod(bb, nm, Gi, a.g_pow2, a.inv_G), a.lo_bits);   // bin bb
-            const v2 w4 = cmul(cmul(w, w), cmul(w, w));
-            const f32x16 &acc = c ? acc1 : acc0;
-            float t = 0.f;
-#pragma unroll
-            for (int g4 = 0; g4 < 4; ++g4) {
-                const v2 e1 = cmul(e, w);   // next bin
-                t += e.x * acc[4 * g4] - e.y * acc[4 * g4 + 1];
-                t += e1.x * acc[4 * g4 + 2] - e1.y * acc[4 * g4 + 3];
-                e = cmul(e, w4);
+        for (int cg = 0; cg < TF; ++cg) {
+            if constexpr (ONE) {
+                acc0 = f32x16{};
+                acc1 = f32x16{};
+                wave_mfma<DEC, KBP>(acc0, acc1, aph, apl, gpk, tile_lo, cg, wave, col, half, mlo,
+                                    0, K, M, H, JL, TR);
             }
-            t += __shfl_xor(t, 32, 64);
-            if (c)
-                y1 += t * unscale;
-            else
-                y0 += t * unscale;
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                // nm = n mod G: n - tile_lo < 1024 and G >= 512, so two steps suffice
+                uint32_t nm = n0g + (uint32_t)(256 * cg + 64 * wave + col + 32 * c);
+                nm = nm >= G ? nm - G : nm;
+                nm = nm >= G ? nm - G : nm;
+                const v2 w = phasor(tlo, thi, (int)nm, a.lo_bits);                             // e^{i 2 pi n/G}
+                v2 e = phasor(tlo, thi, mulmod(bb, nm, Gi, a.g_pow2, a.inv_G), a.lo_bits);   // bin bb
+                const v2 w4 = cmul(cmul(w, w), cmul(w, w));
+                const f32x16 &acc = c ? acc1 : acc0;
+                float t = 0.f;
+#pragma unroll
+                for (int g4 = 0; g4 < 4; ++g4) {
+                    const v2 e1 = cmul(e, w);   // next bin
+                    t += e.x * acc[4 * g4] - e.y * acc[4 * g4 + 1];
+                    t += e1.x * acc[4 * g4 + 2] - e1.y * acc[4 * g4 + 3];
+                    e = cmul(e, w4);
+                }
+                t += __shfl_xor(t, 32, 64);
+                y[cg][c] += t * unscale;
+            }
         }
     }
 
     // denominator and output: lanes of the first half write their two samples
     double d2 = 0.0, r2 = 0.0;
 #pragma unroll
+    for (int cg = 0; cg < TF; ++cg)
+#pragma unroll
     for (int c = 0; c < 2; ++c) {
-        const int n = tile_lo + s0 + 32 * c;
+        const int n = tile_lo + 256 * cg + wave * 64 + col + 32 * c;
         const bool writer = half == 0 && n <= tile_hi;
         float xv = 0.f;
         if (writer) {
@@ -1630,7 +1661,7 @@ __global__ __launch_bounds__(256, ONE ? (DEC ? 6 : 5) : 4) void inv_kernel(InvLa
                     dv += win[n - m * H + M].x;
                 dv *= win[M].x;
             }
-            xv = dv > 0.f ? (c ? y1 : y0) / dv : 0.f;
+            xv = dv > 0.f ? y[cg][c] / dv : 0.f;
             float *out = a.xhat + (int64_t)q * a.n + n;
             if (a.accumulate)
                 xv += *out;
@@ -1802,7 +1833,13 @@ hipError_t launch_fwd_nzm(int max_n_src, int max_n_dst, bool debug, const GroupL
     } else if (debug) {
         hipLaunchKernelGGL((fwd_kernel<NF, NZ, 9, true, true, MULTI>), g, b, 0, s, gl);
     } else if (chunked) {
-        hipLaunchKernelGGL((fwd_kernel<NF, NZ, 9, false, true, MULTI>), g, b, 0, s, gl);
+        // rows longer than the buffer; fewer rounds where they suffice keep
+        // the register count within the four-waves-per-SIMD budget
+        if (NF >= 4096 && fwd_rounds(NF, max_n_src) <= 5)
+            hipLaunchKernelGGL((fwd_kernel<NF, NZ, (NF >= 4096 ? 5 : 9), false, true, MULTI>), g, b,
+                               0, s, gl);
+        else
+            hipLaunchKernelGGL((fwd_kernel<NF, NZ, 9, false, true, MULTI>), g, b, 0, s, gl);
     } else {
         switch (fwd_rounds(NF, max_n_src)) {
         case 3: hipLaunchKernelGGL((fwd_kernel<NF, NZ, 3, false, false, MULTI>), g, b, 0, s, gl); break;
@@ -1980,7 +2017,8 @@ hipError_t launch_put_desc(const ChanDesc &d, ChanDesc *dst, bool clear_max, int
 
 size_t inv_lds_bytes(const InvLaunch &l)
 {
-    return inv_lds_layout(l.max_tab, l.max_gtab, l.max_k).total;
+    const int kbp = l.tf > 1 ? InvGeo<kInvWideTF>::KBP : InvGeo<1>::KBP;
+    return inv_lds_layout(l.max_tab, l.max_gtab, l.max_k, kbp).total;
 }
 
 hipError_t launch_inverse(const InvLaunch &l, int64_t blocks, bool clear_err, hipStream_t s)
@@ -1995,14 +2033,23 @@ hipError_t launch_inverse(const InvLaunch &l, int64_t blocks, bool clear_err, hi
         return hipSuccess;
     const size_t lds = inv_lds_bytes(l);
     const dim3 g((unsigned)blocks), b(256);
-    if (l.max_k <= kInvKB && l.dec)
-        hipLaunchKernelGGL((inv_kernel<true, true>), g, b, lds, s, l);
-    else if (l.max_k <= kInvKB)
-        hipLaunchKernelGGL((inv_kernel<true, false>), g, b, lds, s, l);
-    else if (l.dec)
-        hipLaunchKernelGGL((inv_kernel<false, true>), g, b, lds, s, l);
-    else
-        hipLaunchKernelGGL((inv_kernel<false, false>), g, b, lds, s, l);
+    if (l.tf > 1) {
+        // the host sets tf > 1 only when every tile's frames fit one block
+        if (l.max_k > InvGeo<kInvWideTF>::KB)
+            return hipErrorInvalidValue;
+        if (l.dec)
+            hipLaunchKernelGGL((inv_kernel<true, true, kInvWideTF>), g, b, lds, s, l);
+        else
+            hipLaunchKernelGGL((inv_kernel<true, false, kInvWideTF>), g, b, lds, s, l);
+    } else if (l.max_k <= InvGeo<1>::KB && l.dec) {
+        hipLaunchKernelGGL((inv_kernel<true, true, 1>), g, b, lds, s, l);
+    } else if (l.max_k <= InvGeo<1>::KB) {
+        hipLaunchKernelGGL((inv_kernel<true, false, 1>), g, b, lds, s, l);
+    } else if (l.dec) {
+        hipLaunchKernelGGL((inv_kernel<false, true, 1>), g, b, lds, s, l);
+    } else {
+        hipLaunchKernelGGL((inv_kernel<false, false, 1>), g, b, lds, s, l);
+    }
     return hipGetLastError();
 }
 

@@ -248,3 +248,57 @@ def test_forward_static_rejects_oversized_workspace():
     st = sst.lib().sst_forward_static(p._h, None, 0, 0, None, None, 0, None)
     assert st == sst.SST_E_UNSUPPORTED
     assert b"static scratch" in sst.lib().sst_last_error()
+
+
+def test_tuning_set_get_and_validation():
+    p = sst.Plan(**_params())
+    t = p.get_tuning()
+    assert t["inv_tf"] == 4 and t["seed_step"] == 0    # c2 shape: a 1024-sample tile meets 130 frames
+    p.set_tuning(fwd_wg_per_cu=2, seed_step=64, inv_tf=1)
+    t = p.get_tuning()
+    assert (t["fwd_wg_per_cu"], t["seed_step"], t["inv_tf"]) == (2, 64, 1)
+    with pytest.raises(sst.SSTError) as e:
+        p.set_tuning(inv_tf=3)
+    assert e.value.status == sst.SST_E_ARG
+    with pytest.raises(sst.SSTError) as e:
+        p.set_tuning(seed_step=-1)
+    assert e.value.status == sst.SST_E_ARG
+    # hop 4 with a 1023-tap window: 1024 samples meet 512 frames, beyond the staged block
+    q = sst.Plan(**_params(hop=4))
+    assert q.get_tuning()["inv_tf"] == 1
+    with pytest.raises(sst.SSTError) as e:
+        q.set_tuning(inv_tf=4)
+    assert e.value.status == sst.SST_E_UNSUPPORTED
+
+
+def test_tuning_cache_round_trip(tmp_path, monkeypatch):
+    """The JSON cache is keyed by shape: an entry saved for one plan applies to a
+    plan of the same shape (explicitly, and through SST_TUNE_CACHE at plan time)
+    and not to another shape; entries of other shapes are kept on save."""
+    import json
+    path = str(tmp_path / "tune.json")
+    a = sst.Plan(**_params())
+    a.set_tuning(fwd_wg_per_cu=3, seed_step=16, inv_tf=1)
+    a.tuning_save(path)
+    other = sst.Plan(**_params(hop=8))
+    other.set_tuning(seed_step=128)
+    other.tuning_save(path)
+    a.set_tuning(fwd_wg_per_cu=2, seed_step=16, inv_tf=1)
+    a.tuning_save(path)                      # replaces a's entry, keeps the other one
+    d = json.load(open(path))
+    assert len(d) == 2
+    key = [k for k in d if "H=16" in k][0]
+    assert key.startswith("gfx950 nfft=4096 L=1023 H=16 n_src=1025 n_dst=4097")
+    assert d[key] == {"fwd_wg_per_cu": 2, "seed_step": 16, "inv_tf": 1}
+    b = sst.Plan(**_params())
+    b.tuning_load(path)
+    assert b.get_tuning() == {"fwd_wg_per_cu": 2, "seed_step": 16, "inv_tf": 1}
+    monkeypatch.setenv("SST_TUNE_CACHE", path)
+    c = sst.Plan(**_params())
+    assert c.get_tuning()["seed_step"] == 16 and c.get_tuning()["inv_tf"] == 1
+    e = sst.Plan(**_params(nfft=8192, win_len=2047, sigma=256.0))   # no entry: defaults
+    assert e.get_tuning()["seed_step"] == 0
+    with pytest.raises(sst.SSTError):
+        e.tuning_load(path)
+    monkeypatch.setenv("SST_TUNE_CACHE", str(tmp_path / "missing.json"))
+    assert sst.Plan(**_params()).get_tuning()["seed_step"] == 0

@@ -6,11 +6,16 @@ z = 1) and on a band with k1 > 0 and z = 2.
 Reported for every tier: relative Frobenius error of S, S' and T (T against
 the oracle's coefficients re-scattered with the GPU's index decisions, and
 raw), literal index mismatches, and the inverse SNR against the oracle's.
-Bars: the FP16 x3 tier meets the FP32 bars (relF <= 1e-5, index flips only
-within the per-coefficient error bound of its arithmetic, SNR within 0.1 dB);
-the BF16 tier has 8-bit significands, so each product of two rounded operands
-is only good to about 2^-7 relative: relF <= 1e-2, SNR within 1 dB, indices
-reported."""
+Index rule of both tiers: a destination may differ from the oracle's only
+where the tier's worst-case error bound of S and S' can move the oracle's
+fractional destination across the rounding boundary (tests/parity.py):
+|dS| <= (u_p + L 2^-24) sum_j |x w|, with u_p the relative error of one
+product of rounded operands (FP16 x3: 2^-21; BF16, 8-bit significands:
+2^-7) and L 2^-24 the FP32 accumulation over L taps.
+Bars: the FP16 x3 tier meets the FP32 bars (relF <= 1e-5, SNR within 0.1 dB);
+BF16: relF <= 1e-2, SNR within 1 dB.  The production kernel (no per-
+coefficient outputs), which the benchmark times, gives T bit for bit equal to
+the debug instantiation compared with the oracle."""
 import math
 import sys
 
@@ -83,8 +88,9 @@ def test_gemm_tier_against_oracle(sst, name, w, prec):
     e_s, e_sd = relf(S_g, o.S), relf(Sd_g, o.Sd)
     e_t = relf(T_g, reconciled_T(o.S, idx_g, plan.n_dst))
     e_raw, e_32 = relf(T_g, o.T), relf(T_g, T32.cpu().numpy())
-    # index bound of this arithmetic: S and S' move by u * sum_j |x w| per frame
-    u = 2.0 ** -21 if prec == "f16x3" else 2.0 ** -7
+    # index bound of this arithmetic: S and S' move by at most
+    # (u_p + L 2^-24) sum_j |x w| per frame
+    u = (2.0 ** -21 if prec == "f16x3" else 2.0 ** -7) + cfg.win_len * 2.0 ** -24
     frames = np.arange(nfr)
     err_s = u * _l1_norms(x, o.g, cfg.hop, frames)
     err_sd = u * _l1_norms(x, o.gd, cfg.hop, frames)
@@ -105,13 +111,17 @@ def test_gemm_tier_against_oracle(sst, name, w, prec):
         d_snr.append(s_g - s_o)
     _say(f"[gemm {prec}] {name}: relF S={e_s:.2e} S'={e_sd:.2e} T(reconciled)={e_t:.2e} "
          f"T(raw)={e_raw:.2e} T-vs-FP32-FFT={e_32:.2e} dSNR={['%.3f' % d for d in d_snr]} {rep}")
+    assert rep.ok(), (rep, rep.details)
     if prec == "f16x3":
         assert e_s <= 1e-5 and e_sd <= 1e-5 and e_t <= 1e-5
-        assert rep.ok(), (rep, rep.details)
         assert max(abs(d) for d in d_snr) <= 0.1
     else:
         assert e_s <= 1e-2 and e_sd <= 1e-2 and e_t <= 1e-2
         assert max(abs(d) for d in d_snr) <= 1.0
+    # the production kernel (the one the benchmark times) against the debug one
+    T_prod = plan.forward(xg, reuse_gamma=True)
+    torch.cuda.synchronize()
+    assert torch.equal(torch.view_as_real(T_prod), torch.view_as_real(T)), name
 
 
 @pytest.mark.parametrize("prec", ["f16x3", "bf16"])

@@ -181,14 +181,23 @@ def _ridges_from_if(w, plan):
     return ridge_bins(f, w.cfg.fs, w.cfg.nfft, plan.k1, w.cfg.subdiv, plan.n_dst)
 
 
+@pytest.mark.parametrize("tf", [1, 4])
 @pytest.mark.parametrize("which", ["c2-small", "c1"])
-def test_inverse_on_identical_T(sst, which):
-    """Eqs. 25-26 on the same T (oracle T rounded to complex64): elementwise parity."""
+def test_inverse_on_identical_T(sst, which, tf):
+    """Eqs. 25-26 on the same T (oracle T rounded to complex64): elementwise parity,
+    with one and with four groups of 256 output samples per workgroup."""
     w = make_c2(n=1 << 15) if which == "c2-small" else make_c1()
     c = w.cfg
-    _say(f"[inverse] {which}")
+    _say(f"[inverse] {which} tf={tf}")
     o = oracle.forward(w.x.astype(np.float64), c)
     plan = sst.Plan.from_config(w.n, c, device="cuda")
+    if which == "c1" and tf == 4:
+        # hop 1: the 1278 frames of 1024 samples exceed one staged block
+        with pytest.raises(sst.SSTError) as e:
+            plan.set_tuning(inv_tf=tf)
+        assert e.value.status == sst.SST_E_UNSUPPORTED
+        return
+    plan.set_tuning(inv_tf=tf)
     T32 = o.T.astype(np.complex64)
     ridge = _ridges_from_if(w, plan)
     xh_g = plan.inverse(torch.from_numpy(T32).cuda(), torch.from_numpy(ridge).cuda(), c.hw)
@@ -383,6 +392,55 @@ def test_reuse_gamma_needs_a_threshold_since_bind(sst):
     with pytest.raises(sst.SSTError) as e:
         plan.forward(x, None, 0, 16, reuse_gamma=True)
     assert e.value.status == sst.SST_E_STATE
+
+
+TUNE = [
+    ("c2-shape", 1 << 15, CASES[0][2]),
+    ("c3-short", 12345, SSTConfig(25600.0, 2047, 256.0, 32, 8192, 0.0, 5000.0, 8, "rel", 1e-3, 26)),
+]
+
+
+@pytest.mark.parametrize("name,n,cfg", TUNE, ids=[c[0] for c in TUNE])
+def test_tuned_choices_give_identical_T(sst, name, n, cfg):
+    """Every forward launch choice the autotuner may pick (resident workgroups per
+    CU, threshold seed step) gives T bit for bit equal to the default choice."""
+    x = torch.from_numpy(_signal(name, n, cfg.fs)).cuda()
+    plan = sst.Plan.from_config(n, cfg, device="cuda")
+    occ = plan.get_tuning()["fwd_wg_per_cu"]
+    assert occ >= 1
+    T0 = plan.forward(x)
+    for wg in range(1, occ + 1):
+        for seed in (0, 1, 16, 128):
+            plan.set_tuning(fwd_wg_per_cu=wg, seed_step=seed)
+            T = plan.forward(x)
+            torch.cuda.synchronize()
+            assert torch.equal(torch.view_as_real(T), torch.view_as_real(T0)), (wg, seed)
+
+
+def test_autotune_keeps_parity(sst):
+    """sst_autotune picks choices on the caller's buffers; the forward afterwards
+    equals the default one bit for bit and the tuned inverse matches the oracle."""
+    w = make_c2(n=1 << 15)
+    c = w.cfg
+    plan = sst.Plan.from_config(w.n, c, device="cuda")
+    xg = torch.from_numpy(w.x).cuda()
+    T0 = plan.forward(xg)
+    ridge = torch.from_numpy(_ridges_from_if(w, plan)).cuda()
+    xh = torch.empty((ridge.shape[0], w.n), dtype=torch.float32, device="cuda")
+    T = torch.empty_like(T0)
+    best = plan.autotune(xg, T, ridge, c.hw, xh, reps=2)
+    _say(f"  autotuned: {best}")
+    assert best == plan.get_tuning()
+    T1 = plan.forward(xg)
+    xh1 = plan.inverse(T1, ridge, c.hw)
+    torch.cuda.synchronize()
+    assert torch.equal(torch.view_as_real(T1), torch.view_as_real(T0))
+    o = oracle.forward(w.x.astype(np.float64), c)
+    T1c = T1.cpu().numpy().astype(np.complex128)
+    r = ridge.cpu().numpy()
+    for q in range(r.shape[0]):
+        xo = oracle.inverse(T1c, r[q], c.hw, o.g, c.hop, c.nfft, o.band.k1, c.subdiv, w.n)
+        assert relf(xh1[q].cpu().numpy(), xo) <= 1e-5
 
 
 REPRO = [

@@ -442,3 +442,53 @@ def test_eq15_and_eq26_agree_on_tone_at_hop1():
     for xh in (x26, x15):
         snr = 10 * np.log10(np.sum(x[sl] ** 2) / np.sum((x[sl] - xh[sl]) ** 2))
         assert snr > 50.0
+
+
+# ---------------------------------------------------------------------------
+# Renyi entropy (Sec. 3, Eq. 32), P = |C|^2, discrete form
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("alpha", [2.0, 3.0, 0.5])
+def test_renyi_closed_forms(alpha):
+    """One occupied cell gives 0; K equal cells give log2 K (for every alpha);
+    two levels give the closed form; scaling C changes nothing."""
+    rng = np.random.default_rng(3)
+    C = np.zeros((7, 11), dtype=np.complex128)
+    C[3, 4] = 2.0 - 1.5j
+    assert abs(oracle.renyi(C, alpha)) < 1e-12
+    for K in (2, 5, 77):
+        C = np.zeros(77, dtype=np.complex128)
+        idx = rng.choice(77, size=K, replace=False)
+        C[idx] = 0.3 * np.exp(1j * rng.uniform(0, 2 * np.pi, K))   # equal |C|, any phase
+        assert abs(oracle.renyi(C, alpha) - math.log2(K)) < 1e-12
+    # K1 cells of energy e1 and K2 of e2
+    K1, K2, e1, e2 = 3, 10, 4.0, 0.25
+    C = np.concatenate([np.full(K1, math.sqrt(e1)), np.full(K2, math.sqrt(e2) * 1j),
+                        np.zeros(5)])
+    tot = K1 * e1 + K2 * e2
+    want = math.log2(K1 * (e1 / tot) ** alpha + K2 * (e2 / tot) ** alpha) / (1 - alpha)
+    assert abs(oracle.renyi(C, alpha) - want) < 1e-12
+    C = rng.standard_normal((13, 9)) + 1j * rng.standard_normal((13, 9))
+    assert abs(oracle.renyi(C, alpha) - oracle.renyi(17.5 * C, alpha)) < 1e-12
+
+
+def test_renyi_orders_concentration():
+    """A wider Gaussian ridge (less concentrated) has a larger entropy, and the
+    entropy of a separable product of two grids is the sum of their entropies."""
+    f = np.arange(64)
+    vals = []
+    for width in (1.0, 2.0, 4.0, 8.0):
+        row = np.exp(-0.5 * ((f - 32) / width) ** 2)
+        vals.append(oracle.renyi(np.tile(row, (20, 1)), 3.0))
+    assert all(a < b for a, b in zip(vals, vals[1:]))
+    a = np.exp(-0.5 * ((np.arange(40) - 20) / 3.0) ** 2)
+    b = np.exp(-0.5 * ((np.arange(30) - 10) / 5.0) ** 2)
+    prod = np.sqrt(np.outer(a, b))        # P = |C|^2 = outer(a, b)
+    ra = oracle.renyi(np.sqrt(a), 3.0)
+    rb = oracle.renyi(np.sqrt(b), 3.0)
+    assert abs(oracle.renyi(prod, 3.0) - (ra + rb)) < 1e-10
+
+
+def test_renyi_rejects_degenerate_input():
+    assert math.isnan(oracle.renyi(np.zeros((3, 3)), 3.0))
+    assert math.isnan(oracle.renyi(np.ones((3, 3)), 1.0))
