@@ -510,14 +510,82 @@ def run_single(args):
     print(json.dumps(out), flush=True)
 
 
+def run_e1(args):
+    """The paper's own simulated signal (Sec. 3, Eqs. 30-31: three AM-FM components,
+    N = 8192 at 1024 Hz, 5 dB noise, Gaussian window sigma = 0.03 s): the TF
+    concentration study of Fig. 3 -- the third-order Renyi entropy (Eq. 32) of SST
+    and STFT over a grid of time hops H_t and frequency downsampling H_f = N / N_f
+    -- and the reconstruction SNR (Eq. 33) of the three components against the
+    zone half-width f_w (Figs. 6-7), all on the GPU."""
+    import numpy as np
+    import torch
+    import paper_2003_07065_amd as sst
+    from workloads import SSTConfig, make_paper_eq30, ridge_bins
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    w = make_paper_eq30()
+    c0 = w.cfg
+    n = w.n
+    xg = torch.from_numpy(w.x).to(dev)
+    xref = torch.from_numpy(w.comps.astype(np.float32)).to(dev)
+    hts = [1, 5, 10, 20, 40, 60]
+    nfs = [8192, 4096, 2048, 1024, 512]
+    stream = torch.cuda.current_stream(dev)
+    rows = []
+    for nf in nfs:
+        for ht in hts:
+            cfg = SSTConfig(c0.fs, c0.win_len, c0.sigma, ht, nf, 0.0, c0.fs / 2, 1, "rel", c0.thr,
+                            0)
+            plan = sst.Plan.from_config(n, cfg, device=dev)
+            T = plan.forward(xg)
+            S = plan.stft(xg)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(args.steps):
+                plan.forward(xg, T)
+            e1.record(stream)
+            r_t = sst.renyi(T, 3)
+            r_s = sst.renyi(S, 3)
+            torch.cuda.synchronize()
+            rows.append({"H_t": ht, "N_f": nf, "H_f": n // nf,
+                         "renyi_sst_bits": round(float(r_t[2].cpu()), 4),
+                         "renyi_stft_bits": round(float(r_s[2].cpu()), 4),
+                         "sst_ms": round(e0.elapsed_time(e1) / args.steps, 4)})
+            del plan, T, S
+    # reconstruction SNR against the zone half-width, H_t = 1, N_f = N
+    snr = []
+    for fw in (2.0, 5.0, 10.0, 20.0, 30.0):
+        cfg = SSTConfig(c0.fs, c0.win_len, c0.sigma, 1, n, 0.0, c0.fs / 2, 1, "rel", c0.thr, 0)
+        plan = sst.Plan.from_config(n, cfg, device=dev)
+        T = plan.forward(xg)
+        hw = int(round(fw * cfg.subdiv / cfg.delta_f))
+        ridge = ridge_bins(w.inst_freq(w.frame_times()), cfg.fs, cfg.nfft, plan.k1, cfg.subdiv,
+                           plan.n_dst)
+        err = torch.zeros((3, 2), dtype=torch.float64, device=dev)
+        plan.inverse(T, torch.from_numpy(ridge).to(dev), hw, xref=xref, err=err)
+        e = err.cpu().numpy()
+        snr.append({"f_w_hz": fw, "hw_bins": hw,
+                    "snr_db": [round(float(10 * np.log10(e[q, 1] / e[q, 0])), 3) for q in range(3)]})
+        del plan, T
+    out = {"metric": "SST Renyi entropy (bits) vs downsampling and reconstruction SNR vs f_w, "
+                     "paper Sec. 3 workload", "unit": "bits / dB", "n_gpus": 1, "data": "synthetic",
+           "config": {"workload": "Eqs. 30-31: three AM-FM components, N=8192, fs=1024 Hz, 5 dB "
+                                  "white noise (seed 0), Gaussian sigma=0.03 s (L=247), full band, "
+                                  "z=1, gamma=1e-6 max|S|"},
+           "renyi_grid": rows, "snr_vs_fw": snr}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", choices=["c3", "c2", "c4", "c5"], default="c3",
+    ap.add_argument("--workload", choices=["c3", "c2", "c4", "c5", "e1"], default="c3",
                     help="c3: the long run-up channel, N=2^26 (default); c2: N=2^20; "
-                         "c4: batched uneven channels; c5: precision tiers")
+                         "c4: batched uneven channels; c5: precision tiers; e1: the paper's "
+                         "Sec. 3 concentration and reconstruction study")
     ap.add_argument("--c5-channels", type=int, default=512)
     ap.add_argument("--c5-nfft", type=int, default=512, choices=[512, 1024])
     ap.add_argument("--c4-channels", type=int, default=256)
@@ -549,6 +617,8 @@ def main():
         run_c4(args)
     elif args.workload == "c5":
         run_c5(args)
+    elif args.workload == "e1":
+        run_e1(args)
     else:
         run_single(args)
 

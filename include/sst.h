@@ -70,6 +70,10 @@ typedef int32_t sst_status;
 /* sst_forward flags */
 #define SST_FWD_REUSE_GAMMA 1u  /* keep the gamma computed by the previous forward call
                                    on this plan (chunked calls after the first) */
+#define SST_FWD_OUT_MAG_F32 2u  /* compressed output: T holds float |T| [nframes][n_dst]
+                                   (half the bytes of the complex rows) */
+#define SST_FWD_OUT_MAG_F16 4u  /* compressed output: T holds half |T| [nframes][n_dst]
+                                   (a quarter of the bytes); both FP32 FFT tier only */
 
 /* sst_inverse flags */
 #define SST_INV_ACCUMULATE 1u   /* add into xhat instead of overwriting it */
@@ -180,9 +184,12 @@ typedef struct {
  * IF estimate, threshold, selective subdivided reassignment into T.
  *   x        device float [n_samples]; read only
  *   T        device complex float [nframes][n_dst], row r = frame frame0 + r;
- *            every element of the rows is written (zeros included)
+ *            every element of the rows is written (zeros included); with
+ *            SST_FWD_OUT_MAG_F32 / _F16 it holds float / half |T| instead (the
+ *            norm of the complex value, rounded once; not an input of the
+ *            inverse, which needs the phase)
  *   aux      optional outputs, may be NULL
- *   flags    0 or SST_FWD_REUSE_GAMMA
+ *   flags    0, or SST_FWD_REUSE_GAMMA and at most one SST_FWD_OUT_MAG_*
  * With SST_THR_REL_MAX and no SST_FWD_REUSE_GAMMA, gamma comes from max |S|
  * over ALL frames of x (not only the chunk), on the forward kernel's own FP32
  * arithmetic.  A call over the whole signal (frame0 = 0, nframes = n_frames,
@@ -408,6 +415,32 @@ sst_status sst_autotune(sst_plan_t plan, const float *x, float *T, const int32_t
  */
 sst_status sst_tuning_save(sst_plan_t plan, const char *path);
 sst_status sst_tuning_load(sst_plan_t plan, const char *path);
+
+/*
+ * sst_stft -- the STFT product alone (Sec. 2.1, Eqs. 7-9): S (and, when Sd is
+ * not NULL, S' with the window g') of frames [frame0, frame0 + nframes), in-band
+ * bins k1..k2, with the centre phase of Eq. 9 -- the values sst_forward's
+ * debug output S holds, on the same FP32 FFT pair.
+ *   S, Sd    device complex float [nframes][n_src], row r = frame frame0 + r
+ * Errors: SST_E_ARG, SST_E_STATE, SST_E_DEVICE.
+ */
+sst_status sst_stft(sst_plan_t plan, const float *x, int64_t frame0, int64_t nframes, float *S,
+                    float *Sd, void *stream);
+
+/*
+ * sst_stft_inverse -- STFT synthesis (Sec. 2.1, Eqs. 10-11) of the whole signal
+ * from in-band rows: per frame, the centre phase removed and an N_f-point
+ * inverse DFT of the one-sided spectrum (bins k1..k2; 2 Re(.) for interior
+ * bins, Re(.) at DC and at fs/2), windowed by g and overlap-added:
+ *   xhat[n] = sum_m g[n - mH] s[m, n - mH] / sum_m g[n - mH]^2,
+ *   s[m, j] = (1/N_f) sum_k a_k Re(S[m, k] e^{+i 2 pi k j / N_f}).
+ * With the full band (f_lo = 0, f_hi = fs/2) it reconstructs x exactly up to
+ * rounding; with a narrower band, the band-limited part.
+ *   S     device complex float [n_frames][n_src] (sst_stft of every frame)
+ *   xhat  device float [n_samples]
+ * Errors: SST_E_ARG, SST_E_STATE, SST_E_DEVICE.
+ */
+sst_status sst_stft_inverse(sst_plan_t plan, const float *S, float *xhat, void *stream);
 
 /*
  * sst_renyi -- Renyi entropy (Sec. 3, Eq. 32) of a time-frequency

@@ -36,6 +36,8 @@ SST_PREC_GEMM_F16X3 = 2
 PRECISIONS = {"fp32": SST_PREC_FP32_FFT, "bf16": SST_PREC_GEMM_BF16,
               "f16x3": SST_PREC_GEMM_F16X3}
 SST_FWD_REUSE_GAMMA = 1
+SST_FWD_OUT_MAG_F32 = 2
+SST_FWD_OUT_MAG_F16 = 4
 SST_INV_ACCUMULATE = 1
 SST_INV_EQ15 = 2
 
@@ -45,7 +47,7 @@ EXPORTED = ("sst_plan", "sst_plan_query", "sst_plan_bind", "sst_forward", "sst_f
             "sst_critical_hf", "sst_batch_plan", "sst_batch_query", "sst_batch_bind",
             "sst_batch_set_io", "sst_batch_commit", "sst_batch_forward", "sst_batch_inverse",
             "sst_batch_destroy", "sst_plan_get_tuning", "sst_plan_set_tuning", "sst_autotune",
-            "sst_tuning_save", "sst_tuning_load", "sst_renyi")
+            "sst_tuning_save", "sst_tuning_load", "sst_renyi", "sst_stft", "sst_stft_inverse")
 
 
 class SSTError(RuntimeError):
@@ -161,12 +163,15 @@ def lib():
     L.sst_tuning_save.argtypes = [vp, ctypes.c_char_p]
     L.sst_tuning_load.argtypes = [vp, ctypes.c_char_p]
     L.sst_renyi.argtypes = [vp, i32, i64, i32, i64, i32, vp, vp, vp]
+    L.sst_stft.argtypes = [vp, vp, i64, i64, vp, vp, vp]
+    L.sst_stft_inverse.argtypes = [vp, vp, vp, vp]
     for name in ("sst_plan", "sst_plan_query", "sst_plan_bind", "sst_forward",
                  "sst_forward_static", "sst_ridge", "sst_ridge_guided",
                  "sst_inverse", "sst_critical_hf", "sst_batch_plan", "sst_batch_query",
                  "sst_batch_bind", "sst_batch_set_io", "sst_batch_commit", "sst_batch_forward",
                  "sst_batch_inverse", "sst_plan_get_tuning", "sst_plan_set_tuning",
-                 "sst_autotune", "sst_tuning_save", "sst_tuning_load", "sst_renyi"):
+                 "sst_autotune", "sst_tuning_save", "sst_tuning_load", "sst_renyi",
+                 "sst_stft", "sst_stft_inverse"):
         getattr(L, name).restype = i32
     _lib = L
     return L
@@ -325,15 +330,16 @@ class Plan:
 
     def forward(self, x, T=None, frame0: int = 0, nframes: Optional[int] = None, *,
                 S=None, Sd=None, idx=None, colstats=None, gamma=None,
-                reuse_gamma: bool = False, kernel_events=None):
-        """SST rows of frames [frame0, frame0+nframes) into T (complex64 [nframes, n_dst]).
+                reuse_gamma: bool = False, kernel_events=None, out: str = "complex64"):
+        """SST rows of frames [frame0, frame0+nframes) into T (complex64 [nframes, n_dst]);
+        out="mag_f32" / "mag_f16" writes |T| as float32 / float16 instead.
 
         kernel_events: optional pair of torch.cuda.Event, already recorded once
         (so that they exist); the library records them again right around the
         fused forward kernel."""
         self._need_bound()
         return self._forward_call(lib().sst_forward, "sst_forward", x, T, frame0, nframes, S, Sd,
-                                  idx, colstats, gamma, reuse_gamma, kernel_events)
+                                  idx, colstats, gamma, reuse_gamma, kernel_events, out)
 
     def forward_static(self, x, T=None, frame0: int = 0, nframes: Optional[int] = None, *,
                        S=None, Sd=None, idx=None, colstats=None, gamma=None,
@@ -348,11 +354,16 @@ class Plan:
             self.device = torch.device("cuda", torch.cuda.current_device())
         return self._forward_call(lib().sst_forward_static, "sst_forward_static", x, T, frame0,
                                   nframes, S, Sd, idx, colstats, gamma, reuse_gamma,
-                                  kernel_events)
+                                  kernel_events, "complex64")
 
     def _forward_call(self, fn, where, x, T, frame0, nframes, S, Sd, idx, colstats, gamma,
-                      reuse_gamma, kernel_events):
+                      reuse_gamma, kernel_events, out):
         import torch
+        fmt = {"complex64": (torch.complex64, 0), "mag_f32": (torch.float32, SST_FWD_OUT_MAG_F32),
+               "mag_f16": (torch.float16, SST_FWD_OUT_MAG_F16)}
+        if out not in fmt:
+            raise ValueError("out must be complex64, mag_f32 or mag_f16")
+        tdt, oflag = fmt[out]
         if nframes is None:
             nframes = self.n_frames - frame0
         if x.dtype != torch.float32 or not x.is_contiguous() or x.device != self.device:
@@ -360,8 +371,8 @@ class Plan:
         if x.numel() != self.n_samples:
             raise ValueError("x length differs from the plan's n_samples")
         if T is None:
-            T = torch.empty((nframes, self.n_dst), dtype=torch.complex64, device=self.device)
-        self._check_buf(T, torch.complex64, nframes * self.n_dst, "T")
+            T = torch.empty((nframes, self.n_dst), dtype=tdt, device=self.device)
+        self._check_buf(T, tdt, nframes * self.n_dst, "T")
         for t, n, dt, nm in ((S, self.n_src, torch.complex64, "S"),
                              (Sd, self.n_src, torch.complex64, "Sd"),
                              (idx, self.n_src, torch.int32, "idx"),
@@ -376,7 +387,7 @@ class Plan:
                 aux.kernel_events[i] = ev.cuda_event
         _check(fn(self._h, ctypes.c_void_p(x.data_ptr()), int(frame0), int(nframes),
                   ctypes.c_void_p(T.data_ptr()), ctypes.byref(aux),
-                  SST_FWD_REUSE_GAMMA if reuse_gamma else 0,
+                  (SST_FWD_REUSE_GAMMA if reuse_gamma else 0) | oflag,
                   ctypes.c_void_p(_stream_handle(self.device))), where)
         return T
 
@@ -431,6 +442,37 @@ class Plan:
                                  int(hw), ctypes.c_void_p(xhat.data_ptr()),
                                  ctypes.c_void_p(_ptr(xref)), ctypes.c_void_p(_ptr(err)), flags,
                                  ctypes.c_void_p(_stream_handle(self.device))), "sst_inverse")
+        return xhat
+
+    def stft(self, x, S=None, frame0: int = 0, nframes: Optional[int] = None, Sd=None):
+        """sst_stft: in-band STFT rows (complex64 [nframes, n_src]) of frames
+        [frame0, frame0 + nframes), and S' when Sd is given."""
+        import torch
+        self._need_bound()
+        if nframes is None:
+            nframes = self.n_frames - frame0
+        self._check_buf(x, torch.float32, self.n_samples, "x")
+        if S is None:
+            S = torch.empty((nframes, self.n_src), dtype=torch.complex64, device=self.device)
+        self._check_buf(S, torch.complex64, nframes * self.n_src, "S")
+        self._check_buf(Sd, torch.complex64, nframes * self.n_src, "Sd")
+        _check(lib().sst_stft(self._h, ctypes.c_void_p(x.data_ptr()), int(frame0), int(nframes),
+                              ctypes.c_void_p(S.data_ptr()), ctypes.c_void_p(_ptr(Sd)),
+                              ctypes.c_void_p(_stream_handle(self.device))), "sst_stft")
+        return S
+
+    def stft_inverse(self, S, xhat=None):
+        """sst_stft_inverse: STFT synthesis (Eqs. 10-11) of the whole signal."""
+        import torch
+        self._need_bound()
+        self._check_buf(S, torch.complex64, self.n_frames * self.n_src, "S")
+        if xhat is None:
+            xhat = torch.empty(self.n_samples, dtype=torch.float32, device=self.device)
+        self._check_buf(xhat, torch.float32, self.n_samples, "xhat")
+        _check(lib().sst_stft_inverse(self._h, ctypes.c_void_p(S.data_ptr()),
+                                      ctypes.c_void_p(xhat.data_ptr()),
+                                      ctypes.c_void_p(_stream_handle(self.device))),
+               "sst_stft_inverse")
         return xhat
 
     # -- launch choices (sst_plan_get_tuning / sst_plan_set_tuning / sst_autotune) --

@@ -98,7 +98,7 @@ struct sst_plan_s {
     size_t off_afrag = 0, off_afrag_lo = 0, afrag_bytes = 0;
     // workspace layout (bytes): control block, descriptor slot, tables
     size_t off_desc = 0, off_idesc = 0, off_win = 0, off_twid = 0, off_phlo = 0, off_phhi = 0;
-    size_t off_den = 0;
+    size_t off_den = 0, off_den2 = 0;
     size_t tables_end = 0, ws_bytes = 0;
     // speculative threshold (FFT tier): least kept |S|^2 per forward item, the
     // fix-up list and its count
@@ -506,6 +506,8 @@ sst_status sst_plan(const sst_params *params, sst_plan_t *out)
     off = align_up(off + sizeof(float) * 2 * (size_t)pl->n_hi);
     pl->off_den = off;
     off = align_up(off + sizeof(float) * (size_t)p.hop);
+    pl->off_den2 = off;
+    off = align_up(off + sizeof(float) * (size_t)p.hop);
     const bool gemm = p.precision != SST_PREC_FP32_FFT;
     if (gemm) {
         pl->row_tiles = (4 * pl->n_src + 31) / 32;
@@ -586,6 +588,15 @@ sst_status sst_plan(const sst_params *params, sst_plan_t *out)
                 if ((((j % p.hop) + p.hop) % p.hop) == r)
                     acc += g[j + pl->M];
             den[r] = (float)(pl->g0 * acc);
+        }
+        // STFT synthesis (Eq. 11): sum of g[j]^2 over j = r mod H
+        float *den2 = reinterpret_cast<float *>(pl->blob.data() + (pl->off_den2 - pl->off_win));
+        for (int r = 0; r < p.hop; ++r) {
+            double acc = 0.0;
+            for (int j = -pl->M; j <= pl->M; ++j)
+                if ((((j % p.hop) + p.hop) % p.hop) == r)
+                    acc += g[j + pl->M] * g[j + pl->M];
+            den2[r] = (float)acc;
         }
     }
     if (gemm)
@@ -691,8 +702,13 @@ static sst_status forward_impl(sst_plan_s *pl, Bound &bd, const float *x, int64_
         return fail(SST_E_ARG, "x and T must not be NULL");
     if (frame0 < 0 || nframes < 0 || frame0 + nframes > pl->n_frames)
         return fail(SST_E_ARG, "frame range outside [0, n_frames)");
-    if (flags & ~SST_FWD_REUSE_GAMMA)
+    if (flags & ~(SST_FWD_REUSE_GAMMA | SST_FWD_OUT_MAG_F32 | SST_FWD_OUT_MAG_F16))
         return fail(SST_E_ARG, "unknown forward flags");
+    if ((flags & SST_FWD_OUT_MAG_F32) && (flags & SST_FWD_OUT_MAG_F16))
+        return fail(SST_E_ARG, "choose one compressed output format");
+    const int out_fmt = (flags & SST_FWD_OUT_MAG_F32) ? 1 : ((flags & SST_FWD_OUT_MAG_F16) ? 2 : 0);
+    if (out_fmt && pl->gemm_ft)
+        return fail(SST_E_UNSUPPORTED, "compressed outputs are produced by the FP32 FFT tier");
     if ((flags & SST_FWD_REUSE_GAMMA) && !bd.gamma_valid)
         return fail(SST_E_STATE, "SST_FWD_REUSE_GAMMA before any thresholding forward call on "
                                  "this binding");
@@ -711,6 +727,7 @@ static sst_status forward_impl(sst_plan_s *pl, Bound &bd, const float *x, int64_
     const bool spec = threshold && rel && fft && !debug && frame0 == 0 &&
                       nframes == pl->n_frames && nframes > 0;
     sst::ChanDesc d = chan_desc(pl, bd.ws, x, frame0, nframes, T, aux, ctrl);
+    d.out_fmt = out_fmt;
     d.item0 = 0;
     d.item_end = (nframes + F - 1) / F;
     d.mitem0 = 0;
@@ -1608,6 +1625,72 @@ sst_status sst_batch_inverse(sst_batch_t b, int32_t c_begin, int32_t c_end, void
 
 void sst_batch_destroy(sst_batch_t b) { delete b; }
 
+
+sst_status sst_stft(sst_plan_t pl, const float *x, int64_t frame0, int64_t nframes, float *S,
+                    float *Sd, void *stream)
+{
+    if (!pl)
+        return fail(SST_E_ARG, "plan is NULL");
+    if (!pl->bd.ws)
+        return fail(SST_E_STATE, "plan is not bound to a workspace");
+    if (!x || !S)
+        return fail(SST_E_ARG, "x and S must not be NULL");
+    if (frame0 < 0 || nframes < 0 || frame0 + nframes > pl->n_frames)
+        return fail(SST_E_ARG, "frame range outside [0, n_frames)");
+    if (nframes == 0)
+        return SST_OK;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int F = sst::fwd_frames_per_iter(pl->p.nfft);
+    sst_fwd_aux aux{};
+    aux.S = S;
+    aux.Sd = Sd;
+    sst::ChanDesc d = chan_desc(pl, pl->bd.ws, x, frame0, nframes, nullptr, &aux,
+                                reinterpret_cast<sst::Ctrl *>(pl->bd.ws));
+    d.item0 = 0;
+    d.item_end = (nframes + F - 1) / F;
+    sst::ChanDesc *slot = reinterpret_cast<sst::ChanDesc *>(pl->bd.ws + pl->off_desc);
+    hipError_t e = sst::launch_put_desc(d, slot, false, nullptr, s);
+    sst::GroupLaunch g{};
+    g.ch = slot;
+    g.n_ch = 1;
+    g.twid = reinterpret_cast<const float2 *>(pl->bd.ws + pl->off_twid);
+    g.item_begin = 0;
+    g.item_stop = d.item_end;
+    const int grid = (int)(d.item_end < pl->bd.fwd_grid_cap ? d.item_end : pl->bd.fwd_grid_cap);
+    if (e == hipSuccess)
+        e = sst::launch_stft(pl->p.nfft, pl->p.win_len, g, grid, s);
+    if (e != hipSuccess)
+        return hip_fail(e, "STFT launch");
+    return SST_OK;
+}
+
+sst_status sst_stft_inverse(sst_plan_t pl, const float *S, float *xhat, void *stream)
+{
+    if (!pl)
+        return fail(SST_E_ARG, "plan is NULL");
+    if (!pl->bd.ws)
+        return fail(SST_E_STATE, "plan is not bound to a workspace");
+    if (!S || !xhat)
+        return fail(SST_E_ARG, "S and xhat must not be NULL");
+    sst::SynArgs a{};
+    a.S = reinterpret_cast<const float2 *>(S);
+    a.win = reinterpret_cast<const float2 *>(pl->bd.ws + pl->off_win);
+    a.den2 = reinterpret_cast<const float *>(pl->bd.ws + pl->off_den2);
+    a.twid = reinterpret_cast<const float2 *>(pl->bd.ws + pl->off_twid);
+    a.xhat = xhat;
+    a.n = pl->p.n_samples;
+    a.n_frames = pl->n_frames;
+    a.M = pl->M;
+    a.hop = pl->p.hop;
+    a.k1 = pl->k1;
+    a.k2 = pl->k2;
+    a.n_src = pl->n_src;
+    a.inv_nfft = (float)(1.0 / pl->p.nfft);
+    hipError_t e = sst::launch_synthesis(pl->p.nfft, a, reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess)
+        return hip_fail(e, "STFT synthesis launch");
+    return SST_OK;
+}
 
 sst_status sst_renyi(const void *C, int32_t kind, int64_t rows, int32_t cols, int64_t ld,
                      int32_t alpha, double *work, double *out, void *stream)

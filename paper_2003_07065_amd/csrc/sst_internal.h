@@ -42,7 +42,7 @@ struct ChanDesc {
     float thr;              // gamma (absolute) or rho (relative)
     float inv_s;            // 1/s: S' = B / s
     float cdelta;           // N_f / (2 pi s): delta (bins) = cdelta Im(B conj A) / |A|^2
-    float pad_;
+    int out_fmt;            // rows of T: 0 complex float, 1 float |T|, 2 half |T|
 };
 
 // One launch of the threshold or forward kernel over descriptors ch[0 .. n_ch).
@@ -154,6 +154,22 @@ struct RidgeArgs {
     const int32_t *centre;  // optional [n_comp][nframes] guide bins (-1: no ridge)
     int32_t *ridge;         // [n_comp][nframes]
 };
+
+// STFT synthesis (Eqs. 10-11) from in-band rows [n_frames][n_src].
+constexpr int kSynTile = 2048;   // output samples per synthesis workgroup
+struct SynArgs {
+    const float2 *S;        // [n_frames][n_src], bins k1..k2, centre phase included (Eq. 9)
+    const float2 *win;      // [L]: .x = g[j]
+    const float *den2;      // [hop]: sum of g[j]^2 over j = r mod hop, |j| <= M
+    const float2 *twid;     // [N_f]: exp(-i 2 pi r / N_f)
+    float *xhat;            // [n]
+    int64_t n, n_frames;
+    int M, hop, k1, k2, n_src;
+    float inv_nfft;
+};
+hipError_t launch_synthesis(int nfft, const SynArgs &a, hipStream_t s);
+// STFT product: S (and S') rows of the items of g (forward numbering).
+hipError_t launch_stft(int nfft, int L, const GroupLaunch &g, int grid, hipStream_t s);
 
 // Arguments of the Renyi-entropy reduction (sst_analysis.hip).
 constexpr int kRenyiParts = 1024;   // per-workgroup partial sums (work holds 2 per part)

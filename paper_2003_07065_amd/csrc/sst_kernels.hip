@@ -522,7 +522,7 @@ struct Chan {
     double *colstats;
     Ctrl *ctrl;
     int64_t n, n_frames, frame0, nframes, item0, item_end;
-    int L, M, hop, k1, n_src, n_dst, z, thr_mode;
+    int L, M, hop, k1, n_src, n_dst, z, thr_mode, out_fmt;
     float gamma2, thr, inv_s, cdelta, inv_nsrc, inv_ndst;
 };
 
@@ -554,6 +554,7 @@ __device__ __forceinline__ Chan load_chan(const CA ChanDesc *ch, int c)
     r.n_dst = d.n_dst;
     r.z = d.z;
     r.thr_mode = d.thr_mode;
+    r.out_fmt = d.out_fmt;
     r.thr = d.thr;
     r.gamma2 = THRESHOLD ? 0.f : ((const CA Ctrl *)d.ctrl)->gamma2;
     r.inv_s = d.inv_s;
@@ -575,6 +576,7 @@ __device__ __forceinline__ v2 cphase_of(const v2 *lo, const v2 *hi, int t)
 constexpr int kFwdPlain = 0;     // the forward over items item_begin, item_begin + 1, ...
 constexpr int kFwdMaxOnly = 1;   // threshold pre-pass on the forward's arithmetic
 constexpr int kFwdFixup = 2;     // the forward over the items of a fix-up list
+constexpr int kFwdStft = 3;      // the STFT product only: S (and S') rows of the items
 
 template <int NF, int NZ, int R, bool DEBUG, bool CHUNKED, bool MULTI, int MODE = kFwdPlain>
 // Waves per SIMD: 4 for N_f = 8192 and for N_f = 4096 with at most 8 tap rows
@@ -725,6 +727,38 @@ __global__ __launch_bounds__(Geo<NF>::NT, DEBUG ? 2 : ((NF == 8192 || (NF == 409
         __syncthreads();
         tw.passes(lds, twl);
 
+        if constexpr (MODE == kFwdStft) {
+            // STFT product (Eq. 9 with its centre phase; S' with g'): every
+            // in-band bin of the item's frames, rows of n_src written in order
+            const int EM = nvalid * a.n_src;
+            v2 *__restrict__ Sp = reinterpret_cast<v2 *>(a.S) + m0 * (int64_t)a.n_src;
+            v2 *__restrict__ Sdp =
+                a.Sd ? reinterpret_cast<v2 *>(a.Sd) + m0 * (int64_t)a.n_src : nullptr;
+            for (int e = threadIdx.x; e < EM; e += NT) {
+                int f, ik;
+                if constexpr (F == 1) {
+                    f = 0;
+                    ik = e;
+                } else {
+                    split_flat(e, a.n_src, inv_nsrc, f, ik);
+                }
+                const int k = a.k1 + ik;
+                const v2 P = lds[pad16(f * NF + k)];
+                const v2 Qc = conjv(lds[pad16(f * NF + ((NF - k) & (NF - 1)))]);
+                const v2 phk = cphase_of(clo, chi, (k * a.M) & (NF - 1));
+                __builtin_nontemporal_store(cmul(phk, 0.5f * (P + Qc)), Sp + e);
+                if (Sdp) {
+                    const v2 D = P - Qc;
+                    const v2 B = mk(0.5f * D.y, -0.5f * D.x);
+                    __builtin_nontemporal_store(a.inv_s * cmul(phk, B), Sdp + e);
+                }
+            }
+            a = an;
+            new_chan = chg;
+            it = itn;
+            li += gridDim.x;
+            continue;
+        }
         if constexpr (MAXONLY) {
             const int EM = nvalid * a.n_src;
             for (int e = threadIdx.x; e < EM; e += NT) {
@@ -879,7 +913,10 @@ __global__ __launch_bounds__(Geo<NF>::NT, DEBUG ? 2 : ((NF == 8192 || (NF == 409
                 atomicMax(&a.ctrl->maxbits, __float_as_uint(imx));
         }
 
-        v2 *__restrict__ trow = reinterpret_cast<v2 *>(a.T) + m0 * (int64_t)a.n_dst;
+        // bytes per stored bin: complex float, or the magnitude as float or half
+        const int osh = a.out_fmt == 0 ? 3 : (a.out_fmt == 1 ? 2 : 1);
+        unsigned char *__restrict__ trow =
+            reinterpret_cast<unsigned char *>(a.T) + ((m0 * (int64_t)a.n_dst) << osh);
         // the bound is summed in a fixed order so the scale, hence T, is
         // reproducible bit for bit
         float scf[F];
@@ -928,7 +965,8 @@ __global__ __launch_bounds__(Geo<NF>::NT, DEBUG ? 2 : ((NF == 8192 || (NF == 409
             // makes the hardware drop the stores past the end, so every store
             // instruction is unconditional.
             const __amdgpu_buffer_rsrc_t rs =
-                __builtin_amdgcn_make_buffer_rsrc(trow + c0, (short)0, cn * 8, kBufferWord3);
+                __builtin_amdgcn_make_buffer_rsrc(trow + ((int64_t)c0 << osh), (short)0, cn << osh,
+                                                  kBufferWord3);
             // bins are read in groups of SG: one LDS round trip per group
             constexpr int SG = 6;
 #pragma unroll
@@ -959,8 +997,21 @@ __global__ __launch_bounds__(Geo<NF>::NT, DEBUG ? 2 : ((NF == 8192 || (NF == 409
                     const int re = (int)(unsigned)hv[i];
                     const int im = (int)(unsigned)(hv[i] >> 32);
                     const v2 v = mk((float)re * isc, (float)im * isc);
-                    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), rs,
-                                                          (unsigned)e * 8u, 0, kNonTemporal);
+                    if (osh == 3) {
+                        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), rs,
+                                                              (unsigned)e * 8u, 0, kNonTemporal);
+                    } else {
+                        // compressed rows: |T| (one rounding of the complex value's norm)
+                        const float mg = __builtin_sqrtf(__builtin_fmaf(v.x, v.x, v.y * v.y));
+                        if (osh == 2)
+                            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, mg),
+                                                                  rs, (unsigned)e * 4u, 0,
+                                                                  kNonTemporal);
+                        else
+                            __builtin_amdgcn_raw_buffer_store_b16(
+                                __builtin_bit_cast(unsigned short, (_Float16)mg), rs,
+                                (unsigned)e * 2u, 0, kNonTemporal);
+                    }
                     if constexpr (DEBUG) {
                         if (a.colstats && e < cn) {
                             const int f = (c0 + e) / a.n_dst;
@@ -987,6 +1038,130 @@ __global__ __launch_bounds__(Geo<NF>::NT, DEBUG ? 2 : ((NF == 8192 || (NF == 409
         new_chan = chg;
         it = itn;
         li += gridDim.x;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// STFT synthesis (Sec. 2.1, Eqs. 10-11) from in-band STFT rows.  Per frame m,
+// s[m, j] = (1/N_f) sum_k a_k Re(S[m, k] e^{+i 2 pi k j / N_f}), j in [-M, M]
+// (Eq. 10: the centre phase e^{-i 2 pi k M / N_f} times an N_f-point inverse
+// DFT, read at n = j + M), then the overlap-add of Eq. 11 with the per-sample
+// normalisation sum_m g[n - mH]^2 (reading D3: the paper's unit sum holds for
+// no hop > 1 with its unit-energy window, and this one also covers the ends).
+//
+// The one-sided spectrum is extended Hermitian (conjugate mirror, DC and
+// Nyquist real) so that every inverse is real, and two frames share one
+// complex inverse: Z = Y_a + i Y_b gives y_a + i y_b.  The inverse runs as the
+// forward FFT of conj Z (its output is conj z).  Each workgroup owns a tile of
+// TS output samples and inverts every frame whose window reaches it (tiles
+// overlap by the window length, so each frame is inverted about (TS + L) / TS
+// times); each thread gathers its own TS / NT samples from the frames in
+// registers, so the sums need no atomics and do not depend on scheduling.
+// ---------------------------------------------------------------------------
+template <int NF>
+__global__ __launch_bounds__(Geo<NF>::NT) void syn_kernel(SynArgs a)
+{
+    using G = Geo<NF>;
+    constexpr int F = G::F, NT = G::NT, Q = NF / 16, NHI = NF / 64;
+    constexpr int TS = kSynTile, PER = TS / NT;
+    static_assert(TS % NT == 0, "a tile is a whole number of sample rounds");
+    __shared__ v2 lds[G::LDS];
+    __shared__ v2 twl[Twiddles<NF>::TW];
+    __shared__ v2 clo[64], chi[NHI];   // W^t = chi[t / 64] clo[t mod 64], W = e^{-i 2 pi / N_f}
+    const v2 *__restrict__ twid = reinterpret_cast<const v2 *>(a.twid);
+    Twiddles<NF> tw;
+    tw.load(twl, twid);
+    for (int e = threadIdx.x; e < 64 + NHI; e += NT) {
+        if (e < 64)
+            clo[e] = twid[(unsigned)e];
+        else
+            chi[e - 64] = twid[(unsigned)(e - 64) * 64u];
+    }
+    __syncthreads();
+    const int M = a.M, H = a.hop, L = 2 * a.M + 1;
+    const int n = (int)a.n, nfr = (int)a.n_frames;
+    const int t0 = (int)blockIdx.x * TS;
+    const int t1 = t0 + TS - 1 < n - 1 ? t0 + TS - 1 : n - 1;
+    const int mlo = t0 - M > 0 ? (t0 - M + H - 1) / H : 0;
+    int mhi = (t1 + M) / H;
+    mhi = mhi < nfr - 1 ? mhi : nfr - 1;
+    const v2 *__restrict__ S = reinterpret_cast<const v2 *>(a.S);
+    const v2 *__restrict__ win = reinterpret_cast<const v2 *>(a.win);
+    const int k1 = a.k1, k2 = a.k2, n_src = a.n_src;
+    // in-band S~[m, k] = S[m, k] W^{k M} (the centre phase removed), 0 outside
+    auto spec = [&](int m, int k) -> v2 {
+        if (m > mhi || k < k1 || k > k2)
+            return mk(0.f, 0.f);
+        const int t = (k * M) & (NF - 1);
+        return cmul(S[(int64_t)m * n_src + (k - k1)], cmul(chi[t >> 6], clo[t & 63]));
+    };
+    float acc[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i)
+        acc[i] = 0.f;
+    for (int m0 = mlo; m0 <= mhi; m0 += 2 * F) {
+        // pass 1 reads conj Z of slot f (frames m0 + 2f, m0 + 2f + 1) at index idx
+        pass1<NF, 16>(lds, [&](int f, int idx) -> v2 {
+            const int ma = m0 + 2 * f, mb = ma + 1;
+            v2 ya, yb;
+            if (2 * idx <= NF) {
+                ya = spec(ma, idx);
+                yb = spec(mb, idx);
+                if (idx == 0 || 2 * idx == NF) {   // real at DC and at Nyquist
+                    ya.y = 0.f;
+                    yb.y = 0.f;
+                }
+            } else {                               // conjugate mirror
+                ya = conjv(spec(ma, NF - idx));
+                yb = conjv(spec(mb, NF - idx));
+            }
+            // conj(Y_a + i Y_b)
+            return mk(ya.x - yb.y, -(ya.y + yb.x));
+        });
+        tw.passes(lds, twl);
+        // FFT(conj Z) = conj z = y_a - i y_b; each thread gathers its samples
+#pragma unroll
+        for (int f = 0; f < F; ++f) {
+            const int ma = m0 + 2 * f;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int m = ma + h;
+                if (m > mhi)
+                    continue;
+                const int base = m * H - M;   // sample of window index 0 (n = j + M)
+#pragma unroll
+                for (int i = 0; i < PER; ++i) {
+                    const int sidx = t0 + (int)threadIdx.x + i * NT;
+                    const int nn = sidx - base;
+                    if (nn >= 0 && nn < L) {
+                        const v2 o = lds[pad16(f * NF + nn)];
+                        acc[i] += win[nn].x * (h ? -o.y : o.x);
+                    }
+                }
+            }
+        }
+        __syncthreads();   // gathers done before the next pass 1 writes the buffer
+    }
+    // Eq. 11 with the per-sample normalisation sum_m g[n - mH]^2
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int sidx = t0 + (int)threadIdx.x + i * NT;
+        if (sidx > t1)
+            continue;
+        const int flo = sidx - M > 0 ? (sidx - M + H - 1) / H : 0;
+        const int fhi = (sidx + M) / H;
+        float dv;
+        if (sidx >= M && fhi <= nfr - 1) {
+            dv = a.den2[sidx % H];
+        } else {
+            dv = 0.f;
+            const int hi = fhi < nfr - 1 ? fhi : nfr - 1;
+            for (int m = flo; m <= hi; ++m) {
+                const float gj = win[sidx - m * H + M].x;
+                dv = __builtin_fmaf(gj, gj, dv);
+            }
+        }
+        a.xhat[sidx] = dv > 0.f ? acc[i] * a.inv_nfft / dv : 0.f;
     }
 }
 
@@ -1880,6 +2055,24 @@ hipError_t launch_maxonly_nz(const GroupLaunch &gl, int grid, hipStream_t s)
     return hipGetLastError();
 }
 
+template <int NF, int NZ>
+hipError_t launch_stft_nz(const GroupLaunch &gl, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL((fwd_kernel<NF, NZ, 3, false, false, false, kFwdStft>), dim3(grid),
+                       dim3(Geo<NF>::NT), 0, s, gl);
+    return hipGetLastError();
+}
+
+template <int NF>
+hipError_t launch_stft_t(int L, const GroupLaunch &gl, int grid, hipStream_t s)
+{
+    switch (nz_rows<NF>(L)) {
+    case 4: return launch_stft_nz<NF, 4>(gl, grid, s);
+    case 8: return launch_stft_nz<NF, 8>(gl, grid, s);
+    default: return launch_stft_nz<NF, 16>(gl, grid, s);
+    }
+}
+
 template <int NF>
 hipError_t launch_maxonly_t(int L, const GroupLaunch &gl, int grid, hipStream_t s)
 {
@@ -1981,6 +2174,26 @@ hipError_t launch_max_prepass(int nfft, int L, const GroupLaunch &g, int grid, h
     if (g.item_stop <= g.item_begin || grid <= 0)
         return hipSuccess;
     SST_DISPATCH_NF(nfft, return launch_maxonly_t<NFv>(L, g, grid, s))
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_stft(int nfft, int L, const GroupLaunch &g, int grid, hipStream_t s)
+{
+    if (g.item_stop <= g.item_begin || grid <= 0)
+        return hipSuccess;
+    SST_DISPATCH_NF(nfft, return launch_stft_t<NFv>(L, g, grid, s))
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_synthesis(int nfft, const SynArgs &a, hipStream_t s)
+{
+    const int64_t tiles = (a.n + kSynTile - 1) / kSynTile;
+    if (tiles <= 0)
+        return hipSuccess;
+    SST_DISPATCH_NF(nfft, {
+        hipLaunchKernelGGL(syn_kernel<NFv>, dim3((unsigned)tiles), dim3(Geo<NFv>::NT), 0, s, a);
+        return hipGetLastError();
+    })
     return hipErrorInvalidValue;
 }
 
