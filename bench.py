@@ -326,6 +326,53 @@ def run_c5(args):
     print(json.dumps(out), flush=True)
 
 
+def measure_extras(plan, xg, T, n, stream, steps):
+    """The transform's other outputs on the same resident signal, each timed with
+    HIP events over `steps` calls (outside the step): the STFT product, its
+    synthesis (Eqs. 10-11), the compressed |T| rows, and the Renyi entropy of T.
+    GB/s counts the algorithmic bytes (inputs read once, outputs written once)."""
+    import torch
+    import paper_2003_07065_amd as sst
+
+    def timed(fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        fn()
+        e0.record(stream)
+        for _ in range(steps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    res = {}
+    nfr, nsrc, ndst = plan.n_frames, plan.n_src, plan.n_dst
+    S = torch.empty((nfr, nsrc), dtype=torch.complex64, device=xg.device)
+    ms = timed(lambda: plan.stft(xg, S))
+    b = 4 * n + 8 * nfr * nsrc
+    res["stft_product"] = {"ms": round(ms, 4), "GB_per_s": round(b / ms / 1e6, 1),
+                           "hbm_frac": round(b / ms / 1e6 / HBM_PEAK_GBS, 4)}
+    xh = torch.empty(n, dtype=torch.float32, device=xg.device)
+    ms = timed(lambda: plan.stft_inverse(S, xh))
+    b = 8 * nfr * nsrc + 4 * n
+    res["stft_synthesis"] = {"ms": round(ms, 4), "GB_per_s": round(b / ms / 1e6, 1),
+                             "Msamples_per_s": round(n / ms / 1e3, 1)}
+    del S, xh
+    for fmt, bpb in (("mag_f32", 4), ("mag_f16", 2)):
+        dt = torch.float32 if fmt == "mag_f32" else torch.float16
+        Tm = torch.as_strided(T.view(dt), (nfr, ndst), (ndst, 1))   # aliases T's memory
+        ms = timed(lambda: plan.forward(xg, Tm, out=fmt))
+        b = 4 * n + bpb * nfr * ndst
+        res["forward_" + fmt] = {"ms_whole_call": round(ms, 4), "GB_per_s": round(b / ms / 1e6, 1),
+                                 "Msamples_per_s": round(n / ms / 1e3, 1)}
+    plan.forward(xg, T)   # T holds the complex rows again
+    ms = timed(lambda: sst.renyi(T, 3))
+    b = 8 * nfr * ndst
+    r = float(sst.renyi(T, 3)[2].cpu())
+    res["renyi_T"] = {"ms": round(ms, 4), "GB_per_s": round(b / ms / 1e6, 1),
+                      "hbm_frac": round(b / ms / 1e6 / HBM_PEAK_GBS, 4), "bits": round(r, 4)}
+    return res
+
+
 def run_single(args):
     """One long channel (c3 default, c2): a step is the whole hot path over the
     resident signal -- threshold and fused forward (one sst_forward call),
@@ -495,6 +542,8 @@ def run_single(args):
     }
     if calib:
         out["calibration"] = calib
+    if not args.no_extras:
+        out["extras"] = measure_extras(plan, xg, T, w.n, stream, args.steps)
     if not args.no_cpu_baseline:
         del T
         torch.cuda.empty_cache()
@@ -594,6 +643,8 @@ def main():
     ap.add_argument("--n", type=int, default=0,
                     help="signal length (default: the workload's, 2^26 for c3, 2^20 for c2)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip timing the STFT product / synthesis, |T| rows and Renyi entropy")
     ap.add_argument("--no-tune", action="store_true",
                     help="use the library's default launch choices instead of autotuning")
     ap.add_argument("--cpu-sample", type=int, default=0,

@@ -95,7 +95,9 @@ typedef int32_t sst_status;
  *   thr_mode     SST_THR_ABS or SST_THR_REL_MAX
  *   thr          gamma (ABS, >= 0) or rho (REL_MAX, >= 0)
  *   precision    SST_PREC_FP32_FFT, or a DFT-as-GEMM tier (SST_PREC_GEMM_BF16,
- *                SST_PREC_GEMM_F16X3) for 512 <= nfft <= 2048 and hop a multiple of 8;
+ *                SST_PREC_GEMM_F16X3) for hop a multiple of 8 and a DFT-matrix table
+ *                (4 n_src rows x L taps, 2 bytes each) of at most 64 MiB -- narrow
+ *                bands, where 4 n_src L products per frame undercut the FFT;
  *                the threshold pre-pass stays FP32 FFT; the GEMM tiers are not
  *                supported by the batched calls
  *   flags        reserved, 0

@@ -47,6 +47,7 @@ sst_status hip_fail(hipError_t e, const char *what)
 
 constexpr double kTwoPi = 6.283185307179586476925286766559;
 constexpr size_t kAlign = 256;
+constexpr size_t kGemmTableMax = size_t(64) << 20;   // bytes of one part of the GEMM A table
 // The speculative forward starts from the maximum over every k-th item,
 // k = max(kSeedStep, items / workgroups): one round of the grid at most.
 constexpr int kSeedStep = 32;
@@ -148,8 +149,8 @@ sst_status validate(const sst_params *p)
     if (p->precision != SST_PREC_FP32_FFT && p->precision != SST_PREC_GEMM_BF16 &&
         p->precision != SST_PREC_GEMM_F16X3)
         return fail(SST_E_ARG, "unknown precision");
-    if (p->precision != SST_PREC_FP32_FFT && (p->nfft > 2048 || (p->hop % 8) != 0))
-        return fail(SST_E_UNSUPPORTED, "the GEMM tiers need nfft <= 2048 and hop a multiple of 8");
+    if (p->precision != SST_PREC_FP32_FFT && (p->hop % 8) != 0)
+        return fail(SST_E_UNSUPPORTED, "the GEMM tiers need hop a multiple of 8");
     if (p->flags != 0)
         return fail(SST_E_ARG, "params.flags must be 0");
     return SST_OK;
@@ -512,6 +513,14 @@ sst_status sst_plan(const sst_params *params, sst_plan_t *out)
     if (gemm) {
         pl->row_tiles = (4 * pl->n_src + 31) / 32;
         pl->ksteps = (L + 15) / 16;
+        // the DFT-matrix fragments (4 n_src rows x L taps) stay a small table:
+        // the tiers are for narrow bands, where they cost 4 n_src L products
+        // per frame against the FFT's N_f log N_f
+        if ((size_t)pl->row_tiles * pl->ksteps * 64 * 16 > kGemmTableMax) {
+            delete pl;
+            return fail(SST_E_UNSUPPORTED, "the GEMM tiers need a DFT-matrix table of at most 64 MiB "
+                                           "(4 n_src x L taps): narrow the band or use the FFT tier");
+        }
         for (int ft : {64, 32}) {
             const int slab = ((ft - 1) * p.hop + 16 * pl->ksteps + 7) / 8 * 8;
             if (sst::gemm_lds_bytes(p.precision, ft, pl->n_dst, slab, L) <= 80 * 1024) {
@@ -1132,7 +1141,7 @@ sst_status sst_autotune(sst_plan_t pl, const float *x, float *T, const int32_t *
         e = hipEventCreate(&ev[1]);
     if (e != hipSuccess) {
         if (ev[0])
-            hipEventDestroy(ev[0]);
+            (void)hipEventDestroy(ev[0]);
         return hip_fail(e, "hipEventCreate");
     }
     sst_status st = SST_OK;
@@ -1200,8 +1209,8 @@ sst_status sst_autotune(sst_plan_t pl, const float *x, float *T, const int32_t *
             }
         }
     }
-    hipEventDestroy(ev[0]);
-    hipEventDestroy(ev[1]);
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
     const sst_status st_apply = apply_tuning(pl, st == SST_OK ? chosen : cur);
     if (st != SST_OK)
         return st;

@@ -219,6 +219,12 @@ struct Geo {
 template <int R>
 constexpr int log2i() { return R <= 1 ? 0 : 1 + log2i<R / 2>(); }
 
+// A compile-time integer passed as a value (selects a specialised lambda body).
+template <int V>
+struct IntC {
+    static constexpr int value = V;
+};
+
 // One Stockham pass of radix R and stride NS over the F frames in LDS.  Every
 // butterfly of a thread has the same twiddle index k = (j mod N_f/R) mod NS =
 // tid mod NS (NS divides both N_f/R and the thread count), so the caller
@@ -967,61 +973,72 @@ __global__ __launch_bounds__(Geo<NF>::NT, DEBUG ? 2 : ((NF == 8192 || (NF == 409
             const __amdgpu_buffer_rsrc_t rs =
                 __builtin_amdgcn_make_buffer_rsrc(trow + ((int64_t)c0 << osh), (short)0, cn << osh,
                                                   kBufferWord3);
-            // bins are read in groups of SG: one LDS round trip per group
+            // bins are read in groups of SG: one LDS round trip per group.  The
+            // row format is uniform per call: the loop is specialised for each
+            // (complex rows, or compressed |T| rows as float or half).
             constexpr int SG = 6;
+            auto store_rows = [&](auto fmt) {
+                constexpr int OSH = decltype(fmt)::value;   // log2 bytes per bin
 #pragma unroll
-            for (int g0 = 0; g0 < NST; g0 += SG) {
-                __builtin_amdgcn_sched_barrier(0);
-                if (CHUNKED && g0 >= nst)
-                    break;
-                unsigned long long hv[SG];
+                for (int g0 = 0; g0 < NST; g0 += SG) {
+                    __builtin_amdgcn_sched_barrier(0);
+                    if (CHUNKED && g0 >= nst)
+                        break;
+                    unsigned long long hv[SG];
 #pragma unroll
-                for (int i = 0; i < SG; ++i)
-                    if (g0 + i < NST && (!CHUNKED || g0 + i < nst))
-                        hv[i] = reinterpret_cast<const unsigned long long *>(hq)[threadIdx.x + (g0 + i) * NT];
+                    for (int i = 0; i < SG; ++i)
+                        if (g0 + i < NST && (!CHUNKED || g0 + i < nst))
+                            hv[i] = reinterpret_cast<const unsigned long long *>(hq)[threadIdx.x + (g0 + i) * NT];
 #pragma unroll
-                for (int i = 0; i < SG; ++i) {
-                    if (g0 + i >= NST || (CHUNKED && g0 + i >= nst))
-                        continue;
-                    const int e = threadIdx.x + (g0 + i) * NT;
-                    float isc = 1.0f / scf[0];   // exact: a power of two
-                    if constexpr (F > 1) {
-                        int f = (int)(((float)(c0 + e) + 0.5f) * inv_ndst);
-                        f = f < nvalid ? f : nvalid - 1;
-                        float sc = scf[0];
+                    for (int i = 0; i < SG; ++i) {
+                        if (g0 + i >= NST || (CHUNKED && g0 + i >= nst))
+                            continue;
+                        const int e = threadIdx.x + (g0 + i) * NT;
+                        float isc = 1.0f / scf[0];   // exact: a power of two
+                        if constexpr (F > 1) {
+                            int f = (int)(((float)(c0 + e) + 0.5f) * inv_ndst);
+                            f = f < nvalid ? f : nvalid - 1;
+                            float sc = scf[0];
 #pragma unroll
-                        for (int ff = 1; ff < F; ++ff)
-                            sc = ff == f ? scf[ff] : sc;
-                        isc = 1.0f / sc;
-                    }
-                    const int re = (int)(unsigned)hv[i];
-                    const int im = (int)(unsigned)(hv[i] >> 32);
-                    const v2 v = mk((float)re * isc, (float)im * isc);
-                    if (osh == 3) {
-                        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), rs,
-                                                              (unsigned)e * 8u, 0, kNonTemporal);
-                    } else {
-                        // compressed rows: |T| (one rounding of the complex value's norm)
-                        const float mg = __builtin_sqrtf(__builtin_fmaf(v.x, v.x, v.y * v.y));
-                        if (osh == 2)
-                            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, mg),
-                                                                  rs, (unsigned)e * 4u, 0,
-                                                                  kNonTemporal);
-                        else
-                            __builtin_amdgcn_raw_buffer_store_b16(
-                                __builtin_bit_cast(unsigned short, (_Float16)mg), rs,
-                                (unsigned)e * 2u, 0, kNonTemporal);
-                    }
-                    if constexpr (DEBUG) {
-                        if (a.colstats && e < cn) {
-                            const int f = (c0 + e) / a.n_dst;
-                            atomicAdd(&colacc[3 * f], (double)v.x);
-                            atomicAdd(&colacc[3 * f + 1], (double)v.y);
-                            atomicAdd(&colacc[3 * f + 2], (double)v.x * v.x + (double)v.y * v.y);
+                            for (int ff = 1; ff < F; ++ff)
+                                sc = ff == f ? scf[ff] : sc;
+                            isc = 1.0f / sc;
+                        }
+                        const int re = (int)(unsigned)hv[i];
+                        const int im = (int)(unsigned)(hv[i] >> 32);
+                        const v2 v = mk((float)re * isc, (float)im * isc);
+                        if constexpr (OSH == 3) {
+                            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), rs,
+                                                                  (unsigned)e * 8u, 0, kNonTemporal);
+                        } else {
+                            // compressed rows: |T| (one rounding of the complex value's norm)
+                            const float mg = __builtin_sqrtf(__builtin_fmaf(v.x, v.x, v.y * v.y));
+                            if constexpr (OSH == 2)
+                                __builtin_amdgcn_raw_buffer_store_b32(
+                                    __builtin_bit_cast(unsigned, mg), rs, (unsigned)e * 4u, 0,
+                                    kNonTemporal);
+                            else
+                                __builtin_amdgcn_raw_buffer_store_b16(
+                                    __builtin_bit_cast(unsigned short, (_Float16)mg), rs,
+                                    (unsigned)e * 2u, 0, kNonTemporal);
+                        }
+                        if constexpr (DEBUG) {
+                            if (a.colstats && e < cn) {
+                                const int f = (c0 + e) / a.n_dst;
+                                atomicAdd(&colacc[3 * f], (double)v.x);
+                                atomicAdd(&colacc[3 * f + 1], (double)v.y);
+                                atomicAdd(&colacc[3 * f + 2], (double)v.x * v.x + (double)v.y * v.y);
+                            }
                         }
                     }
                 }
-            }
+            };
+            if (osh == 3)
+                store_rows(IntC<3>{});
+            else if (osh == 2)
+                store_rows(IntC<2>{});
+            else
+                store_rows(IntC<1>{});
             if (CHUNKED && c0 + CH < EH)
                 __syncthreads();   // store reads done before the next chunk is cleared
         }

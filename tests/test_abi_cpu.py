@@ -222,9 +222,16 @@ def test_gemm_precision_validation():
     bad_hop = sst._params(1 << 15, 25600.0, 511, 64.0, 6, 512, 0.0, 6400.0, 1, "rel", 1e-3, None,
                           None, keep, "f16x3")
     assert L.sst_plan(ctypes.byref(bad_hop), ctypes.byref(h)) == sst.SST_E_UNSUPPORTED
-    big = sst._params(1 << 15, 25600.0, 511, 64.0, 8, 4096, 0.0, 6400.0, 1, "rel", 1e-3, None,
+    # narrow bands at any DFT size (the filter-bank use of the tiers)
+    narrow = sst._params(1 << 15, 25600.0, 1023, 128.0, 8, 4096, 1000.0, 1500.0, 2, "rel", 1e-3,
+                         None, None, keep, "f16x3")
+    assert L.sst_plan(ctypes.byref(narrow), ctypes.byref(h)) == sst.SST_OK
+    L.sst_destroy(h)
+    # a DFT-matrix table beyond 64 MiB (4097 bins x 8191 taps) is refused
+    big = sst._params(1 << 15, 25600.0, 8191, 900.0, 8, 8192, 0.0, 12800.0, 1, "rel", 1e-3, None,
                       None, keep, "bf16")
     assert L.sst_plan(ctypes.byref(big), ctypes.byref(h)) == sst.SST_E_UNSUPPORTED
+    assert b"64 MiB" in L.sst_last_error()
     unknown = sst._params(1 << 15, 25600.0, 511, 64.0, 8, 512, 0.0, 6400.0, 1, "rel", 1e-3, None,
                           None, keep)
     unknown.precision = 7
