@@ -164,7 +164,9 @@ sst_status sst_plan_bind(sst_plan_t plan, void *workspace_dev, size_t bytes, voi
  *   idx      int32 [nframes][n_src]: destination l, -1 below threshold,
  *            -2 destination outside [0, n_dst)
  *   colstats double [nframes][3]: sum_l Re T, sum_l Im T, sum_l |T|^2,
- *            accumulated in FP64 from the FP32 row of T
+ *            accumulated in FP64 from the FP32 row of T by an epilogue of the
+ *            forward kernel (it needs none of the per-coefficient outputs;
+ *            complex rows only, SST_E_UNSUPPORTED with SST_FWD_OUT_MAG_*)
  *   gamma    float [1]: the threshold gamma used by the call
  *   kernel_events  two hipEvent_t handles (created by the caller), recorded
  *            on the call's stream right before and right after the launch of

@@ -30,8 +30,9 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
+    srcs = _build.SRCS + [os.path.join(_build.HERE, "sst_oracle.h")]
     if not os.path.exists(_build.LIB) or (
-            os.path.getmtime(_build.LIB) < os.path.getmtime(_build.SRC)):
+            os.path.getmtime(_build.LIB) < max(os.path.getmtime(p) for p in srcs)):
         _build.build()
     lib = ctypes.CDLL(_build.LIB)
     lib.sso_gaussian_windows.argtypes = [_I, ctypes.c_double, _D, _D]
@@ -59,6 +60,21 @@ def _load():
     lib.sso_renyi.restype = ctypes.c_double
     lib.sso_num_threads.argtypes = []
     lib.sso_num_threads.restype = _I
+    _F = ctypes.POINTER(ctypes.c_float)
+    _V = ctypes.c_void_p
+    lib.sst_oracle_plan.argtypes = [ctypes.POINTER(MirrorParams), ctypes.POINTER(_V)]
+    lib.sst_oracle_plan.restype = ctypes.c_int32
+    lib.sst_oracle_plan_query.argtypes = [_V, ctypes.POINTER(MirrorShape)]
+    lib.sst_oracle_plan_query.restype = ctypes.c_int32
+    lib.sst_oracle_forward.argtypes = [_V, _F, _I64, _I64, _F, _F, _F, _I32, _D, _F]
+    lib.sst_oracle_forward.restype = ctypes.c_int32
+    lib.sst_oracle_ridge.argtypes = [_V, _F, _I64, _I32, ctypes.c_int32, _I32]
+    lib.sst_oracle_ridge.restype = ctypes.c_int32
+    lib.sst_oracle_inverse.argtypes = [_V, _F, _I64, _I64, _I32, ctypes.c_int32, ctypes.c_int32,
+                                       _F, _F, _D, ctypes.c_uint32]
+    lib.sst_oracle_inverse.restype = ctypes.c_int32
+    lib.sst_oracle_destroy.argtypes = [_V]
+    lib.sst_oracle_destroy.restype = None
     _lib = lib
     return lib
 
@@ -240,3 +256,117 @@ def forward(x, cfg, frame0: int = 0, nframes: Optional[int] = None,
     S, Sd = stft(x, g, gd, cfg.hop, cfg.nfft, b.k1, b.k2, frame0, nframes)
     T, idx, frac = reassign(S, Sd, cfg.nfft, b.k1, cfg.subdiv, b.n_dst, gamma)
     return OracleResult(b, gamma, S, Sd, T, idx, frac, g, gd)
+
+
+# ---------------------------------------------------------------------------
+# Mirror of the GPU library's C ABI over host pointers (sst_oracle.h): the same
+# calls, argument order and layouts, float storage, float64 arithmetic.
+# ---------------------------------------------------------------------------
+class MirrorParams(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("n_samples", ctypes.c_int64),
+                ("fs", ctypes.c_double), ("win_len", ctypes.c_int32), ("sigma", ctypes.c_double),
+                ("window", ctypes.POINTER(ctypes.c_double)),
+                ("dwindow", ctypes.POINTER(ctypes.c_double)), ("hop", ctypes.c_int32),
+                ("nfft", ctypes.c_int32), ("f_lo", ctypes.c_double), ("f_hi", ctypes.c_double),
+                ("subdiv", ctypes.c_int32), ("thr_mode", ctypes.c_int32), ("thr", ctypes.c_double),
+                ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class MirrorShape(ctypes.Structure):
+    _fields_ = [("n_samples", ctypes.c_int64), ("n_frames", ctypes.c_int64),
+                ("win_len", ctypes.c_int32), ("hop", ctypes.c_int32), ("nfft", ctypes.c_int32),
+                ("subdiv", ctypes.c_int32), ("k1", ctypes.c_int32), ("k2", ctypes.c_int32),
+                ("n_src", ctypes.c_int32), ("n_dst", ctypes.c_int32),
+                ("workspace_bytes", ctypes.c_size_t), ("t_row_bytes", ctypes.c_size_t)]
+
+
+MIRROR_INV_ACCUMULATE = 1
+MIRROR_INV_EQ15 = 2
+
+
+class MirrorError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        super().__init__(f"{where}: oracle status {status}")
+        self.status = status
+
+
+def _fp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)) if a is not None else None
+
+
+class MirrorPlan:
+    """A plan of the oracle's mirror ABI; float32 numpy arrays in and out."""
+
+    def __init__(self, n_samples: int, cfg):
+        self._lib = _load()
+        p = MirrorParams(ctypes.sizeof(MirrorParams), int(n_samples), float(cfg.fs),
+                         int(cfg.win_len), float(cfg.sigma), None, None, int(cfg.hop),
+                         int(cfg.nfft), float(cfg.f_lo), float(cfg.f_hi), int(cfg.subdiv),
+                         0 if cfg.thr_mode == "abs" else 1, float(cfg.thr), 0, 0)
+        h = ctypes.c_void_p()
+        rc = self._lib.sst_oracle_plan(ctypes.byref(p), ctypes.byref(h))
+        if rc != 0:
+            raise MirrorError(rc, "sst_oracle_plan")
+        self._h = h
+        sh = MirrorShape()
+        self._lib.sst_oracle_plan_query(h, ctypes.byref(sh))
+        self.shape = sh
+        self.n_frames, self.n_src, self.n_dst = sh.n_frames, sh.n_src, sh.n_dst
+        self.k1, self.k2 = sh.k1, sh.k2
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            self._lib.sst_oracle_destroy(h)
+            self._h = None
+
+    def forward(self, x, frame0: int = 0, nframes: Optional[int] = None, want_aux: bool = False):
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        nframes = self.n_frames - frame0 if nframes is None else nframes
+        T = np.empty((nframes, self.n_dst), dtype=np.complex64)
+        aux = {}
+        S = Sd = idx = cs = None
+        if want_aux:
+            S = np.empty((nframes, self.n_src), dtype=np.complex64)
+            Sd = np.empty_like(S)
+            idx = np.empty((nframes, self.n_src), dtype=np.int32)
+            cs = np.empty((nframes, 3), dtype=np.float64)
+        gam = np.zeros(1, dtype=np.float32)
+        rc = self._lib.sst_oracle_forward(
+            self._h, _fp(x), int(frame0), int(nframes), _fp(T.view(np.float32)),
+            _fp(S.view(np.float32)) if S is not None else None,
+            _fp(Sd.view(np.float32)) if Sd is not None else None,
+            _ip(idx) if idx is not None else None, _dp(cs) if cs is not None else None, _fp(gam))
+        if rc != 0:
+            raise MirrorError(rc, "sst_oracle_forward")
+        aux.update(gamma=float(gam[0]), S=S, Sd=Sd, idx=idx, colstats=cs)
+        return T, aux
+
+    def ridge(self, T, bands):
+        T = np.ascontiguousarray(T, dtype=np.complex64)
+        b = np.ascontiguousarray(np.asarray(bands, dtype=np.int32).ravel())
+        nq = b.shape[0] // 2
+        out = np.empty((nq, T.shape[0]), dtype=np.int32)
+        rc = self._lib.sst_oracle_ridge(self._h, _fp(T.view(np.float32)), T.shape[0], _ip(b), nq,
+                                        _ip(out))
+        if rc != 0:
+            raise MirrorError(rc, "sst_oracle_ridge")
+        return out
+
+    def inverse(self, T, ridge, hw: int, frame0: int = 0, xhat=None, xref=None,
+                flags: int = 0):
+        T = np.ascontiguousarray(T, dtype=np.complex64)
+        r = np.ascontiguousarray(np.asarray(ridge, dtype=np.int32))
+        if r.ndim == 1:
+            r = r[None, :]
+        nq = r.shape[0]
+        if xhat is None:
+            xhat = np.zeros((nq, self.shape.n_samples), dtype=np.float32)
+        err = np.empty((nq, 2), dtype=np.float64) if xref is not None else None
+        xr = np.ascontiguousarray(xref, dtype=np.float32) if xref is not None else None
+        rc = self._lib.sst_oracle_inverse(self._h, _fp(T.view(np.float32)), int(frame0),
+                                          T.shape[0], _ip(r), nq, int(hw), _fp(xhat), _fp(xr),
+                                          _dp(err) if err is not None else None, int(flags))
+        if rc != 0:
+            raise MirrorError(rc, "sst_oracle_inverse")
+        return xhat, err

@@ -10,12 +10,13 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "sst_oracle.c")
+SRCS = [SRC, os.path.join(HERE, "sst_oracle_abi.c")]
 LIB = os.path.join(HERE, "libsst_oracle.so")
 
 
 def build(verbose: bool = False) -> str:
     cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fopenmp", "-fPIC", "-shared",
-           "-Wall", "-Wextra", SRC, "-o", LIB + ".tmp", "-lm"]
+           "-Wall", "-Wextra"] + SRCS + ["-o", LIB + ".tmp", "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -718,6 +718,8 @@ static sst_status forward_impl(sst_plan_s *pl, Bound &bd, const float *x, int64_
     const int out_fmt = (flags & SST_FWD_OUT_MAG_F32) ? 1 : ((flags & SST_FWD_OUT_MAG_F16) ? 2 : 0);
     if (out_fmt && pl->gemm_ft)
         return fail(SST_E_UNSUPPORTED, "compressed outputs are produced by the FP32 FFT tier");
+    if (out_fmt && aux && aux->colstats)
+        return fail(SST_E_UNSUPPORTED, "colstats are summed from complex rows, not |T| rows");
     if ((flags & SST_FWD_REUSE_GAMMA) && !bd.gamma_valid)
         return fail(SST_E_STATE, "SST_FWD_REUSE_GAMMA before any thresholding forward call on "
                                  "this binding");
@@ -729,7 +731,11 @@ static sst_status forward_impl(sst_plan_s *pl, Bound &bd, const float *x, int64_
     const bool threshold = !(flags & SST_FWD_REUSE_GAMMA);
     const bool rel = pl->p.thr_mode == SST_THR_REL_MAX;
     const bool fft = !pl->gemm_ft;
-    const bool debug = aux && (aux->S || aux->Sd || aux->idx || aux->colstats);
+    // per-coefficient outputs take the debug variant; the per-frame sums
+    // (colstats) are an epilogue of the production kernel
+    const bool debug = aux && (aux->S || aux->Sd || aux->idx);
+    const int kind = debug ? sst::kFwdKindDebug
+                           : ((aux && aux->colstats) ? sst::kFwdKindStats : sst::kFwdKindPlain);
     // A call over the whole signal that needs gamma takes the speculative
     // forward: threshold at a lower bound of gamma, then redo the items whose
     // decisions the final gamma changes.
@@ -836,7 +842,7 @@ static sst_status forward_impl(sst_plan_s *pl, Bound &bd, const float *x, int64_
     if (!spec) {
         e = record_event(aux, 0, s);
         if (e == hipSuccess)
-            e = sst::launch_forward(NF, pl->p.win_len, pl->n_src, pl->n_dst, debug, g, grid, s);
+            e = sst::launch_forward(NF, pl->p.win_len, pl->n_src, pl->n_dst, kind, g, grid, s);
         if (e == hipSuccess)
             e = record_event(aux, 1, s);
         if (e != hipSuccess)
@@ -847,7 +853,7 @@ static sst_status forward_impl(sst_plan_s *pl, Bound &bd, const float *x, int64_
     g.smin = reinterpret_cast<float *>(bd.ws + pl->off_smin);
     e = record_event(aux, 0, s);
     if (e == hipSuccess)
-        e = sst::launch_forward(NF, pl->p.win_len, pl->n_src, pl->n_dst, false, g, grid, s);
+        e = sst::launch_forward(NF, pl->p.win_len, pl->n_src, pl->n_dst, kind, g, grid, s);
     if (e == hipSuccess)
         e = record_event(aux, 1, s);
     g.spec = 0;
@@ -859,7 +865,7 @@ static sst_status forward_impl(sst_plan_s *pl, Bound &bd, const float *x, int64_
         bd.gamma_valid = true;
     g.smin = nullptr;
     if (e == hipSuccess)
-        e = sst::launch_forward(NF, pl->p.win_len, pl->n_src, pl->n_dst, false, g, grid, s);
+        e = sst::launch_forward(NF, pl->p.win_len, pl->n_src, pl->n_dst, kind, g, grid, s);
     if (e != hipSuccess)
         return hip_fail(e, "speculative forward launch");
     if (aux && aux->gamma) {
@@ -1553,7 +1559,8 @@ sst_status sst_batch_forward(sst_batch_t b, int32_t c_begin, int32_t c_end, uint
         }
         g.spec = spec ? 1 : 0;
         g.smin = spec ? reinterpret_cast<float *>(b->ws + gr.off_smin) : nullptr;
-        e = sst::launch_forward(gr.nfft, gr.max_L, gr.max_n_src, gr.max_n_dst, false, g, grid, s);
+        e = sst::launch_forward(gr.nfft, gr.max_L, gr.max_n_src, gr.max_n_dst, sst::kFwdKindPlain,
+                                    g, grid, s);
         g.spec = 0;
         if (spec) {
             g.list = list;
@@ -1562,7 +1569,8 @@ sst_status sst_batch_forward(sst_batch_t b, int32_t c_begin, int32_t c_end, uint
                 e = sst::launch_spec_list(g, s);
             g.smin = nullptr;
             if (e == hipSuccess)
-                e = sst::launch_forward(gr.nfft, gr.max_L, gr.max_n_src, gr.max_n_dst, false, g,
+                e = sst::launch_forward(gr.nfft, gr.max_L, gr.max_n_src, gr.max_n_dst,
+                                        sst::kFwdKindPlain, g,
                                         grid, s);
         }
         if (e != hipSuccess)

@@ -201,9 +201,13 @@ hipError_t launch_gamma(const GroupLaunch &g, hipStream_t s);
 // and appends to g.list the items whose least kept |S|^2 does not exceed the
 // final gamma^2.
 hipError_t launch_spec_list(const GroupLaunch &g, hipStream_t s);
-// Forward: `debug` selects the variant that writes S, S', idx and colstats;
+// Forward variants: production; debug (writes S, S', idx, colstats); stats
+// (production arithmetic with the colstats epilogue, single channel).
+constexpr int kFwdKindPlain = 0;
+constexpr int kFwdKindDebug = 1;
+constexpr int kFwdKindStats = 2;
 // max_n_src / max_n_dst / max_L bound the launch's channels.
-hipError_t launch_forward(int nfft, int max_L, int max_n_src, int max_n_dst, bool debug,
+hipError_t launch_forward(int nfft, int max_L, int max_n_src, int max_n_dst, int kind,
                           const GroupLaunch &g, int grid, hipStream_t s);
 // DFT-as-GEMM forward (FT frames per tile: 32 or 64).
 hipError_t launch_gemm_forward(int prec, int ft, bool debug, const GemmArgs &a, int grid,

@@ -584,10 +584,12 @@ constexpr int kFwdMaxOnly = 1;   // threshold pre-pass on the forward's arithmet
 constexpr int kFwdFixup = 2;     // the forward over the items of a fix-up list
 constexpr int kFwdStft = 3;      // the STFT product only: S (and S') rows of the items
 
-template <int NF, int NZ, int R, bool DEBUG, bool CHUNKED, bool MULTI, int MODE = kFwdPlain>
+template <int NF, int NZ, int R, bool DEBUG, bool CHUNKED, bool MULTI, int MODE = kFwdPlain,
+          bool STATS = false>
 // Waves per SIMD: 4 for N_f = 8192 and for N_f = 4096 with at most 8 tap rows
 // (two 8-wave or four 4-wave workgroups fill a CU's LDS), 3 otherwise.  MULTI: the launch may hold several channels (else
-// exactly one).
+// exactly one).  STATS (and DEBUG): the per-frame FP64 sums of the stored rows
+// (colstats) as an epilogue of the store phase.
 __global__ __launch_bounds__(Geo<NF>::NT, DEBUG ? 2 : ((NF == 8192 || (NF == 4096 && NZ < 16)) ? 4 : 3)) void fwd_kernel(GroupLaunch g)
 {
     // kFwdMaxOnly: the threshold pre-pass on the forward's own arithmetic --
@@ -596,6 +598,7 @@ __global__ __launch_bounds__(Geo<NF>::NT, DEBUG ? 2 : ((NF == 8192 || (NF == 409
     // signal.  kFwdFixup: the items of g.list only.
     constexpr bool MAXONLY = MODE == kFwdMaxOnly;
     constexpr bool listed = MODE == kFwdFixup;
+    constexpr bool COLS = DEBUG || STATS;   // the colstats epilogue is compiled in
     if (listed && (int64_t)blockIdx.x >= (int64_t)*g.list_n)
         return;   // no entry for this workgroup (the usual case: an empty list)
     using G = Geo<NF>;
@@ -608,7 +611,7 @@ __global__ __launch_bounds__(Geo<NF>::NT, DEBUG ? 2 : ((NF == 8192 || (NF == 409
     __shared__ v2 lds[G::LDS];
     __shared__ float bpart[NT / 64][F];   // per-wave partial bounds, summed in fixed order
     __shared__ float spart[NT / 64][2];   // per-wave max |S|^2 and least kept |S|^2
-    __shared__ double colacc[DEBUG ? 3 * F : 1];
+    __shared__ double colacc[COLS ? 3 * F : 1];   // per-frame FP64 sums (colstats)
     __shared__ v2 twl[Twiddles<NF>::TW];
     __shared__ v2 clo[64], chi[NHI];   // centre-phase tables (Eq. 9)
     int *hq = reinterpret_cast<int *>(lds);   // bin b: hq[2b] = re, hq[2b + 1] = im
@@ -658,7 +661,7 @@ __global__ __launch_bounds__(Geo<NF>::NT, DEBUG ? 2 : ((NF == 8192 || (NF == 409
         }
     };
 
-    if (DEBUG && threadIdx.x < 3 * F)
+    if (COLS && threadIdx.x < 3 * F)
         colacc[threadIdx.x] = 0.0;
     // Items of this workgroup: every gridDim.x-th entry of the fix-up list, or
     // of item_begin, item_begin + step, ...; item_stop ends the sequence.
@@ -937,6 +940,35 @@ __global__ __launch_bounds__(Geo<NF>::NT, DEBUG ? 2 : ((NF == 8192 || (NF == 409
         // Rows longer than the buffer go in chunks of equal size, a multiple of
         // NT (at most HB), so that no pass clears or stores bins past the row
         // beyond the last partial round: nst rounds of NT bins per chunk.
+        // per-frame sums of the stored row (only when the call asks for them)
+        double cre = 0.0, cim = 0.0, ce2 = 0.0;
+        int cf = 0;   // frame of the thread's running sums
+        auto flush_col = [&]() {
+            if constexpr (!COLS) {
+                return;
+            } else if constexpr (F == 1) {
+                // called where the whole workgroup is: one atomic per wave
+#pragma unroll
+                for (int o = 32; o >= 1; o >>= 1) {
+                    cre += __shfl_xor(cre, o, 64);
+                    cim += __shfl_xor(cim, o, 64);
+                    ce2 += __shfl_xor(ce2, o, 64);
+                }
+                if ((threadIdx.x & 63) == 0) {
+                    atomicAdd(&colacc[0], cre);
+                    atomicAdd(&colacc[1], cim);
+                    atomicAdd(&colacc[2], ce2);
+                }
+                cre = cim = ce2 = 0.0;
+            } else {
+                if (cre != 0.0 || cim != 0.0 || ce2 != 0.0) {
+                    atomicAdd(&colacc[3 * cf], cre);
+                    atomicAdd(&colacc[3 * cf + 1], cim);
+                    atomicAdd(&colacc[3 * cf + 2], ce2);
+                }
+                cre = cim = ce2 = 0.0;
+            }
+        };
         int CH = HB;
         if constexpr (CHUNKED) {
             const int nch = (EH + HB - 1) / HB;
@@ -1022,14 +1054,6 @@ __global__ __launch_bounds__(Geo<NF>::NT, DEBUG ? 2 : ((NF == 8192 || (NF == 409
                                     __builtin_bit_cast(unsigned short, (_Float16)mg), rs,
                                     (unsigned)e * 2u, 0, kNonTemporal);
                         }
-                        if constexpr (DEBUG) {
-                            if (a.colstats && e < cn) {
-                                const int f = (c0 + e) / a.n_dst;
-                                atomicAdd(&colacc[3 * f], (double)v.x);
-                                atomicAdd(&colacc[3 * f + 1], (double)v.y);
-                                atomicAdd(&colacc[3 * f + 2], (double)v.x * v.x + (double)v.y * v.y);
-                            }
-                        }
                     }
                 }
             };
@@ -1039,17 +1063,48 @@ __global__ __launch_bounds__(Geo<NF>::NT, DEBUG ? 2 : ((NF == 8192 || (NF == 409
                 store_rows(IntC<2>{});
             else
                 store_rows(IntC<1>{});
+            if (COLS && a.colstats) {
+                // Per-frame sums and energy of the stored FP32 row (a uniform
+                // branch: calls that ask for them), in FP64, from the same
+                // histogram values and scales as the stores above.  A
+                // thread's frame index only grows over its bins, so its sums
+                // go to that frame's LDS slot when the frame changes.
+                for (int r = 0; r < (CHUNKED ? nst : NST); ++r) {
+                    const int e = threadIdx.x + r * NT;
+                    if (e >= cn)
+                        break;
+                    const unsigned long long h = reinterpret_cast<const unsigned long long *>(hq)[e];
+                    int f = 0;
+                    float sc = scf[0];
+                    if constexpr (F > 1) {
+                        f = (int)(((float)(c0 + e) + 0.5f) * inv_ndst);
+                        f = f < nvalid ? f : nvalid - 1;
+#pragma unroll
+                        for (int ff = 1; ff < F; ++ff)
+                            sc = ff == f ? scf[ff] : sc;
+                        if (f != cf) {
+                            flush_col();
+                            cf = f;
+                        }
+                    }
+                    const float isc = 1.0f / sc;
+                    const double dx = (double)((float)(int)(unsigned)h * isc);
+                    const double dy = (double)((float)(int)(unsigned)(h >> 32) * isc);
+                    cre += dx;
+                    cim += dy;
+                    ce2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, ce2));
+                }
+            }
             if (CHUNKED && c0 + CH < EH)
                 __syncthreads();   // store reads done before the next chunk is cleared
         }
-        if constexpr (DEBUG) {
-            if (a.colstats) {
-                __syncthreads();
-                if ((int)threadIdx.x < 3 * nvalid)
-                    a.colstats[m0 * 3 + threadIdx.x] = colacc[threadIdx.x];
-                if (threadIdx.x < 3 * F)
-                    colacc[threadIdx.x] = 0.0;
-            }
+        if (COLS && a.colstats) {   // uniform: the call asked for per-frame sums
+            flush_col();
+            __syncthreads();
+            if ((int)threadIdx.x < 3 * nvalid)
+                a.colstats[m0 * 3 + threadIdx.x] = colacc[threadIdx.x];
+            if (threadIdx.x < 3 * F)
+                colacc[threadIdx.x] = 0.0;
         }
         a = an;
         new_chan = chg;
@@ -1526,12 +1581,13 @@ __host__ __device__ inline InvLds inv_lds_layout(int max_tab, int max_gtab, int 
 // 0..31 and 32..63) accumulate Z 2^(sc + tg) = sum_m c~[m, d] g[n - mH].
 // Only the frames whose windows reach the wave's samples are visited (the
 // others meet g = 0 in every column of the wave), in steps of 16 from a
-// multiple of 16 (the staged rows are zero past kn).
-template <bool DEC, int KBP>
+// multiple of 16 (the staged rows are zero past kn).  ZERO: the sums start
+// here (the first step's products take a zero accumulator in place of acc).
+template <bool DEC, int KBP, bool ZERO>
 __device__ __forceinline__ void wave_mfma(f32x16 &acc0, f32x16 &acc1, const unsigned short *aph,
                                           const unsigned short *apl, const unsigned *gpk,
                                           int tile_lo, int cg, int wave, int col, int half, int mlo,
-                                          int kb, int kn, int M, int H, int JL, int TR)
+                                          int kb, int kn, int M, int H, int JL, int TR, float invH)
 {
     const int w_lo = tile_lo + 256 * cg + 64 * __builtin_amdgcn_readfirstlane(wave);
     const int wm_lo = w_lo - M > 0 ? (w_lo - M + H - 1) / H : 0;
@@ -1548,11 +1604,25 @@ __device__ __forceinline__ void wave_mfma(f32x16 &acc0, f32x16 &acc1, const unsi
     // samples, so |j| <= M + 63 + 15 H.
     const unsigned *pc0 = gpk, *pc1 = gpk;
     if constexpr (DEC) {
-        const int u0 = j0 + JL, u1 = u0 + 32;
-        pc0 = gpk + (u0 % H) * TR + u0 / H - 7;
-        pc1 = gpk + (u1 % H) * TR + u1 / H - 7;
+        // u0 = q0 H + r0 and u1 = u0 + 32 = q1 H + r1, 0 <= u0 < 2^24: the
+        // float quotient is within one of the exact one, then corrected
+        const int u0 = j0 + JL;
+        int q0 = (int)((float)u0 * invH);
+        int r0 = u0 - q0 * H;
+        q0 += r0 >= H ? 1 : (r0 < 0 ? -1 : 0);
+        r0 = u0 - q0 * H;
+        const int u1 = u0 + 32;
+        int q1 = (int)((float)u1 * invH);
+        int r1 = u1 - q1 * H;
+        q1 += r1 >= H ? 1 : (r1 < 0 ? -1 : 0);
+        r1 = u1 - q1 * H;
+        pc0 = gpk + r0 * TR + q0 - 7;
+        pc1 = gpk + r1 * TR + q1 - 7;
     }
-    for (int k0 = kw0; k0 <= kw1; k0 += 16) {
+    // one step of 16 frames; FRESH: the first step of a fresh sum, whose
+    // products take a zero accumulator operand (no register clearing)
+    auto step = [&](int k0, auto fresh) {
+        constexpr bool FRESH = decltype(fresh)::value != 0;
         const u4v_t a_hi = *reinterpret_cast<const u4v_t *>(aph + k0);
         const u4v_t a_lo = *reinterpret_cast<const u4v_t *>(apl + k0);
         const f16x8v ah = __builtin_bit_cast(f16x8v, a_hi), al = __builtin_bit_cast(f16x8v, a_lo);
@@ -1580,14 +1650,29 @@ __device__ __forceinline__ void wave_mfma(f32x16 &acc0, f32x16 &acc1, const unsi
             }
             const f16x8v fh = __builtin_bit_cast(f16x8v, bh), fl = __builtin_bit_cast(f16x8v, bl);
             f32x16 &acc = c ? acc1 : acc0;
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, fh, acc, 0, 0, 0);
+            if constexpr (FRESH)
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, fh, f32x16{}, 0, 0, 0);
+            else
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, fh, acc, 0, 0, 0);
             acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, fl, acc, 0, 0, 0);
             acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(al, fh, acc, 0, 0, 0);
         }
         j0 -= 16 * H;
         pc0 -= 16;
         pc1 -= 16;
+    };
+    int k0 = kw0;
+    if constexpr (ZERO) {
+        if (k0 > kw1) {   // no frame reaches the wave's samples
+            acc0 = f32x16{};
+            acc1 = f32x16{};
+            return;
+        }
+        step(k0, IntC<1>{});
+        k0 += 16;
     }
+    for (; k0 <= kw1; k0 += 16)
+        step(k0, IntC<0>{});
 }
 
 // ONE: every tile's frames fit one staged block (K <= KB), so the sums start
@@ -1630,6 +1715,7 @@ __global__ __launch_bounds__(256, TF > 1 ? 4 : (ONE ? (DEC ? 6 : 5) : 4)) void i
     const int tile_lo = span_lo + (int)(local - (unsigned)q * tiles) * (kInvTile * TF);
     const int tile_hi = tile_lo + kInvTile * TF - 1 < span_end ? tile_lo + kInvTile * TF - 1 : span_end;
     const int M = a.M, H = a.hop, Gi = a.G;
+    const float invH = 1.0f / (float)H;
     const int frame0 = (int)a.frame0, nfr = (int)a.nframes, nframes_all = (int)a.n_frames;
     const v2 *__restrict__ win = reinterpret_cast<const v2 *>(a.win);
 
@@ -1726,8 +1812,13 @@ __global__ __launch_bounds__(256, TF > 1 ? 4 : (ONE ? (DEC ? 6 : 5) : 4)) void i
             // c~[m, d] of this block in registers: 16 destinations per frame
             float cre[STAGE], cim[STAGE];
             float amax = 0.f;
+            // rounds of 256 coefficients (16 frames) up to the staged rows
+            const int nrd = kn16 / 16;
 #pragma unroll
             for (int i = 0; i < STAGE; ++i) {
+                cre[i] = cim[i] = 0.f;
+                if (i >= nrd)
+                    continue;
                 const int e = tid + 256 * i;
                 const int kk = e >> 4, dd = e & 15;
                 const int k = kb + kk;
@@ -1780,7 +1871,7 @@ __global__ __launch_bounds__(256, TF > 1 ? 4 : (ONE ? (DEC ? 6 : 5) : 4)) void i
             for (int i = 0; i < STAGE; ++i) {
                 const int e = tid + 256 * i;
                 const int kk = e >> 4, dd = e & 15;
-                if (kk < kn16) {
+                if (i < nrd) {   // kk < kn16
                     unsigned h, lw;
                     split_f16(cre[i] * scl, h, lw);
                     ahi[(2 * dd) * KBP + kk] = (unsigned short)h;
@@ -1792,8 +1883,8 @@ __global__ __launch_bounds__(256, TF > 1 ? 4 : (ONE ? (DEC ? 6 : 5) : 4)) void i
             }
             __syncthreads();
             if constexpr (!ONE) {
-                wave_mfma<DEC, KBP>(acc0, acc1, aph, apl, gpk, tile_lo, 0, wave, col, half, mlo,
-                                    kb, kn, M, H, JL, TR);
+                wave_mfma<DEC, KBP, false>(acc0, acc1, aph, apl, gpk, tile_lo, 0, wave, col, half,
+                                           mlo, kb, kn, M, H, JL, TR, invH);
             }
         }
         // rows 8 (i/4) + 4 half + i mod 4 = 2 dd + p: dd = 4 (i/4) + 2 half + (i mod 4) / 2
@@ -1802,10 +1893,8 @@ __global__ __launch_bounds__(256, TF > 1 ? 4 : (ONE ? (DEC ? 6 : 5) : 4)) void i
 #pragma unroll
         for (int cg = 0; cg < TF; ++cg) {
             if constexpr (ONE) {
-                acc0 = f32x16{};
-                acc1 = f32x16{};
-                wave_mfma<DEC, KBP>(acc0, acc1, aph, apl, gpk, tile_lo, cg, wave, col, half, mlo,
-                                    0, K, M, H, JL, TR);
+                wave_mfma<DEC, KBP, true>(acc0, acc1, aph, apl, gpk, tile_lo, cg, wave, col, half,
+                                          mlo, 0, K, M, H, JL, TR, invH);
             }
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
@@ -2013,11 +2102,25 @@ int nz_rows(int L)
 }
 
 template <int NF, int NZ, bool MULTI>
-hipError_t launch_fwd_nzm(int max_n_src, int max_n_dst, bool debug, const GroupLaunch &gl,
+hipError_t launch_fwd_nzm(int max_n_src, int max_n_dst, int kind, const GroupLaunch &gl,
                           int grid, hipStream_t s)
 {
     const dim3 g(grid), b(Geo<NF>::NT);
     const bool chunked = (int64_t)Geo<NF>::F * max_n_dst > Geo<NF>::LDS;
+    const bool debug = kind == kFwdKindDebug;
+    if constexpr (!MULTI) {
+        if (kind == kFwdKindStats) {
+            // the per-frame sums: the general variant (any row length, nine
+            // rounds, same rows bit for bit) with the epilogue compiled in
+            if (gl.list)
+                hipLaunchKernelGGL((fwd_kernel<NF, NZ, 9, false, true, false, kFwdFixup, true>), g,
+                                   b, 0, s, gl);
+            else
+                hipLaunchKernelGGL((fwd_kernel<NF, NZ, 9, false, true, false, kFwdPlain, true>), g,
+                                   b, 0, s, gl);
+            return hipGetLastError();
+        }
+    }
     if (gl.list) {
         // fix-up pass: the general variant (any row length, nine rounds) gives
         // every row bit for bit what the variant chosen below gives
@@ -2043,21 +2146,21 @@ hipError_t launch_fwd_nzm(int max_n_src, int max_n_dst, bool debug, const GroupL
 }
 
 template <int NF, int NZ>
-hipError_t launch_fwd_nz(int max_n_src, int max_n_dst, bool debug, const GroupLaunch &gl,
+hipError_t launch_fwd_nz(int max_n_src, int max_n_dst, int kind, const GroupLaunch &gl,
                          int grid, hipStream_t s)
 {
-    return gl.n_ch > 1 ? launch_fwd_nzm<NF, NZ, true>(max_n_src, max_n_dst, debug, gl, grid, s)
-                       : launch_fwd_nzm<NF, NZ, false>(max_n_src, max_n_dst, debug, gl, grid, s);
+    return gl.n_ch > 1 ? launch_fwd_nzm<NF, NZ, true>(max_n_src, max_n_dst, kind, gl, grid, s)
+                       : launch_fwd_nzm<NF, NZ, false>(max_n_src, max_n_dst, kind, gl, grid, s);
 }
 
 template <int NF>
-hipError_t launch_fwd_t(int max_L, int max_n_src, int max_n_dst, bool debug, const GroupLaunch &gl,
+hipError_t launch_fwd_t(int max_L, int max_n_src, int max_n_dst, int kind, const GroupLaunch &gl,
                         int grid, hipStream_t s)
 {
     switch (nz_rows<NF>(max_L)) {
-    case 4: return launch_fwd_nz<NF, 4>(max_n_src, max_n_dst, debug, gl, grid, s);
-    case 8: return launch_fwd_nz<NF, 8>(max_n_src, max_n_dst, debug, gl, grid, s);
-    default: return launch_fwd_nz<NF, 16>(max_n_src, max_n_dst, debug, gl, grid, s);
+    case 4: return launch_fwd_nz<NF, 4>(max_n_src, max_n_dst, kind, gl, grid, s);
+    case 8: return launch_fwd_nz<NF, 8>(max_n_src, max_n_dst, kind, gl, grid, s);
+    default: return launch_fwd_nz<NF, 16>(max_n_src, max_n_dst, kind, gl, grid, s);
     }
 }
 
@@ -2231,10 +2334,10 @@ hipError_t launch_spec_list(const GroupLaunch &g, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_forward(int nfft, int max_L, int max_n_src, int max_n_dst, bool debug,
+hipError_t launch_forward(int nfft, int max_L, int max_n_src, int max_n_dst, int kind,
                           const GroupLaunch &g, int grid, hipStream_t s)
 {
-    SST_DISPATCH_NF(nfft, return launch_fwd_t<NFv>(max_L, max_n_src, max_n_dst, debug, g, grid, s))
+    SST_DISPATCH_NF(nfft, return launch_fwd_t<NFv>(max_L, max_n_src, max_n_dst, kind, g, grid, s))
     return hipErrorInvalidValue;
 }
 

@@ -13,7 +13,7 @@ hipError_t launch_clear_max(const GroupLaunch &, hipStream_t) { return hipErrorN
 hipError_t launch_max_prepass(int, int, const GroupLaunch &, int, hipStream_t) { return hipErrorNoDevice; }
 hipError_t launch_gamma(const GroupLaunch &, hipStream_t) { return hipErrorNoDevice; }
 hipError_t launch_spec_list(const GroupLaunch &, hipStream_t) { return hipErrorNoDevice; }
-hipError_t launch_forward(int, int, int, int, bool, const GroupLaunch &, int, hipStream_t) { return hipErrorNoDevice; }
+hipError_t launch_forward(int, int, int, int, int, const GroupLaunch &, int, hipStream_t) { return hipErrorNoDevice; }
 hipError_t launch_gemm_forward(int, int, bool, const GemmArgs &, int, hipStream_t) { return hipErrorNoDevice; }
 size_t gemm_lds_bytes(int, int, int, int, int) { return 16384; }   // fits: the plan proceeds
 int gemm_occupancy(int, int, size_t) { return 1; }

@@ -640,3 +640,49 @@ def test_speculative_threshold_fixup(sst):
         e_t = relf(T[f0:f0 + nfr].cpu().numpy(), reconciled_T(o.S, idx_g, plan.n_dst))
         _say(f"  frames {f0}+{nfr}: T(reconciled) relF={e_t:.2e} {rep}")
         assert e_t <= 1e-5 and rep.ok(), (rep, rep.details)
+
+
+STATS_CASES = [c for c in CASES if c[0] in ("c2-shape", "c3-shape", "nf1024-F4", "nf512-F8-nz16")]
+
+
+@pytest.mark.parametrize("name,n,cfg", STATS_CASES, ids=[c[0] for c in STATS_CASES])
+def test_colstats_epilogue_of_the_production_forward(sst, name, n, cfg):
+    """Per-frame FP64 sums (sum Re T, sum Im T, sum |T|^2) asked for without any
+    per-coefficient output: the production arithmetic (speculative threshold
+    and fix-up included) with the sums as an epilogue.  T must equal the plain
+    call's bit for bit; the sums must equal the FP64 sums of the stored rows
+    (to FP64 rounding: the order of a float64 reduction) and those of the debug
+    variant; and a chunked call must give the whole call's rows."""
+    x = _signal(name, n, cfg.fs)
+    plan = sst.Plan.from_config(n, cfg, device="cuda")
+    xg = torch.from_numpy(x).cuda()
+    T0 = plan.forward(xg)
+    col = torch.full((plan.n_frames, 3), float("nan"), dtype=torch.float64, device="cuda")
+    T1 = plan.forward(xg, colstats=col)
+    torch.cuda.synchronize()
+    assert torch.equal(torch.view_as_real(T0), torch.view_as_real(T1))
+    Td = T1.cpu().numpy().astype(np.complex128)
+    c = col.cpu().numpy()
+    ref = np.stack([Td.real.sum(1), Td.imag.sum(1), (np.abs(Td) ** 2).sum(1)], axis=1)
+    scale = np.abs(Td).sum(1)
+    _say(f"[colstats] {name}: frames {plan.n_frames}, max |d sum| / sum|T| "
+         f"{np.max(np.abs(c[:, :2] - ref[:, :2]) / (scale[:, None] + 1e-300)):.2e}")
+    assert np.all(np.isfinite(c))
+    assert np.all(np.abs(c[:, :2] - ref[:, :2]) <= 1e-12 * (scale[:, None] + 1e-300))
+    assert np.allclose(c[:, 2], ref[:, 2], rtol=1e-12, atol=0.0)
+    # the debug variant's sums over a middle chunk
+    f0, nf = plan.n_frames // 3, min(64, plan.n_frames // 3)
+    S = torch.empty((nf, plan.n_src), dtype=torch.complex64, device="cuda")
+    cd = torch.empty((nf, 3), dtype=torch.float64, device="cuda")
+    cp = torch.empty((nf, 3), dtype=torch.float64, device="cuda")
+    Td2 = plan.forward(xg, None, f0, nf, S=S, colstats=cd, reuse_gamma=True)
+    Tp2 = plan.forward(xg, None, f0, nf, colstats=cp, reuse_gamma=True)
+    torch.cuda.synchronize()
+    assert torch.equal(torch.view_as_real(Td2), torch.view_as_real(T0[f0:f0 + nf]))
+    assert torch.equal(torch.view_as_real(Tp2), torch.view_as_real(T0[f0:f0 + nf]))
+    sc = np.concatenate([scale[f0:f0 + nf, None]] * 2 + [ref[f0:f0 + nf, 2:3]], axis=1)
+    for got in (cd.cpu().numpy(), cp.cpu().numpy()):
+        assert np.all(np.abs(got - c[f0:f0 + nf]) <= 1e-12 * (sc + 1e-300))
+    # compressed rows carry no phase: no sums from them
+    with pytest.raises(sst.SSTError):
+        plan.forward(xg, colstats=col, out="mag_f32")

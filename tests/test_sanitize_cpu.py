@@ -4,7 +4,7 @@ The host runtime of the library (sst_host.cpp, with host stand-ins for the
 device launchers) and the float64 oracle (sst_oracle.c) are compiled by a plain
 host compiler with -fsanitize=address,undefined and run through their host
 paths: plans of every size and tier, invalid parameters, batches, the tuning
-cache; the oracle's whole pipeline on a small signal.  Any sanitizer report
+cache; the oracle's whole pipeline and its mirror ABI on a small signal.  Any sanitizer report
 fails the test."""
 import os
 import shutil
@@ -44,7 +44,9 @@ def test_host_runtime_under_sanitizers(tmp_path):
 @pytest.mark.skipif(not os.path.exists(CC), reason="ROCm clang not installed")
 def test_oracle_under_sanitizers(tmp_path):
     exe = str(tmp_path / "oracle_driver")
-    _run([CC, "-std=c11", "-D_GNU_SOURCE", *SAN, os.path.join(ROOT, "oracle", "sst_oracle.c"),
+    _run([CC, "-std=c11", "-D_GNU_SOURCE", *SAN, "-I" + os.path.join(ROOT, "oracle"),
+          os.path.join(ROOT, "oracle", "sst_oracle.c"), os.path.join(ROOT, "oracle", "sst_oracle_abi.c"),
           os.path.join(HERE, "oracle_driver.c"), "-lm", "-o", exe])
     r = _run([exe], env=ENV)
     assert "synthesis max err" in r.stdout
+    assert "mirror ABI ok" in r.stdout
