@@ -243,7 +243,8 @@ def run_c5(args):
     t0 = time.perf_counter()
     xs, w0 = [], None
     for c0 in range(0, nch, 32):
-        chunk = make_c5(n_channels=min(32, nch - c0), n=n, nfft=args.c5_nfft, seed=c0)
+        chunk = make_c5(n_channels=min(32, nch - c0), n=n, nfft=args.c5_nfft, seed=c0,
+                        f_hi=args.c5_band_hi)
         if w0 is None:
             w0 = chunk[0]
         for w in chunk:
@@ -315,7 +316,7 @@ def run_c5(args):
         "data": "synthetic",
         "config": {"workload": f"precision tier: {nch} channels x 2^20 samples at 25.6 kHz, "
                                f"three AM-FM components + noise 10 dB, N_f={args.c5_nfft}, "
-                               f"L=N_f-1, sigma=N_f/8, H=8, band [0, 6.4 kHz], z=1, "
+                               f"L=N_f-1, sigma=N_f/8, H=8, band [0, {args.c5_band_hi:g} Hz], z=1, "
                                "rho=1e-3; STFT+SST forward (threshold pre-pass included)",
                    "generation_s": round(gen_s, 1)},
         "roofline": {"kernel": "gemm_kernel (FP16 hi/lo x3, 32x32x16 MFMA)", "bound": "mfma",
@@ -323,6 +324,75 @@ def run_c5(args):
                      "frac": round(best["mfma_tflops"] / peak, 4), "traffic": None},
         "tiers": res,
     }
+    print(json.dumps(out), flush=True)
+
+
+def run_c5x(args):
+    """Narrow-band crossover of the filter-bank STFT (DFT-as-GEMM) against the
+    FP32 FFT path: c5 channels (2^20 samples, H = 8, L = N_f - 1), bands
+    [0, f_hi] swept at N_f 1024 and 4096.  The GEMM tiers' work grows with
+    n_src L (4 n_src L products per frame), the FFT's with N_f log2 N_f, so the
+    matrix cores win below some band width; each point is the forward call
+    with gamma reused (the threshold pre-pass excluded), HIP events over
+    `steps` passes over the channels."""
+    import torch
+    import paper_2003_07065_amd as sst
+    from workloads import SSTConfig, make_c5
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    n = 1 << 20
+    nch = min(args.c5_channels, 32)
+    xs = [torch.from_numpy(w.x).to(dev) for w in make_c5(n_channels=nch, n=n, nfft=1024)]
+    stream = torch.cuda.current_stream(dev)
+    rows = []
+    for nfft in (1024, 4096):
+        for f_hi in (100.0, 200.0, 400.0, 800.0, 1600.0, 3200.0, 6400.0, 12800.0):
+            cfg = SSTConfig(fs=25600.0, win_len=nfft - 1, sigma=nfft / 8.0, hop=8, nfft=nfft,
+                            f_lo=0.0, f_hi=f_hi, subdiv=1, thr_mode="rel", thr=1e-3, hw=1)
+            row = {"nfft": nfft, "f_hi": f_hi}
+            for prec in ("fp32", "bf16", "f16x3"):
+                try:
+                    plan = sst.Plan.from_config(n, cfg, device=dev, precision=prec)
+                except sst.SSTError as e:
+                    row[prec] = None
+                    row[prec + "_why"] = str(e).split(":")[-1].strip()[:80]
+                    continue
+                row["n_src"] = plan.n_src
+                T = torch.empty((plan.n_frames, plan.n_dst), dtype=torch.complex64, device=dev)
+                for x in xs[:2]:
+                    plan.forward(x, T)
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                for _ in range(args.steps):
+                    for x in xs:
+                        plan.forward(x, T, reuse_gamma=True)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                row[prec] = round(e0.elapsed_time(e1) / args.steps / nch, 4)   # ms per channel
+                del plan, T
+            row["nsrc_L_over_nf_log2nf"] = round(row.get("n_src", 0) * (nfft - 1)
+                                                 / (nfft * math.log2(nfft)), 2)
+            log(f"c5x nfft={nfft} f_hi={f_hi:g}: {row}")
+            rows.append(row)
+    cross = {}
+    for nfft in (1024, 4096):
+        for prec in ("bf16", "f16x3"):
+            wins = [r for r in rows if r["nfft"] == nfft and r.get(prec) and r.get("fp32")
+                    and r[prec] < r["fp32"]]
+            best = max(wins, key=lambda r: r["f_hi"]) if wins else None
+            cross[f"{prec}_nfft{nfft}"] = (
+                {"widest_winning_band_hz": best["f_hi"], "n_src": best["n_src"],
+                 "speedup": round(best["fp32"] / best[prec], 3),
+                 "nsrc_L_over_nf_log2nf": best["nsrc_L_over_nf_log2nf"]} if best else None)
+    out = {"metric": "forward ms per channel vs band width (filter-bank STFT crossover)",
+           "unit": "ms", "n_gpus": 1, "steps": args.steps, "higher_is_better": False,
+           "data": "synthetic",
+           "config": {"workload": f"{nch} c5 channels x 2^20 samples at 25.6 kHz, H=8, "
+                                  "L=N_f-1, sigma=N_f/8, z=1, bands [0, f_hi]; forward with "
+                                  "gamma reused"},
+           "sweep": rows, "crossover": cross}
     print(json.dumps(out), flush=True)
 
 
@@ -631,12 +701,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", choices=["c3", "c2", "c4", "c5", "e1"], default="c3",
+    ap.add_argument("--workload", choices=["c3", "c2", "c4", "c5", "c5x", "e1"], default="c3",
                     help="c3: the long run-up channel, N=2^26 (default); c2: N=2^20; "
-                         "c4: batched uneven channels; c5: precision tiers; e1: the paper's "
-                         "Sec. 3 concentration and reconstruction study")
+                         "c4: batched uneven channels; c5: precision tiers; c5x: narrow-band "
+                         "crossover of the GEMM tiers; e1: the paper's Sec. 3 concentration "
+                         "and reconstruction study")
     ap.add_argument("--c5-channels", type=int, default=512)
     ap.add_argument("--c5-nfft", type=int, default=512, choices=[512, 1024])
+    ap.add_argument("--c5-band-hi", type=float, default=6400.0,
+                    help="c5: upper edge of the band in Hz (1000 for the narrow-band variant)")
     ap.add_argument("--c4-channels", type=int, default=256)
     ap.add_argument("--t-pool-gb", type=float, default=120.0,
                     help="c4: device memory for T; channels are processed in passes that fit")
@@ -654,8 +727,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(sharding is described in DESIGN.md); use --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU: the library has no multi-GPU path; use --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -668,6 +741,8 @@ def main():
         run_c4(args)
     elif args.workload == "c5":
         run_c5(args)
+    elif args.workload == "c5x":
+        run_c5x(args)
     elif args.workload == "e1":
         run_e1(args)
     else:

@@ -375,20 +375,28 @@ void sst_batch_destroy(sst_batch_t batch);
  *   inv_tf         inverse: groups of 256 output samples per workgroup, 1 or 4
  *                  (4 only when the frames 1024 samples meet fit the staged
  *                  block; SST_E_UNSUPPORTED otherwise)
+ *   inv_groups     inverse with inv_tf 4: destination groups of 16 bins staged
+ *                  together, 1 (one at a time), 2 or 4 (groups of the tile's
+ *                  zones together, sharing each window operand read and each
+ *                  sample's phasors; needs the hop-decimated window table and
+ *                  the staged groups within a third (2) or half (4) of the
+ *                  CU's LDS, SST_E_UNSUPPORTED otherwise); 0 = 1
  */
 typedef struct {
     int32_t fwd_wg_per_cu;
     int32_t seed_step;
     int32_t inv_tf;
-    int32_t reserved;
+    int32_t inv_groups;
 } sst_tuning;
 
 /* sst_plan_get_tuning -- the choices in effect (defaults resolved where known:
- * fwd_wg_per_cu after bind, inv_tf always; seed_step 0 = automatic). */
+ * fwd_wg_per_cu after bind, inv_tf and inv_groups always; seed_step 0 =
+ * automatic). */
 sst_status sst_plan_get_tuning(sst_plan_t plan, sst_tuning *out);
 
 /* sst_plan_set_tuning -- set the launch choices (before or after bind).
- * Errors: SST_E_ARG (negative values, reserved != 0), SST_E_UNSUPPORTED. */
+ * Errors: SST_E_ARG (negative values, inv_tf not 0/1/4, inv_groups not
+ * 0/1/2/4), SST_E_UNSUPPORTED. */
 sst_status sst_plan_set_tuning(sst_plan_t plan, const sst_tuning *tuning);
 
 /*

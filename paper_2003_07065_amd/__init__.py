@@ -99,12 +99,12 @@ class Tuning(ctypes.Structure):
         ("fwd_wg_per_cu", ctypes.c_int32),
         ("seed_step", ctypes.c_int32),
         ("inv_tf", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("inv_groups", ctypes.c_int32),
     ]
 
     def as_dict(self):
         return {"fwd_wg_per_cu": self.fwd_wg_per_cu, "seed_step": self.seed_step,
-                "inv_tf": self.inv_tf}
+                "inv_tf": self.inv_tf, "inv_groups": self.inv_groups}
 
 
 class FwdAux(ctypes.Structure):
@@ -482,8 +482,9 @@ class Plan:
         _check(lib().sst_plan_get_tuning(self._h, ctypes.byref(t)), "sst_plan_get_tuning")
         return t.as_dict()
 
-    def set_tuning(self, fwd_wg_per_cu: int = 0, seed_step: int = 0, inv_tf: int = 0):
-        t = Tuning(int(fwd_wg_per_cu), int(seed_step), int(inv_tf), 0)
+    def set_tuning(self, fwd_wg_per_cu: int = 0, seed_step: int = 0, inv_tf: int = 0,
+                   inv_groups: int = 0):
+        t = Tuning(int(fwd_wg_per_cu), int(seed_step), int(inv_tf), int(inv_groups))
         _check(lib().sst_plan_set_tuning(self._h, ctypes.byref(t)), "sst_plan_set_tuning")
 
     def autotune(self, x, T, ridge=None, hw: int = 0, xhat=None, reps: int = 3) -> dict:

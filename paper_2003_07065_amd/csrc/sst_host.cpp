@@ -267,22 +267,59 @@ bool inv_wide_fits(const sst_plan_s *pl)
 {
     return inv_max_k(pl->M, pl->p.hop, sst::kInvWideTF) <= sst::kInvWideKB;
 }
+// Words of the plan's decimated inverse window table (InvDesc::dec_row times the hop).
+int inv_dec_words(const sst_plan_s *pl)
+{
+    const int reach = pl->M + 63 + 16 * pl->p.hop;
+    return pl->p.hop * ((2 * reach) / pl->p.hop + 2);
+}
 
 // max_dec: the largest decimated window table of the list (inv_dec_words);
 // max_L: its longest window; tf: sample groups per workgroup of every channel.
 sst::InvLaunch inv_launch(const sst::InvDesc *dev, int n_ch, int64_t blk_begin, int max_k,
-                          int max_tab, int max_L, int max_dec, int tf)
+                          int max_tab, int max_L, int max_dec, int tf, int groups = 1)
 {
     sst::InvLaunch l{};
     l.ch = dev;
     l.n_ch = n_ch;
     l.tf = tf;
+    l.groups = groups;
     l.blk_begin = blk_begin;
     l.max_k = max_k;
     l.max_tab = max_tab;
     l.dec = max_dec <= sst::kInvDecMax ? 1 : 0;
     l.max_gtab = ((l.dec ? max_dec : max_L + 2) + 3) & ~3;
     return l;
+}
+
+// Wide tiles with a decimated window table may stage 2 or 4 destination
+// groups of the tile's zones at once (a tuning choice, when that fits three or
+// two workgroups per CU); a plan's choice depends on the plan alone, so
+// single-channel and batched calls take the same kernel (and give the same
+// bits).
+bool inv_groups_fit(const sst_plan_s *pl, int tf, int groups)
+{
+    if (tf <= 1 || inv_dec_words(pl) > sst::kInvDecMax)
+        return false;
+    sst::InvLaunch l = inv_launch(nullptr, 1, 0, inv_max_k(pl->M, pl->p.hop, tf),
+                                  pl->n_lo + pl->n_hi, pl->p.win_len, inv_dec_words(pl), tf,
+                                  groups);
+    return sst::inv_lds_bytes(l) <= sst::inv_group_lds_max(groups);
+}
+// The plan's groups staged together: the tuned value, else 1 (the default).
+int inv_groups_of(const sst_plan_s *pl)
+{
+    const int g = pl->tune.inv_groups;
+    return (g > 1 && inv_groups_fit(pl, pl->inv_tf, g)) ? g : 1;
+}
+// Kind of inverse tile of a plan: 0 narrow, 1 wide, 2 / 3 wide with 2 / 4
+// groups staged together.
+int inv_kind_of(const sst_plan_s *pl)
+{
+    if (pl->inv_tf <= 1)
+        return 0;
+    const int g = inv_groups_of(pl);
+    return g == 4 ? 3 : (g == 2 ? 2 : 1);
 }
 
 // Round to BF16, nearest even.
@@ -971,8 +1008,9 @@ sst_status sst_inverse(sst_plan_t pl, const float *T, int64_t frame0, int64_t nf
     if (a.blk_end >= (int64_t(1) << 31))
         return fail(SST_E_UNSUPPORTED, "n_comp * ceil(span / 256) must be below 2^31");
     sst::InvLaunch l = inv_launch(slot, 1, a.blk0, inv_max_k(pl), pl->n_lo + pl->n_hi,
-                                  pl->p.win_len, pl->p.hop * a.dec_row, pl->inv_tf);
-    if (sst::inv_lds_bytes(l) > 64 * 1024)
+                                  pl->p.win_len, pl->p.hop * a.dec_row, pl->inv_tf,
+                                  inv_groups_of(pl));
+    if (sst::inv_lds_bytes(l) > (l.groups > 1 ? sst::inv_group_lds_max(l.groups) : 64 * 1024))
         return fail(SST_E_UNSUPPORTED, "inverse tiles need more than 64 KiB of LDS "
                                        "(window too long for the hop)");
     hipError_t e = sst::launch_put_inv_desc(a, slot, s);
@@ -1004,21 +1042,28 @@ std::string tuning_key(const sst_plan_s *pl)
 
 sst_status apply_tuning(sst_plan_s *pl, const sst_tuning &t)
 {
-    if (t.fwd_wg_per_cu < 0 || t.seed_step < 0 || t.reserved != 0)
-        return fail(SST_E_ARG, "tuning values must be >= 0 and reserved 0");
+    if (t.fwd_wg_per_cu < 0 || t.seed_step < 0)
+        return fail(SST_E_ARG, "tuning values must be >= 0");
     if (t.inv_tf != 0 && t.inv_tf != 1 && t.inv_tf != sst::kInvWideTF)
         return fail(SST_E_ARG, "inv_tf must be 0, 1 or 4");
+    if (t.inv_groups < 0 || t.inv_groups == 3 || t.inv_groups > 4)
+        return fail(SST_E_ARG, "inv_groups must be 0, 1, 2 or 4");
     if (t.inv_tf == sst::kInvWideTF && !inv_wide_fits(pl))
         return fail(SST_E_UNSUPPORTED, "inv_tf 4: the frames 1024 output samples meet exceed "
                                        "the staged block");
+    const int tf = t.inv_tf ? t.inv_tf : (inv_wide_fits(pl) ? sst::kInvWideTF : 1);
+    if (t.inv_groups > 1 && !inv_groups_fit(pl, tf, t.inv_groups))
+        return fail(SST_E_UNSUPPORTED, "inv_groups 2 / 4 need inv_tf 4, the hop-decimated window "
+                                       "table and the staged groups within a third / half of "
+                                       "the CU's LDS");
     pl->tune = t;
-    pl->inv_tf = t.inv_tf ? t.inv_tf : (inv_wide_fits(pl) ? sst::kInvWideTF : 1);
+    pl->inv_tf = tf;
     if (pl->bd.ws)
         apply_grid(pl, pl->bd);
     return SST_OK;
 }
 
-// One cache line: "key": {"fwd_wg_per_cu": a, "seed_step": b, "inv_tf": c}
+// One cache line: "key": {"fwd_wg_per_cu": a, "seed_step": b, "inv_tf": c, "inv_groups": d}
 bool parse_entry(const std::string &line, std::string &key, sst_tuning &t)
 {
     const size_t q0 = line.find('"');
@@ -1039,6 +1084,8 @@ bool parse_entry(const std::string &line, std::string &key, sst_tuning &t)
         v = (int32_t)std::strtol(line.c_str() + colon + 1, nullptr, 10);
         return true;
     };
+    if (!field("inv_groups", t.inv_groups))   // absent from older caches: default
+        t.inv_groups = 0;
     return field("fwd_wg_per_cu", t.fwd_wg_per_cu) && field("seed_step", t.seed_step) &&
            field("inv_tf", t.inv_tf);
 }
@@ -1071,6 +1118,7 @@ sst_status sst_plan_get_tuning(sst_plan_t pl, sst_tuning *out)
     if (pl->bd.ws && pl->bd.cus > 0)
         out->fwd_wg_per_cu = pl->bd.fwd_grid_cap / pl->bd.cus;
     out->inv_tf = pl->inv_tf;
+    out->inv_groups = pl->inv_tf > 1 ? inv_groups_of(pl) : 1;
     return SST_OK;
 }
 
@@ -1103,7 +1151,6 @@ sst_status sst_tuning_save(sst_plan_t pl, const char *path)
     read_cache(path, entries);   // a missing file starts an empty cache
     sst_tuning cur{};
     sst_plan_get_tuning(pl, &cur);
-    cur.reserved = 0;
     const std::string key = tuning_key(pl);
     bool found = false;
     for (auto &e : entries)
@@ -1119,10 +1166,12 @@ sst_status sst_tuning_save(sst_plan_t pl, const char *path)
         return fail(SST_E_ARG, std::string("cannot write ") + tmp);
     std::fprintf(f, "{\n");
     for (size_t i = 0; i < entries.size(); ++i)
-        std::fprintf(f, "  \"%s\": {\"fwd_wg_per_cu\": %d, \"seed_step\": %d, \"inv_tf\": %d}%s\n",
+        std::fprintf(f,
+                     "  \"%s\": {\"fwd_wg_per_cu\": %d, \"seed_step\": %d, \"inv_tf\": %d, "
+                     "\"inv_groups\": %d}%s\n",
                      entries[i].first.c_str(), entries[i].second.fwd_wg_per_cu,
                      entries[i].second.seed_step, entries[i].second.inv_tf,
-                     i + 1 < entries.size() ? "," : "");
+                     entries[i].second.inv_groups, i + 1 < entries.size() ? "," : "");
     std::fprintf(f, "}\n");
     const bool ok = std::fclose(f) == 0 && std::rename(tmp.c_str(), path) == 0;
     return ok ? SST_OK : fail(SST_E_ARG, std::string("cannot write ") + path);
@@ -1170,7 +1219,6 @@ sst_status sst_autotune(sst_plan_t pl, const float *x, float *T, const int32_t *
         return st == SST_OK ? ms / reps : -1.f;
     };
     sst_tuning cur = pl->tune;
-    cur.reserved = 0;
     sst_tuning chosen = cur;
     // forward: resident workgroups per CU x seed step of the speculative threshold
     const int occ = pl->bd.fwd_occ > 0 ? pl->bd.fwd_occ : 1;
@@ -1193,14 +1241,20 @@ sst_status sst_autotune(sst_plan_t pl, const float *x, float *T, const int32_t *
                 chosen.seed_step = seed;
             }
         }
-    // inverse: tile width
+    // inverse: tile width, and the grouped staging of the wide tiles
     if (st == SST_OK && ridge) {
         float best_inv = -1.f;
-        for (int tf : {1, sst::kInvWideTF}) {
+        const int choices[4][2] = {{1, 1}, {sst::kInvWideTF, 1}, {sst::kInvWideTF, 2},
+                                   {sst::kInvWideTF, 4}};
+        for (const auto &ch : choices) {
+            const int tf = ch[0], gr = ch[1];
             if (tf > 1 && !inv_wide_fits(pl))
+                continue;
+            if (gr > 1 && !inv_groups_fit(pl, tf, gr))
                 continue;
             sst_tuning t = chosen;
             t.inv_tf = tf;
+            t.inv_groups = gr;
             if ((st = apply_tuning(pl, t)) != SST_OK)
                 break;
             const float ms = timed([&] {
@@ -1212,6 +1266,7 @@ sst_status sst_autotune(sst_plan_t pl, const float *x, float *T, const int32_t *
             if (best_inv < 0.f || ms < best_inv) {
                 best_inv = ms;
                 chosen.inv_tf = tf;
+                chosen.inv_groups = gr;
             }
         }
     }
@@ -1462,11 +1517,11 @@ sst_status sst_batch_commit(sst_batch_t b, void *stream)
     b->idesc.assign(b->plans.size(), sst::InvDesc{});
     b->inv_pos.assign(b->plans.size(), 0);
     size_t pos = 0;
-    for (int wide = 0; wide < 2; ++wide) {
+    for (int kind = 0; kind < 4; ++kind) {
         int64_t blk = 0;
         for (size_t c = 0; c < b->plans.size(); ++c) {
             const sst_plan_s *pl = b->plans[c];
-            if ((pl->inv_tf > 1) != (wide == 1))
+            if (inv_kind_of(pl) != kind)
                 continue;
             const sst_batch_s::Io &o = b->io[c];
             sst::InvDesc a = inv_desc(pl, o.T, 0, pl->n_frames, o.ridge, o.ridge ? o.n_comp : 0,
@@ -1603,13 +1658,13 @@ sst_status sst_batch_inverse(sst_batch_t b, int32_t c_begin, int32_t c_end, void
     const sst::InvDesc *dev = reinterpret_cast<const sst::InvDesc *>(b->ws + b->off_idesc);
     // one launch per kind of tile: the range's channels of that kind are a
     // contiguous run of the descriptor array
-    for (int wide = 0; wide < 2; ++wide) {
+    for (int kind = 0; kind < 4; ++kind) {
         int p0 = -1, p1 = -1;
         int max_k = 2, max_tab = 1, max_L = 1, max_dec = 1;
         bool any_err = false;
         for (int c = c_begin; c < c_end; ++c) {
             const sst_plan_s *pl = b->plans[(size_t)c];
-            if ((pl->inv_tf > 1) != (wide == 1))
+            if (inv_kind_of(pl) != kind)
                 continue;
             const int pos = b->inv_pos[(size_t)c];
             if (p0 < 0)
@@ -1624,8 +1679,11 @@ sst_status sst_batch_inverse(sst_batch_t b, int32_t c_begin, int32_t c_end, void
         if (p0 < 0)
             continue;
         sst::InvLaunch l = inv_launch(dev + p0, p1 - p0 + 1, b->idesc[(size_t)p0].blk0, max_k,
-                                      max_tab, max_L, max_dec, wide ? sst::kInvWideTF : 1);
-        if (sst::inv_lds_bytes(l) > 64 * 1024)
+                                      max_tab, max_L, max_dec, kind ? sst::kInvWideTF : 1,
+                                      kind == 3 ? 4 : (kind == 2 ? 2 : 1));
+        // grouped tiles of several channels may need more than one channel's
+        // LDS (the maxima of different channels); up to the CU's 160 KiB
+        if (sst::inv_lds_bytes(l) > (kind >= 2 ? 160 * 1024 : 64 * 1024))
             return fail(SST_E_UNSUPPORTED, "inverse tiles need more than 64 KiB of LDS "
                                            "(window too long for the hop)");
         const int64_t blocks = b->idesc[(size_t)p1].blk_end - l.blk_begin;
@@ -1740,7 +1798,7 @@ const char *sst_status_string(sst_status s)
     switch (s) {
     case SST_OK: return "SST_OK";
     case SST_E_ARG: return "SST_E_ARG: invalid argument";
-    case SST_E_UNSUPPORTED: return "SST_E_UNSUPPORTED: not supported by this build";
+    case SST_E_UNSUPPORTED: return "SST_E_UNSUPPORTED: valid for the method, not supported by the library";
     case SST_E_WORKSPACE: return "SST_E_WORKSPACE: workspace missing, misaligned or too small";
     case SST_E_DEVICE: return "SST_E_DEVICE: HIP call failed";
     case SST_E_STATE: return "SST_E_STATE: plan not bound";

@@ -104,6 +104,8 @@ struct InvLaunch {
     int max_gtab;           // LDS words of the largest window table in the list
     int dec;                // window tables decimated by the hop (inv_gtab_words)
     int tf;                 // groups of kInvTileSamples per workgroup (1 or kInvWideTF)
+    int groups;             // groups of 16 destinations staged together (1, 2 or 4; 2 and 4
+                            // need tf > 1 and dec)
 };
 
 // Words of a channel's inverse window table: decimated by the hop,
@@ -114,6 +116,9 @@ constexpr int kInvDecMax = 10240;
 constexpr int kInvTileSamples = 256;   // output samples per group of four inverse waves
 constexpr int kInvWideTF = 4;          // groups per workgroup of the wide inverse tiles
 constexpr int kInvWideKB = 144;        // frames a wide tile may meet (one staged block)
+// LDS of the grouped inverse with g groups staged: three workgroups per CU
+// for two groups, two for four
+constexpr size_t inv_group_lds_max(int g) { return g >= 4 ? 80 * 1024 : 53 * 1024; }
 
 // Precision tiers of the DFT-as-GEMM forward (values of sst_params.precision).
 constexpr int SST_GEMM_BF16 = 1;

@@ -1563,17 +1563,28 @@ __host__ __device__ inline size_t inv_align16(size_t v)
 {
     return (v + 15) & ~(size_t)15;
 }
-__host__ __device__ inline InvLds inv_lds_layout(int max_tab, int max_gtab, int max_k, int kbp)
+// ng groups of 16 destinations staged at once (1, 2 or 4): ahi and alo
+// hold ng blocks of 32 rows of kbp halves each, fred ng x 4 wave maxima.
+__host__ __device__ inline InvLds inv_lds_layout(int max_tab, int max_gtab, int max_k, int kbp,
+                                                 int ng = 1)
 {
     InvLds o;
     o.gpk = inv_align16(8 * (size_t)max_tab);
     o.rid = inv_align16(o.gpk + 4 * (size_t)max_gtab);
     o.ahi = inv_align16(o.rid + 4 * (size_t)max_k);
-    o.alo = o.ahi + 2 * 32 * (size_t)kbp;
-    o.fred = inv_align16(o.alo + 2 * 32 * (size_t)kbp);
-    o.red = o.fred + 16;
+    o.alo = o.ahi + (size_t)ng * 2 * 32 * (size_t)kbp;
+    o.fred = inv_align16(o.alo + (size_t)ng * 2 * 32 * (size_t)kbp);
+    o.red = o.fred + 16 * (size_t)ng;
     o.total = o.red + 16;
     return o;
+}
+
+// Row length (halves) of the grouped inverse's staged blocks: the frames a
+// tile meets rounded up to 16, plus 8; an odd multiple of 8, so that the 16
+// lanes of a 16-byte read reach 16 different groups of four banks.
+__host__ __device__ inline int inv_group_kbp(int max_k)
+{
+    return ((max_k + 15) & ~15) + 8;
 }
 
 // Window contraction of one wave's 64 samples (sample group cg of the tile)
@@ -1921,6 +1932,341 @@ __global__ __launch_bounds__(256, TF > 1 ? 4 : (ONE ? (DEC ? 6 : 5) : 4)) void i
     }
 
     // denominator and output: lanes of the first half write their two samples
+    double d2 = 0.0, r2 = 0.0;
+#pragma unroll
+    for (int cg = 0; cg < TF; ++cg)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const int n = tile_lo + 256 * cg + wave * 64 + col + 32 * c;
+        const bool writer = half == 0 && n <= tile_hi;
+        float xv = 0.f;
+        if (writer) {
+            const int flo = n - M > 0 ? (n - M + H - 1) / H : 0;
+            const int fhi = (n + M) / H;
+            float dv;
+            if (n >= M && fhi <= nframes_all - 1) {
+                dv = a.den[n % H];
+            } else {
+                dv = 0.f;
+                const int hi = fhi < nframes_all - 1 ? fhi : nframes_all - 1;
+                for (int m = flo; m <= hi; ++m)
+                    dv += win[n - m * H + M].x;
+                dv *= win[M].x;
+            }
+            xv = dv > 0.f ? y[cg][c] / dv : 0.f;
+            float *out = a.xhat + (int64_t)q * a.n + n;
+            if (a.accumulate)
+                xv += *out;
+            *out = xv;
+        }
+        if (a.err && writer && n >= M && n < a.n - M) {
+            const double rv = a.xref[(int64_t)q * a.n + n];
+            d2 += (rv - (double)xv) * (rv - (double)xv);
+            r2 += rv * rv;
+        }
+    }
+    if (a.err)
+        err_reduce(d2, r2, a.err, q);
+}
+
+// Grouped wide inverse: the wide, one-block, decimated-table inverse with NG
+// groups of 16 destinations of the tile's zones staged at once (2 or 4; more
+// take further passes).  A step of 16 frames then
+// reads each lane's window values (the B operand) once for all groups, the
+// accumulators of all groups are live together (2 x 16 registers per group),
+// and the phase sums of a sample column share its phasors.  Same arithmetic,
+// term by term, as inv_kernel<true, true, kInvWideTF>: the same coefficients,
+// splits, products and power-of-two scales per group.
+template <int NG>
+__device__ __forceinline__ void wave_mfma_groups(f32x16 (&acc)[NG][2], const unsigned short *aph,
+                                                 const unsigned short *apl, int gstride,
+                                                 const unsigned *gpk, int tile_lo, int cg, int wave,
+                                                 int col, int half, int mlo, int kn, int M, int H,
+                                                 int JL, int TR, float invH, int ng)
+{
+    const int w_lo = tile_lo + 256 * cg + 64 * __builtin_amdgcn_readfirstlane(wave);
+    const int wm_lo = w_lo - M > 0 ? (w_lo - M + H - 1) / H : 0;
+    const int wm_hi = (w_lo + 63 + M) / H;
+    int kw0 = wm_lo - mlo, kw1 = wm_hi - mlo;
+    kw0 = kw0 > 0 ? kw0 & ~15 : 0;
+    kw1 = kw1 < kn - 1 ? kw1 : kn - 1;
+    const int j0 = w_lo + col - mlo * H - (kw0 + 8 * half) * H;
+    // residue rows of the decimated window table (see wave_mfma)
+    const int u0 = j0 + JL;
+    int q0 = (int)((float)u0 * invH);
+    int r0 = u0 - q0 * H;
+    q0 += r0 >= H ? 1 : (r0 < 0 ? -1 : 0);
+    r0 = u0 - q0 * H;
+    const int u1 = u0 + 32;
+    int q1 = (int)((float)u1 * invH);
+    int r1 = u1 - q1 * H;
+    q1 += r1 >= H ? 1 : (r1 < 0 ? -1 : 0);
+    r1 = u1 - q1 * H;
+    const unsigned *pc0 = gpk + r0 * TR + q0 - 7;
+    const unsigned *pc1 = gpk + r1 * TR + q1 - 7;
+    auto step = [&](int k0, auto fresh) {
+        constexpr bool FRESH = decltype(fresh)::value != 0;
+        f16x8v fh[2], fl[2];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const unsigned *pc = c ? pc1 : pc0;
+            unsigned w[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                w[i] = pc[7 - i];
+            u4v_t bh, bl;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                bh[i] = __builtin_amdgcn_perm(w[2 * i + 1], w[2 * i], 0x05040100u);
+                bl[i] = __builtin_amdgcn_perm(w[2 * i + 1], w[2 * i], 0x07060302u);
+            }
+            fh[c] = __builtin_bit_cast(f16x8v, bh);
+            fl[c] = __builtin_bit_cast(f16x8v, bl);
+        }
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+            if (g >= ng)
+                break;
+            const u4v_t a_hi = *reinterpret_cast<const u4v_t *>(aph + g * gstride + k0);
+            const u4v_t a_lo = *reinterpret_cast<const u4v_t *>(apl + g * gstride + k0);
+            const f16x8v ah = __builtin_bit_cast(f16x8v, a_hi);
+            const f16x8v al = __builtin_bit_cast(f16x8v, a_lo);
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                if constexpr (FRESH)
+                    acc[g][c] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, fh[c], f32x16{}, 0, 0, 0);
+                else
+                    acc[g][c] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, fh[c], acc[g][c], 0, 0, 0);
+                acc[g][c] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, fl[c], acc[g][c], 0, 0, 0);
+                acc[g][c] = __builtin_amdgcn_mfma_f32_32x32x16_f16(al, fh[c], acc[g][c], 0, 0, 0);
+            }
+        }
+        pc0 -= 16;
+        pc1 -= 16;
+    };
+    int k0 = kw0;
+    if (k0 > kw1) {   // no frame reaches the wave's samples
+#pragma unroll
+        for (int g = 0; g < NG; ++g)
+            acc[g][0] = acc[g][1] = f32x16{};
+        return;
+    }
+    step(k0, IntC<1>{});
+    for (k0 += 16; k0 <= kw1; k0 += 16)
+        step(k0, IntC<0>{});
+}
+
+template <int NG>
+__global__ __launch_bounds__(256, NG >= 4 ? 2 : 3) void inv_kernel_g(InvLaunch l)
+{
+    constexpr int TF = kInvWideTF;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int64_t blk = l.blk_begin + (int64_t)blockIdx.x;
+    const CA InvDesc *chs = (const CA InvDesc *)l.ch;
+    const CA InvDesc &a = chs[inv_chan_of(chs, l.n_ch, blk)];
+    const int nlo = 1 << a.lo_bits;
+    const int nhi = (a.G + nlo - 1) >> a.lo_bits;
+    const int KBP = inv_group_kbp(l.max_k);
+    const int GS = 32 * KBP;   // halves per staged group
+    const InvLds lay = inv_lds_layout(l.max_tab, l.max_gtab, l.max_k, KBP, NG);
+    v2 *tlo = reinterpret_cast<v2 *>(smem);
+    v2 *thi = tlo + nlo;
+    unsigned *gpk = reinterpret_cast<unsigned *>(smem + lay.gpk);
+    int *rid = reinterpret_cast<int *>(smem + lay.rid);
+    unsigned short *ahi = reinterpret_cast<unsigned short *>(smem + lay.ahi);   // [NG][32][KBP]
+    unsigned short *alo = reinterpret_cast<unsigned short *>(smem + lay.alo);   // [NG][32][KBP]
+    float *fred = reinterpret_cast<float *>(smem + lay.fred);                   // [NG][4]
+    int *red = reinterpret_cast<int *>(smem + lay.red);
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = lane & 31, half = lane >> 5;
+    const unsigned local = (unsigned)(blk - a.blk0);
+    const unsigned tiles = (unsigned)a.tiles;
+    const int q = (int)(local / tiles);
+    const int span_lo = (int)a.span_lo, span_end = (int)(a.span_lo + a.span_len - 1);
+    const int tile_lo = span_lo + (int)(local - (unsigned)q * tiles) * (kInvTile * TF);
+    const int tile_hi = tile_lo + kInvTile * TF - 1 < span_end ? tile_lo + kInvTile * TF - 1 : span_end;
+    const int M = a.M, H = a.hop, Gi = a.G;
+    const float invH = 1.0f / (float)H;
+    const int frame0 = (int)a.frame0, nfr = (int)a.nframes, nframes_all = (int)a.n_frames;
+    const v2 *__restrict__ win = reinterpret_cast<const v2 *>(a.win);
+
+#pragma unroll 2
+    for (int e = threadIdx.x; e < nlo; e += 256)
+        tlo[e] = reinterpret_cast<const v2 *>(a.ph_lo)[e];
+#pragma unroll 2
+    for (int e = threadIdx.x; e < nhi; e += 256)
+        thi[e] = reinterpret_cast<const v2 *>(a.ph_hi)[e];
+    // decimated window table, g[j] 2^tg as FP16 hi | lo << 16 (see inv_kernel)
+    const float gsc = a.g_scale;
+    const int JL = a.dec_reach;
+    const int TR = a.dec_row;
+    const int n_tab = H * TR;
+#pragma unroll 4
+    for (int e = threadIdx.x; e < n_tab; e += 256) {
+        const int r = e / TR;
+        const int j = r + (e - r * TR) * H - JL;
+        unsigned w = 0u;
+        if (j >= -M && j <= M) {
+            unsigned h, lw;
+            split_f16(win[j + M].x * gsc, h, lw);
+            w = h | (lw << 16);
+        }
+        gpk[e] = w;
+    }
+
+    int mlo = tile_lo - M > 0 ? (tile_lo - M + H - 1) / H : 0;
+    int mhi = (tile_hi + M) / H;
+    if (mlo < frame0)
+        mlo = frame0;
+    if (mhi > frame0 + nfr - 1)
+        mhi = frame0 + nfr - 1;
+    const int K = mhi >= mlo ? mhi - mlo + 1 : 0;
+    const int32_t *__restrict__ ridge = a.ridge + (int64_t)q * a.nframes + (mlo - frame0);
+    for (int k = threadIdx.x; k < K; k += 256)
+        rid[k] = ridge[k];
+    if (threadIdx.x < 2)
+        red[threadIdx.x] = threadIdx.x == 0 ? 0x7fffffff : -1;
+    __syncthreads();
+    {
+        int dmin = 0x7fffffff, dmax = -1;
+        for (int k = threadIdx.x; k < K; k += 256) {
+            const int r = rid[k];
+            if (r >= 0) {
+                dmin = min(dmin, max(r - a.hw, 0));
+                dmax = max(dmax, min(r + a.hw, a.n_dst - 1));
+            }
+        }
+        if (dmax >= 0) {
+            atomicMin(&red[0], dmin);
+            atomicMax(&red[1], dmax);
+        }
+    }
+    __syncthreads();
+    const int d_lo = red[0], d_hi = red[1];
+    const int zk1 = a.z * a.k1;
+    const uint32_t G = (uint32_t)Gi;
+    const bool pow2 = a.g_pow2 != 0;
+    const uint32_t mh0 = (uint32_t)(mlo * H) % G;
+    const uint32_t n0g = (uint32_t)tile_lo % G;
+    const uint32_t hg = (uint32_t)H % G;
+    const int kn16 = (K + 15) & ~15;
+    const int nrd = kn16 / 16;   // rounds of 256 staged coefficients (16 frames)
+    constexpr int STAGE = kInvWideKB * 16 / 256;
+
+    const v2 *__restrict__ Trow = reinterpret_cast<const v2 *>(a.T) + (int64_t)(mlo - frame0) * a.n_dst;
+    const unsigned short *aph = ahi + col * KBP + 8 * half;
+    const unsigned short *apl = alo + col * KBP + 8 * half;
+    float y[TF][2];
+#pragma unroll
+    for (int cg = 0; cg < TF; ++cg)
+        y[cg][0] = y[cg][1] = 0.f;
+    for (int D0 = d_lo; D0 <= d_hi; D0 += 16 * NG) {
+        const int ng = (d_hi - D0) / 16 + 1 < NG ? (d_hi - D0) / 16 + 1 : NG;
+        int scg[NG];
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+            scg[g] = 0;
+            if (g >= ng)
+                break;
+            const int d0 = D0 + 16 * g;
+            int tid = threadIdx.x;
+            asm volatile("" : "+v"(tid));
+            float cre[STAGE], cim[STAGE];
+            float amax = 0.f;
+#pragma unroll
+            for (int i = 0; i < STAGE; ++i) {
+                cre[i] = cim[i] = 0.f;
+                if (i >= nrd)
+                    continue;
+                const int e = tid + 256 * i;
+                const int kk = e >> 4, dd = e & 15;
+                const int ld = d0 + dd;
+                v2 c = mk(0.f, 0.f);
+                const int r = kk < K ? rid[kk] : -1;
+                if (r >= 0 && ld <= d_hi && ld >= r - a.hw && ld <= r + a.hw) {
+                    const int b = zk1 + ld;
+                    const float wgt = (b == 0 || 2 * b == Gi) ? 1.f : 2.f;
+                    const v2 t = Trow[(int64_t)kk * a.n_dst + ld];
+                    uint32_t mh = mh0 + (uint32_t)kk * hg;
+                    mh = pow2 ? (mh & (G - 1)) : mh % G;
+                    const int bm = mulmod((uint32_t)b, mh, Gi, a.g_pow2, a.inv_G);
+                    const v2 ph = phasor(tlo, thi, bm, a.lo_bits);   // e^{+i 2 pi b m H / G}
+                    c = (wgt * a.inv_nfft) * cmul(t, conjv(ph));
+                }
+                cre[i] = c.x;
+                cim[i] = c.y;
+                amax = fmaxf(amax, fmaxf(fabsf(c.x), fabsf(c.y)));
+            }
+            amax = wave_reduce63(amax, 0.f, [](float p, float r) { return fmaxf(p, r); });
+            if (lane == 63)
+                fred[4 * g + wave] = amax;
+            __syncthreads();
+            const float bmax = fmaxf(fmaxf(fred[4 * g], fred[4 * g + 1]),
+                                     fmaxf(fred[4 * g + 2], fred[4 * g + 3]));
+            int ex = 0;
+            (void)frexpf(bmax, &ex);
+            int sb = 14 - ex;
+            sb = sb > 100 ? 100 : (sb < -100 ? -100 : sb);
+            scg[g] = sb;
+            const float scl = ldexpf(1.f, sb);
+            unsigned short *gh = ahi + g * GS, *gl = alo + g * GS;
+#pragma unroll
+            for (int i = 0; i < STAGE; ++i) {
+                const int e = tid + 256 * i;
+                const int kk = e >> 4, dd = e & 15;
+                if (i < nrd) {
+                    unsigned h, lw;
+                    split_f16(cre[i] * scl, h, lw);
+                    gh[(2 * dd) * KBP + kk] = (unsigned short)h;
+                    gl[(2 * dd) * KBP + kk] = (unsigned short)lw;
+                    split_f16(cim[i] * scl, h, lw);
+                    gh[(2 * dd + 1) * KBP + kk] = (unsigned short)h;
+                    gl[(2 * dd + 1) * KBP + kk] = (unsigned short)lw;
+                }
+            }
+        }
+        __syncthreads();   // every staged group complete
+        // one sample group at a time (not unrolled: the accumulators of all
+        // groups are live through it), its sums added into y by selection
+#pragma unroll 1
+        for (int cg = 0; cg < TF; ++cg) {
+            f32x16 acc[NG][2];
+            wave_mfma_groups<NG>(acc, aph, apl, GS, gpk, tile_lo, cg, wave, col, half, mlo, K, M,
+                                 H, JL, TR, invH, ng);
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                uint32_t nm = n0g + (uint32_t)(256 * cg + 64 * wave + col + 32 * c);
+                nm = nm >= G ? nm - G : nm;
+                nm = nm >= G ? nm - G : nm;
+                const v2 w = phasor(tlo, thi, (int)nm, a.lo_bits);   // e^{i 2 pi n/G}
+                const v2 w4 = cmul(cmul(w, w), cmul(w, w));
+                float tsum = 0.f;
+#pragma unroll
+                for (int g = 0; g < NG; ++g) {
+                    if (g >= ng)
+                        break;
+                    const uint32_t bb = (uint32_t)(zk1 + D0 + 16 * g + 2 * half);
+                    v2 e = phasor(tlo, thi, mulmod(bb, nm, Gi, a.g_pow2, a.inv_G), a.lo_bits);
+                    float t = 0.f;
+#pragma unroll
+                    for (int g4 = 0; g4 < 4; ++g4) {
+                        const v2 e1 = cmul(e, w);
+                        t += e.x * acc[g][c][4 * g4] - e.y * acc[g][c][4 * g4 + 1];
+                        t += e1.x * acc[g][c][4 * g4 + 2] - e1.y * acc[g][c][4 * g4 + 3];
+                        e = cmul(e, w4);
+                    }
+                    tsum += t * ldexpf(a.g_unscale, -scg[g]);
+                }
+                tsum += __shfl_xor(tsum, 32, 64);
+#pragma unroll
+                for (int k = 0; k < TF; ++k)
+                    y[k][c] += k == cg ? tsum : 0.f;
+            }
+        }
+        __syncthreads();   // staged groups consumed before the next pass
+    }
+
     double d2 = 0.0, r2 = 0.0;
 #pragma unroll
     for (int cg = 0; cg < TF; ++cg)
@@ -2350,6 +2696,9 @@ hipError_t launch_put_desc(const ChanDesc &d, ChanDesc *dst, bool clear_max, int
 
 size_t inv_lds_bytes(const InvLaunch &l)
 {
+    if (l.groups > 1)
+        return inv_lds_layout(l.max_tab, l.max_gtab, l.max_k, inv_group_kbp(l.max_k), l.groups)
+            .total;
     const int kbp = l.tf > 1 ? InvGeo<kInvWideTF>::KBP : InvGeo<1>::KBP;
     return inv_lds_layout(l.max_tab, l.max_gtab, l.max_k, kbp).total;
 }
@@ -2370,7 +2719,11 @@ hipError_t launch_inverse(const InvLaunch &l, int64_t blocks, bool clear_err, hi
         // the host sets tf > 1 only when every tile's frames fit one block
         if (l.max_k > InvGeo<kInvWideTF>::KB)
             return hipErrorInvalidValue;
-        if (l.dec)
+        if (l.groups == 4 && l.dec)
+            hipLaunchKernelGGL((inv_kernel_g<4>), g, b, lds, s, l);
+        else if (l.groups == 2 && l.dec)
+            hipLaunchKernelGGL((inv_kernel_g<2>), g, b, lds, s, l);
+        else if (l.dec)
             hipLaunchKernelGGL((inv_kernel<true, true, kInvWideTF>), g, b, lds, s, l);
         else
             hipLaunchKernelGGL((inv_kernel<true, false, kInvWideTF>), g, b, lds, s, l);

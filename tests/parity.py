@@ -1,6 +1,6 @@
 """Comparison rules between the GPU library and the float64 oracle.
 
-Tolerances (derived in DESIGN.md, "Parity rules"):
+Tolerances:
   * STFT pair S, S' and the SST matrix T: relative Frobenius error <= 1e-5
     (T after reconciling the index decisions below; the raw value is reported);
   * threshold gamma: relative 1e-5;
@@ -9,7 +9,7 @@ Tolerances (derived in DESIGN.md, "Parity rules"):
         tier's own error bound of |S|) may be retained by one side only, and
       - a coefficient may land in the bin next to the oracle's when the
         oracle's fractional destination u lies within max(1e-4, 4 e_u) of the
-        rounding boundary between them (the zone of the spec rule,
+        rounding boundary between them (the 1e-4 zone of the acceptance rule,
         widened to where FP32 cannot decide), e_u = z N_f / (2 pi) 2^-24 ||y||
         (1/(s|S|) + |S'|/|S|^2) being the first-order effect on u of one unit
         2^-24 ||y|| of error in S and in S' (||y||: norm of the packed windowed

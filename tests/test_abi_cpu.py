@@ -278,6 +278,34 @@ def test_tuning_set_get_and_validation():
     assert e.value.status == sst.SST_E_UNSUPPORTED
 
 
+def test_tuning_inverse_groups():
+    """Grouped staging of the wide inverse (2 or 4 destination groups staged
+    together): a tuning choice, accepted where its LDS fits three or two
+    workgroups per CU."""
+    c3 = dict(nfft=8192, win_len=2047, sigma=256.0, hop=32, f_hi=5000.0, subdiv=8)
+    p = sst.Plan(**_params(**c3))     # 1024 samples meet 98 frames: 4 groups in about 79 KiB
+    t = p.get_tuning()
+    assert (t["inv_tf"], t["inv_groups"]) == (4, 1)
+    for g in (2, 4, 1):
+        p.set_tuning(inv_groups=g)
+        assert p.get_tuning()["inv_groups"] == g
+    p.set_tuning(inv_tf=1)
+    assert p.get_tuning()["inv_groups"] == 1   # narrow tiles stage one group at a time
+    with pytest.raises(sst.SSTError) as e:
+        p.set_tuning(inv_tf=1, inv_groups=4)
+    assert e.value.status == sst.SST_E_UNSUPPORTED
+    for bad in (3, 5, -1):
+        with pytest.raises(sst.SSTError) as e:
+            p.set_tuning(inv_groups=bad)
+        assert e.value.status == sst.SST_E_ARG
+    q = sst.Plan(**_params())         # c2 shape: 130 frames per tile: 2 groups fit, 4 do not
+    q.set_tuning(inv_groups=2)
+    assert (q.get_tuning()["inv_tf"], q.get_tuning()["inv_groups"]) == (4, 2)
+    with pytest.raises(sst.SSTError) as e:
+        q.set_tuning(inv_groups=4)
+    assert e.value.status == sst.SST_E_UNSUPPORTED
+
+
 def test_tuning_cache_round_trip(tmp_path, monkeypatch):
     """The JSON cache is keyed by shape: an entry saved for one plan applies to a
     plan of the same shape (explicitly, and through SST_TUNE_CACHE at plan time)
@@ -296,10 +324,10 @@ def test_tuning_cache_round_trip(tmp_path, monkeypatch):
     assert len(d) == 2
     key = [k for k in d if "H=16" in k][0]
     assert key.startswith("gfx950 nfft=4096 L=1023 H=16 n_src=1025 n_dst=4097")
-    assert d[key] == {"fwd_wg_per_cu": 2, "seed_step": 16, "inv_tf": 1}
+    assert d[key] == {"fwd_wg_per_cu": 2, "seed_step": 16, "inv_tf": 1, "inv_groups": 1}
     b = sst.Plan(**_params())
     b.tuning_load(path)
-    assert b.get_tuning() == {"fwd_wg_per_cu": 2, "seed_step": 16, "inv_tf": 1}
+    assert b.get_tuning() == {"fwd_wg_per_cu": 2, "seed_step": 16, "inv_tf": 1, "inv_groups": 1}
     monkeypatch.setenv("SST_TUNE_CACHE", path)
     c = sst.Plan(**_params())
     assert c.get_tuning()["seed_step"] == 16 and c.get_tuning()["inv_tf"] == 1

@@ -1,7 +1,8 @@
 """GPU: the DFT-as-GEMM precision tiers (BF16, FP16 hi/lo x3 on the matrix
 cores) against the float64 oracle and against the FP32 FFT path, on c5-shaped
 inputs (N_f 512 / 1024, L = N_f - 1, sigma = N_f / 8, H = 8, band [0, 6.4 kHz],
-z = 1) and on a band with k1 > 0 and z = 2.
+z = 1), on a band with k1 > 0 and z = 2, and on narrow bands at N_f 4096 and
+8192 (L = N_f - 1).
 
 Reported for every tier: relative Frobenius error of S, S' and T (T against
 the oracle's coefficients re-scattered with the GPU's index decisions, and
@@ -52,6 +53,11 @@ def _workloads():
     w = make_c5(n_channels=1, n=20000, nfft=512)[0]
     w.cfg = SSTConfig(25600.0, 255, 32.0, 16, 512, 1000.0, 6000.0, 2, "rel", 1e-3, 2)
     out.append(("nf512-z2-k1", w))
+    # narrow bands at long DFTs (the filter-bank use of the GEMM tiers):
+    # N_f 4096 with [0, 1 kHz] and N_f 8192 with [0, 500 Hz], L = N_f - 1
+    for nfft, f_hi in ((4096, 1000.0), (8192, 500.0)):
+        w = make_c5(n_channels=1, n=1 << 14, nfft=nfft, f_hi=f_hi)[0]
+        out.append((f"nf{nfft}-narrow", w))
     return out
 
 
