@@ -111,7 +111,8 @@ def run_c4(args):
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     t0 = time.perf_counter()
-    ws = make_c4(n_channels=args.c4_channels)
+    ws = make_c4(n_channels=args.c4_channels, log2_min=args.c4_log2_min,
+                 log2_max=args.c4_log2_max)
     gen_s = time.perf_counter() - t0
     plans = [sst.Plan.from_config(w.n, w.cfg, device=dev) for w in ws]
     sizes = [p.n_frames * p.n_dst for p in plans]
@@ -207,7 +208,8 @@ def run_c4(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"batched uneven channels: {len(ws)} channels (seed 0), lengths "
-                               "log-uniform in [2^16, 2^22], H in {4,8,16,32}, N_f in "
+                               f"log-uniform in [2^{args.c4_log2_min:g}, 2^{args.c4_log2_max:g}], "
+                               "H in {4,8,16,32}, N_f in "
                                "{1024,2048,4096}, z in {2,4}, L=N_f/4-1, sigma=N_f/32, band "
                                "[0, 6.4 kHz], 1-4 chirp/AM-FM components + noise 5-25 dB, "
                                "closed-form ridges",
@@ -711,6 +713,9 @@ def main():
     ap.add_argument("--c5-band-hi", type=float, default=6400.0,
                     help="c5: upper edge of the band in Hz (1000 for the narrow-band variant)")
     ap.add_argument("--c4-channels", type=int, default=256)
+    ap.add_argument("--c4-log2-min", type=float, default=16.0,
+                    help="c4: channel lengths are log-uniform in [2^min, 2^max] samples")
+    ap.add_argument("--c4-log2-max", type=float, default=22.0)
     ap.add_argument("--t-pool-gb", type=float, default=120.0,
                     help="c4: device memory for T; channels are processed in passes that fit")
     ap.add_argument("--n", type=int, default=0,

@@ -1593,8 +1593,15 @@ sst_status sst_batch_forward(sst_batch_t b, int32_t c_begin, int32_t c_end, uint
             g.list_n = nullptr;
             g.item_begin = gr.desc[i0].mitem0;
             g.item_stop = gr.desc[i1 - 1].mitem_end;
-            g.step = (int)seed_step(g.item_stop - g.item_begin, gr.fwd_grid_cap,
-                                    b->plans[(size_t)gr.chans[i0]]->tune.seed_step);
+            // one step over the launch's items, as dense as the densest of the
+            // channels' own single-call seeds: every channel's running maximum
+            // starts at least as close to its final one as in a single call
+            int64_t step = INT64_MAX;
+            for (size_t i = i0; i < i1; ++i)
+                step = std::min(step, seed_step(gr.desc[i].mitem_end - gr.desc[i].mitem0,
+                                                gr.fwd_grid_cap,
+                                                b->plans[(size_t)gr.chans[i]]->tune.seed_step));
+            g.step = (int)step;
             const int64_t visits = (g.item_stop - g.item_begin + g.step - 1) / g.step;
             const int grid = (int)(visits < gr.fwd_grid_cap ? visits : gr.fwd_grid_cap);
             if (e == hipSuccess)

@@ -937,9 +937,6 @@ __global__ __launch_bounds__(Geo<NF>::NT, DEBUG ? 2 : ((NF == 8192 || (NF == 409
                 B += bpart[wv][ff];
             scf[ff] = fixed_scale(B * 1.001f);
         }
-        // Rows longer than the buffer go in chunks of equal size, a multiple of
-        // NT (at most HB), so that no pass clears or stores bins past the row
-        // beyond the last partial round: nst rounds of NT bins per chunk.
         // per-frame sums of the stored row (only when the call asks for them)
         double cre = 0.0, cim = 0.0, ce2 = 0.0;
         int cf = 0;   // frame of the thread's running sums
@@ -969,6 +966,9 @@ __global__ __launch_bounds__(Geo<NF>::NT, DEBUG ? 2 : ((NF == 8192 || (NF == 409
                 cre = cim = ce2 = 0.0;
             }
         };
+        // Rows longer than the buffer go in chunks of equal size, a multiple of
+        // NT (at most HB), so that no pass clears or stores bins past the row
+        // beyond the last partial round: nst rounds of NT bins per chunk.
         int CH = HB;
         if constexpr (CHUNKED) {
             const int nch = (EH + HB - 1) / HB;
@@ -976,10 +976,12 @@ __global__ __launch_bounds__(Geo<NF>::NT, DEBUG ? 2 : ((NF == 8192 || (NF == 409
         }
         for (int c0 = 0; c0 < (CHUNKED ? EH : 1); c0 += CH) {
             const int cn = CHUNKED ? ((EH - c0) < CH ? (EH - c0) : CH) : EH;
-            const int nst = CHUNKED ? (cn + NT - 1) / NT : NST;
+            // rounds of NT bins that hold the row(s): the rest of the buffer
+            // is neither cleared nor stored
+            const int nst = (cn + NT - 1) / NT;
 #pragma unroll
             for (int i = 0; i < NST; ++i)
-                if (!CHUNKED || i < nst)
+                if (i < nst)
                     reinterpret_cast<unsigned long long *>(hq)[threadIdx.x + i * NT] = 0ull;
             __syncthreads();
             // scatter phase (Eq. 28)
@@ -1014,16 +1016,16 @@ __global__ __launch_bounds__(Geo<NF>::NT, DEBUG ? 2 : ((NF == 8192 || (NF == 409
 #pragma unroll
                 for (int g0 = 0; g0 < NST; g0 += SG) {
                     __builtin_amdgcn_sched_barrier(0);
-                    if (CHUNKED && g0 >= nst)
+                    if (g0 >= nst)
                         break;
                     unsigned long long hv[SG];
 #pragma unroll
                     for (int i = 0; i < SG; ++i)
-                        if (g0 + i < NST && (!CHUNKED || g0 + i < nst))
+                        if (g0 + i < NST && g0 + i < nst)
                             hv[i] = reinterpret_cast<const unsigned long long *>(hq)[threadIdx.x + (g0 + i) * NT];
 #pragma unroll
                     for (int i = 0; i < SG; ++i) {
-                        if (g0 + i >= NST || (CHUNKED && g0 + i >= nst))
+                        if (g0 + i >= NST || g0 + i >= nst)
                             continue;
                         const int e = threadIdx.x + (g0 + i) * NT;
                         float isc = 1.0f / scf[0];   // exact: a power of two
@@ -1069,7 +1071,7 @@ __global__ __launch_bounds__(Geo<NF>::NT, DEBUG ? 2 : ((NF == 8192 || (NF == 409
                 // histogram values and scales as the stores above.  A
                 // thread's frame index only grows over its bins, so its sums
                 // go to that frame's LDS slot when the frame changes.
-                for (int r = 0; r < (CHUNKED ? nst : NST); ++r) {
+                for (int r = 0; r < nst; ++r) {
                     const int e = threadIdx.x + r * NT;
                     if (e >= cn)
                         break;
