@@ -708,6 +708,13 @@ __global__ __launch_bounds__(Geo<NF>::NT, DEBUG ? 2 : ((NF == 8192 || (NF == 409
             ph_step = cphase_of(clo, chi, (NT * a.M) & (NF - 1));
         }
 
+        // Wave priorities: the FFT passes (below) wait at a barrier after every
+        // LDS round trip; the IF, scatter and store phases that follow are long
+        // runs without one.  With two or more workgroups resident per CU in
+        // different phases, letting the barrier-free phases issue first (and
+        // the FFT waves fill the gaps) keeps the SIMDs busier: 0 for the FFT,
+        // 1 for the IF phase, 2 for scatter and store.
+        __builtin_amdgcn_s_setprio(0);
         {   // pass 1 from the prefetched samples
             v2 v[16];
 #pragma unroll
@@ -735,6 +742,7 @@ __global__ __launch_bounds__(Geo<NF>::NT, DEBUG ? 2 : ((NF == 8192 || (NF == 409
         fetch(itn, an, chg);
         __syncthreads();
         tw.passes(lds, twl);
+        __builtin_amdgcn_s_setprio(1);
 
         if constexpr (MODE == kFwdStft) {
             // STFT product (Eq. 9 with its centre phase; S' with g'): every
@@ -908,6 +916,7 @@ __global__ __launch_bounds__(Geo<NF>::NT, DEBUG ? 2 : ((NF == 8192 || (NF == 409
                 bpart[threadIdx.x >> 6][ff] = part[ff];
         }
         __syncthreads();   // FFT buffer free, frame bounds complete
+        __builtin_amdgcn_s_setprio(2);
         if (spec && threadIdx.x == 0) {
             // the item is final if nothing it kept lies at or below the final
             // gamma; the running maximum grows with the item's
