@@ -261,6 +261,8 @@ def run_c5(args):
     for prec in ("fp32", "bf16", "f16x3"):
         plan = sst.Plan.from_config(n, cfg, device=dev, precision=prec)
         T = torch.empty((plan.n_frames, plan.n_dst), dtype=torch.complex64, device=dev)
+        tuning = plan.autotune(xs[0], T, reps=2) if not args.no_tune else plan.get_tuning()
+        log(f"c5 {prec}: tuning {tuning}")
 
         def step(reuse=False):
             for x in xs:
@@ -297,7 +299,8 @@ def run_c5(args):
         if prec != "fp32":
             products = 3 if prec == "f16x3" else 1
             flops = 2.0 * 4 * plan.n_src * cfg.win_len * plan.n_frames * nch * products
-        res[prec] = {"ms_with_threshold": round(full_ms, 3), "forward_ms": round(fwd_ms, 3),
+        res[prec] = {"tuning": tuning,
+                     "ms_with_threshold": round(full_ms, 3), "forward_ms": round(fwd_ms, 3),
                      "Msamples_per_s": round(n * nch / (full_ms / 1e3) / 1e6, 1),
                      "snr_db_channel0": snr,
                      "mfma_tflops": (round(flops / (fwd_ms / 1e3) / 1e12, 1) if flops else None)}
@@ -319,7 +322,7 @@ def run_c5(args):
         "config": {"workload": f"precision tier: {nch} channels x 2^20 samples at 25.6 kHz, "
                                f"three AM-FM components + noise 10 dB, N_f={args.c5_nfft}, "
                                f"L=N_f-1, sigma=N_f/8, H=8, band [0, {args.c5_band_hi:g} Hz], z=1, "
-                               "rho=1e-3; STFT+SST forward (threshold pre-pass included)",
+                               "rho=1e-3; STFT+SST forward (threshold included)",
                    "generation_s": round(gen_s, 1)},
         "roofline": {"kernel": "gemm_kernel (FP16 hi/lo x3, 32x32x16 MFMA)", "bound": "mfma",
                      "achieved": best["mfma_tflops"], "peak": peak, "unit": "TFLOP/s",

@@ -98,7 +98,8 @@ typedef int32_t sst_status;
  *                SST_PREC_GEMM_F16X3) for hop a multiple of 8 and a DFT-matrix table
  *                (4 n_src rows x L taps, 2 bytes each) of at most 64 MiB -- narrow
  *                bands, where 4 n_src L products per frame undercut the FFT;
- *                the threshold pre-pass stays FP32 FFT; the GEMM tiers are not
+ *                the relative threshold is taken on the tier's own arithmetic
+ *                (as for the FFT tier, see sst_forward); the GEMM tiers are not
  *                supported by the batched calls
  *   flags        reserved, 0
  */
@@ -195,14 +196,15 @@ typedef struct {
  *   aux      optional outputs, may be NULL
  *   flags    0, or SST_FWD_REUSE_GAMMA and at most one SST_FWD_OUT_MAG_*
  * With SST_THR_REL_MAX and no SST_FWD_REUSE_GAMMA, gamma comes from max |S|
- * over ALL frames of x (not only the chunk), on the forward kernel's own FP32
- * arithmetic.  A call over the whole signal (frame0 = 0, nframes = n_frames,
- * no per-coefficient outputs) computes it speculatively: the maximum over
- * every 32nd frame group and the running maximum give a lower bound of gamma,
- * each group records the least |S| it kept, and the groups that kept a
- * coefficient at or below the final gamma are transformed again -- T is the
- * same, bit for bit, as with the final gamma given.  Other calls run a
- * maximum pre-pass over all frames first.  Calls on one plan share the
+ * over ALL frames of x (not only the chunk), on the forward kernel's own
+ * arithmetic (FP32 FFT, or the GEMM tier's products).  A call over the whole
+ * signal (frame0 = 0, nframes = n_frames, no per-coefficient outputs)
+ * computes it speculatively: the maximum over every k-th frame group (or GEMM
+ * tile; k from sst_tuning.seed_step) and the running maximum give a lower
+ * bound of gamma, each group records the least |S| it kept, and the groups
+ * that kept a coefficient at or below the final gamma are transformed again
+ * -- T is the same, bit for bit, as with the final gamma given.  Other calls
+ * run a maximum pre-pass over all frames first.  Calls on one plan share the
  * workspace: calls that overlap in time on different streams race.
  * Errors: SST_E_ARG (range, NULL x/T), SST_E_STATE, SST_E_DEVICE.
  */

@@ -95,6 +95,12 @@ __device__ __forceinline__ float widen(unsigned short hi, unsigned short lo)
         return (float)__builtin_bit_cast(_Float16, hi) + (float)__builtin_bit_cast(_Float16, lo);
 }
 
+__device__ __forceinline__ float gamma2_rel(int thr_mode, float thr, float max2)
+{
+    const float gm = thr_mode == 1 ? thr * sqrtf(max2) : thr;
+    return gm * gm;
+}
+
 __device__ __forceinline__ float block_max(float v, float *red)
 {
 #pragma unroll
@@ -128,11 +134,27 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmArgs a)
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int col = lane & 31, half = lane >> 5;
     const int64_t n_tiles = (a.nframes + FT - 1) / FT;
-    const float gamma2 = a.ctrl->gamma2;
     const u4v *__restrict__ afrag = reinterpret_cast<const u4v *>(a.afrag);
     const u4v *__restrict__ afrag_lo = reinterpret_cast<const u4v *>(a.afrag_lo);
+    const bool maxonly = a.mode == 1;
+    const bool spec = a.mode == 0 && a.spec;
+    const int64_t n_visit = a.mode == 2 ? (int64_t)*a.list_n
+                            : (maxonly ? (n_tiles + a.tile_step - 1) / a.tile_step : n_tiles);
 
-    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+    for (int64_t v = blockIdx.x; v < n_visit; v += gridDim.x) {
+        const int64_t tile = a.mode == 2 ? (int64_t)a.list[v] : (maxonly ? v * a.tile_step : v);
+        // Speculative relative threshold: the running maximum is at most the
+        // final one, so the gamma it gives is a lower bound (a superset of the
+        // coefficients is kept; the tiles that kept one at or below the final
+        // gamma are redone in mode 2).
+        unsigned runbits = 0u;
+        float gamma2 = a.ctrl->gamma2;
+        if (spec) {
+            runbits = __hip_atomic_load(&a.ctrlw->maxbits, __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT);
+            gamma2 = gamma2_rel(a.thr_mode, a.thr, __uint_as_float(runbits)) * 0.999999f;
+        }
+        float tmax = 0.f, tmin = __builtin_huge_valf();   // max |S|^2, least kept |S|^2
         const int64_t m0 = tile * FT;   // first frame of the tile, relative to frame0
         const int nvalid = (int)((a.nframes - m0) < FT ? (a.nframes - m0) : FT);
         const int64_t s0 = (a.frame0 + m0) * (int64_t)a.hop - a.M;
@@ -184,13 +206,14 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmArgs a)
             if constexpr (SPLIT)
                 *reinterpret_cast<u4v *>(xlo + 8 * gi) = pl;
         }
-        for (int e = threadIdx.x; e < 2 * FT * a.n_dst; e += NT)
-            hist[e] = 0;
+        if (!maxonly)
+            for (int e = threadIdx.x; e < 2 * FT * a.n_dst; e += NT)
+                hist[e] = 0;
         __syncthreads();
 
         // per-frame fixed-point scale: Parseval bound with sum_j x_j^2 g_j^2 <=
         // max g^2 times the sums of squares of the groups covering the window
-        {
+        if (!maxonly) {
             constexpr int TPF = NT / FT;          // threads per frame
             const int f = threadIdx.x / TPF, part = threadIdx.x % TPF;
             const int g0 = f * (a.hop / 8), gn = (a.L + 7) / 8;
@@ -251,6 +274,9 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmArgs a)
                     const float sr = acc[c][4 * q] * ug, si = acc[c][4 * q + 1] * ug;
                     const float dr = acc[c][4 * q + 2] * ugd, di = acc[c][4 * q + 3] * ugd;
                     const float mag2 = sr * sr + si * si;
+                    tmax = fmaxf(tmax, mag2);
+                    if (maxonly)
+                        continue;
                     const int k = a.k1 + b;
                     int code = -1;
                     if (mag2 > gamma2) {
@@ -263,6 +289,7 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmArgs a)
                         code = (fabsf(zd) < 1.0e8f && l >= 0 && l < a.n_dst) ? l : -2;
                     }
                     if (code >= 0) {
+                        tmin = fminf(tmin, mag2);
                         const float sc = scf[f];
                         int *h = hist + 2 * (f * a.n_dst + code);
                         atomicAdd(h, (int)rintf(sr * sc));
@@ -281,6 +308,19 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmArgs a)
             }
         }
         __syncthreads();
+        if (maxonly || spec) {
+            // the tile's maximum into the running one; its least kept |S|^2
+            const float bm = block_max(tmax, red);
+            const float bn = -block_max(-tmin, red);
+            if (threadIdx.x == 0) {
+                if (bm > __uint_as_float(runbits))
+                    atomicMax(&a.ctrlw->maxbits, __float_as_uint(bm));
+                if (spec)
+                    a.smin[tile] = bn;
+            }
+        }
+        if (maxonly)
+            continue;
 
         // store phase: the tile's rows of T are contiguous; a buffer resource
         // bounded to the valid rows drops the rest

@@ -74,7 +74,6 @@ struct Bound {
     int cus = 0;
     int fwd_occ = 0;        // forward workgroups that fit one CU
     int fwd_grid_cap = 0;   // persistent forward grid: CUs x min(fwd_occ, tuned count)
-    int max_grid_cap = 0;
     // a thresholding forward has set gamma in this workspace (cleared by every
     // bind, which leaves the control block unset)
     bool gamma_valid = false;
@@ -443,7 +442,6 @@ sst_status bind_impl(sst_plan_s *pl, Bound &bd, unsigned char *ws, hipStream_t s
             pl->p.precision, pl->gemm_ft,
             sst::gemm_lds_bytes(pl->p.precision, pl->gemm_ft, pl->n_dst, pl->slab, pl->p.win_len));
     apply_grid(pl, bd);
-    bd.max_grid_cap = cus * sst::max_occupancy(pl->p.nfft, pl->p.win_len);
     return SST_OK;
 }
 
@@ -580,8 +578,12 @@ sst_status sst_plan(const sst_params *params, sst_plan_t *out)
         }
     }
     pl->tables_end = off;
-    if (!gemm) {
-        pl->n_items = (pl->n_frames + sst::fwd_frames_per_iter(NF) - 1) / sst::fwd_frames_per_iter(NF);
+    {
+        // speculative threshold state: one entry per forward item (FFT tier)
+        // or per GEMM tile
+        pl->n_items = gemm ? (pl->n_frames + pl->gemm_ft - 1) / pl->gemm_ft
+                           : (pl->n_frames + sst::fwd_frames_per_iter(NF) - 1) /
+                                 sst::fwd_frames_per_iter(NF);
         pl->off_smin = off;
         off = align_up(off + sizeof(float) * (size_t)pl->n_items);
         pl->off_list = off;
@@ -776,35 +778,86 @@ static sst_status forward_impl(sst_plan_s *pl, Bound &bd, const float *x, int64_
     // A call over the whole signal that needs gamma takes the speculative
     // forward: threshold at a lower bound of gamma, then redo the items whose
     // decisions the final gamma changes.
-    const bool spec = threshold && rel && fft && !debug && frame0 == 0 &&
-                      nframes == pl->n_frames && nframes > 0;
+    const bool spec = threshold && rel && !debug && frame0 == 0 && nframes == pl->n_frames &&
+                      nframes > 0;
     sst::ChanDesc d = chan_desc(pl, bd.ws, x, frame0, nframes, T, aux, ctrl);
     d.out_fmt = out_fmt;
     d.item0 = 0;
     d.item_end = (nframes + F - 1) / F;
     d.mitem0 = 0;
-    // threshold items: forward items of the whole signal (FFT tier) or frame
-    // pairs (the GEMM tiers' two-frames-per-FFT pre-pass)
-    d.mitem_end = !(threshold && rel) ? 0
-                  : fft ? (pl->n_frames + F - 1) / F : ((pl->n_frames + 1) / 2 + F - 1) / F;
-    int32_t *list = fft ? reinterpret_cast<int32_t *>(bd.ws + pl->off_list) : nullptr;
-    int32_t *list_n = fft ? reinterpret_cast<int32_t *>(bd.ws + pl->off_list_n) : nullptr;
+    // threshold items of the FFT tier: forward items of the whole signal
+    d.mitem_end = (threshold && rel && fft) ? (pl->n_frames + F - 1) / F : 0;
+    int32_t *list = reinterpret_cast<int32_t *>(bd.ws + pl->off_list);
+    int32_t *list_n = reinterpret_cast<int32_t *>(bd.ws + pl->off_list_n);
     // the upload also clears the running maximum (and the fix-up count)
-    hipError_t e = sst::launch_put_desc(d, slot, threshold && fft, spec ? list_n : nullptr, s);
+    hipError_t e = sst::launch_put_desc(d, slot, threshold, spec ? list_n : nullptr, s);
     if (e != hipSuccess)
         return hip_fail(e, "descriptor upload");
     sst::GroupLaunch g{};
     g.ch = slot;
     g.n_ch = 1;
     g.twid = reinterpret_cast<const float2 *>(bd.ws + pl->off_twid);
+    // GEMM tiers: arguments of a launch over frames [f0, f0 + nf)
+    auto gemm_args = [&](int64_t f0, int64_t nf, int mode) {
+        sst::GemmArgs ga{};
+        ga.x = x;
+        ga.n = pl->p.n_samples;
+        ga.frame0 = f0;
+        ga.nframes = nf;
+        ga.afrag = bd.ws + pl->off_afrag;
+        ga.afrag_lo = pl->off_afrag_lo ? bd.ws + pl->off_afrag_lo : nullptr;
+        ga.win = reinterpret_cast<const float2 *>(bd.ws + pl->off_win);
+        ga.ctrl = ctrl;
+        ga.ctrlw = ctrl;
+        ga.T = reinterpret_cast<float2 *>(T);
+        if (aux && mode == 0) {
+            ga.S = reinterpret_cast<float2 *>(aux->S);
+            ga.Sd = reinterpret_cast<float2 *>(aux->Sd);
+            ga.idx = aux->idx;
+        }
+        ga.L = pl->p.win_len;
+        ga.M = pl->M;
+        ga.hop = pl->p.hop;
+        ga.k1 = pl->k1;
+        ga.n_src = pl->n_src;
+        ga.n_dst = pl->n_dst;
+        ga.z = pl->p.subdiv;
+        ga.row_tiles = pl->row_tiles;
+        ga.ksteps = pl->ksteps;
+        ga.slab = pl->slab;
+        ga.unscale_g = pl->unscale_g;
+        ga.unscale_gd = pl->unscale_gd;
+        ga.cdelta = (float)(pl->p.nfft / kTwoPi);
+        ga.bound_c = (float)(1.1 * std::sqrt(2.0 * pl->n_src * pl->p.nfft));
+        ga.gmax2 = pl->gmax2;
+        ga.mode = mode;
+        ga.tile_step = 1;
+        ga.thr_mode = pl->p.thr_mode;
+        ga.thr = (float)pl->p.thr;
+        ga.smin = reinterpret_cast<float *>(bd.ws + pl->off_smin);
+        ga.list = list;
+        ga.list_n = list_n;
+        return ga;
+    };
+    auto gemm_grid = [&](int64_t visits) {
+        return (int)(visits < bd.fwd_grid_cap ? visits : bd.fwd_grid_cap);
+    };
     if (threshold && !fft) {
-        g.item_begin = 0;
-        g.item_stop = d.mitem_end;
-        const int grid = (int)(d.mitem_end < bd.max_grid_cap ? d.mitem_end : bd.max_grid_cap);
-        e = sst::launch_threshold(NF, pl->p.win_len, g, grid, s);
+        // gamma on the tier's own arithmetic: the maximum over every tile of
+        // the signal (a max-only pass), unless the speculative forward below
+        // finds it as it goes
+        if (rel && !spec) {
+            const int64_t tiles_all = (pl->n_frames + pl->gemm_ft - 1) / pl->gemm_ft;
+            const sst::GemmArgs gm = gemm_args(0, pl->n_frames, 1);
+            if (tiles_all > 0)
+                e = sst::launch_gemm_forward(pl->p.precision, pl->gemm_ft, false, gm,
+                                             gemm_grid(tiles_all), s);
+        }
+        if (e == hipSuccess && !spec)
+            e = sst::launch_gamma(g, s);
         if (e != hipSuccess)
             return hip_fail(e, "threshold launch");
-        bd.gamma_valid = true;
+        bd.gamma_valid = !spec;
     } else if (threshold) {
         g.item_begin = 0;
         g.item_stop = d.mitem_end;
@@ -831,46 +884,48 @@ static sst_status forward_impl(sst_plan_s *pl, Bound &bd, const float *x, int64_
     if (pl->gemm_ft) {
         if (aux && aux->colstats)
             return fail(SST_E_UNSUPPORTED, "colstats are not produced by the GEMM tiers");
-        sst::GemmArgs ga{};
-        ga.x = x;
-        ga.n = pl->p.n_samples;
-        ga.frame0 = frame0;
-        ga.nframes = nframes;
-        ga.afrag = bd.ws + pl->off_afrag;
-        ga.afrag_lo = pl->off_afrag_lo ? bd.ws + pl->off_afrag_lo : nullptr;
-        ga.win = reinterpret_cast<const float2 *>(bd.ws + pl->off_win);
-        ga.ctrl = ctrl;
-        ga.T = reinterpret_cast<float2 *>(T);
-        if (aux) {
-            ga.S = reinterpret_cast<float2 *>(aux->S);
-            ga.Sd = reinterpret_cast<float2 *>(aux->Sd);
-            ga.idx = aux->idx;
-        }
-        ga.L = pl->p.win_len;
-        ga.M = pl->M;
-        ga.hop = pl->p.hop;
-        ga.k1 = pl->k1;
-        ga.n_src = pl->n_src;
-        ga.n_dst = pl->n_dst;
-        ga.z = pl->p.subdiv;
-        ga.row_tiles = pl->row_tiles;
-        ga.ksteps = pl->ksteps;
-        ga.slab = pl->slab;
-        ga.unscale_g = pl->unscale_g;
-        ga.unscale_gd = pl->unscale_gd;
-        ga.cdelta = (float)(pl->p.nfft / kTwoPi);
-        ga.bound_c = (float)(1.1 * std::sqrt(2.0 * pl->n_src * pl->p.nfft));
-        ga.gmax2 = pl->gmax2;
         const int64_t tiles = (nframes + pl->gemm_ft - 1) / pl->gemm_ft;
-        const int grid = (int)(tiles < bd.fwd_grid_cap ? tiles : bd.fwd_grid_cap);
         const bool dbg = aux && (aux->S || aux->Sd || aux->idx);
+        if (spec) {
+            // seed the running maximum with every k-th tile (max-only)
+            sst::GemmArgs gs = gemm_args(0, nframes, 1);
+            gs.tile_step = seed_step(tiles, bd.fwd_grid_cap, pl->tune.seed_step);
+            e = sst::launch_gemm_forward(pl->p.precision, pl->gemm_ft, false, gs,
+                                         gemm_grid((tiles + gs.tile_step - 1) / gs.tile_step), s);
+            if (e != hipSuccess)
+                return hip_fail(e, "GEMM threshold seed launch");
+        }
+        sst::GemmArgs ga = gemm_args(frame0, nframes, 0);
+        ga.spec = spec ? 1 : 0;
         e = record_event(aux, 0, s);
         if (e == hipSuccess)
-            e = sst::launch_gemm_forward(pl->p.precision, pl->gemm_ft, dbg, ga, grid, s);
+            e = sst::launch_gemm_forward(pl->p.precision, pl->gemm_ft, dbg, ga, gemm_grid(tiles), s);
         if (e == hipSuccess)
             e = record_event(aux, 1, s);
         if (e != hipSuccess)
             return hip_fail(e, "GEMM forward launch");
+        if (!spec)
+            return SST_OK;
+        // gamma, the list of tiles that kept a coefficient at or below it, and
+        // those tiles again at the final gamma
+        g.item_begin = 0;
+        g.item_stop = tiles;
+        g.smin = reinterpret_cast<float *>(bd.ws + pl->off_smin);
+        g.list = list;
+        g.list_n = list_n;
+        e = sst::launch_spec_list(g, s);
+        if (e == hipSuccess)
+            bd.gamma_valid = true;
+        if (e == hipSuccess)
+            e = sst::launch_gemm_forward(pl->p.precision, pl->gemm_ft, false,
+                                         gemm_args(0, nframes, 2), gemm_grid(tiles), s);
+        if (e != hipSuccess)
+            return hip_fail(e, "GEMM speculative fix-up launch");
+        if (aux && aux->gamma) {
+            e = hipMemcpyAsync(aux->gamma, &ctrl->gamma, sizeof(float), hipMemcpyDeviceToDevice, s);
+            if (e != hipSuccess)
+                return hip_fail(e, "hipMemcpyAsync(gamma)");
+        }
         return SST_OK;
     }
     g.item_begin = 0;
@@ -1223,8 +1278,13 @@ sst_status sst_autotune(sst_plan_t pl, const float *x, float *T, const int32_t *
     // forward: resident workgroups per CU x seed step of the speculative threshold
     const int occ = pl->bd.fwd_occ > 0 ? pl->bd.fwd_occ : 1;
     float best_ms = -1.f;
+    // seed steps: frame groups of the FFT tier; GEMM tiles (1 = the exact
+    // maximum first, so no tile is redone)
+    const int seeds_fft[3] = {0, 16, 128}, seeds_gemm[3] = {0, 1, 4};
+    const int *seeds = pl->gemm_ft ? seeds_gemm : seeds_fft;
     for (int wg = occ; wg >= 1 && wg >= occ - 2 && st == SST_OK; --wg)
-        for (int seed : {0, 16, 128}) {
+        for (int si = 0; si < 3; ++si) {
+            const int seed = seeds[si];
             sst_tuning t = cur;
             t.fwd_wg_per_cu = wg;
             t.seed_step = seed;
@@ -1307,7 +1367,7 @@ struct sst_batch_s {
         int max_L = 0, max_n_src = 0, max_n_dst = 0;
         size_t off_desc = 0;        // ChanDesc[chans.size()]
         std::vector<sst::ChanDesc> desc;
-        int fwd_grid_cap = 0, max_grid_cap = 0;
+        int fwd_grid_cap = 0;
         // speculative forward: least kept |S|^2 per item of the group, fix-up list
         int64_t n_items = 0;
         size_t off_smin = 0, off_list = 0, off_list_n = 0;
@@ -1445,10 +1505,8 @@ sst_status sst_batch_bind(sst_batch_t b, void *workspace, size_t bytes, void *st
     for (auto &gr : b->groups) {
         const sst_plan_s *p0 = b->plans[(size_t)gr.chans[0]];
         gr.fwd_grid_cap = p0->bd.fwd_grid_cap;
-        gr.max_grid_cap = p0->bd.max_grid_cap;
         for (int c : gr.chans) {
             gr.fwd_grid_cap = std::max(gr.fwd_grid_cap, b->plans[(size_t)c]->bd.fwd_grid_cap);
-            gr.max_grid_cap = std::max(gr.max_grid_cap, b->plans[(size_t)c]->bd.max_grid_cap);
         }
     }
     b->ws = ws;

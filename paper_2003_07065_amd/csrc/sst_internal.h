@@ -146,6 +146,21 @@ struct GemmArgs {
     float cdelta;           // N_f / (2 pi)
     float bound_c;          // 1.1 sqrt(2 n_src N_f)
     float gmax2;            // max_j g[j]^2
+    // Threshold (relative gamma on the tier's own arithmetic):
+    //   mode 0: forward of every tile; spec: gamma from the running maximum
+    //     (a lower bound), recording each tile's least kept |S|^2 in smin and
+    //     folding its max |S|^2 into ctrl->maxbits;
+    //   mode 1: max |S|^2 only, of every tile_step-th tile, into ctrl->maxbits;
+    //   mode 2: forward of the tiles listed in list[0 .. *list_n).
+    int mode;
+    int spec;
+    int64_t tile_step;
+    int thr_mode;
+    float thr;
+    Ctrl *ctrlw;            // the same control block, written (maxbits)
+    float *smin;            // [tiles]
+    const int32_t *list;
+    const int32_t *list_n;
 };
 
 // Arguments of the ridge kernel.
@@ -191,11 +206,8 @@ struct RenyiArgs {
 hipError_t launch_renyi(const RenyiArgs &a, int kind, hipStream_t s);
 
 // Launchers (sst_kernels.hip).  Each returns the hipError_t of its launch.
-// Threshold of the GEMM tiers: clears maxbits of the launch's channels, runs
-// the two-frames-per-FFT pre-pass over items [item_begin, item_stop) when
-// there are any and sets gamma of every channel of the list.
-hipError_t launch_threshold(int nfft, int L, const GroupLaunch &g, int grid, hipStream_t s);
-// Pieces of the threshold of the FFT path.  launch_clear_max zeroes maxbits of
+// Pieces of the threshold of the FFT path (launch_gamma and launch_spec_list
+// serve the GEMM tiers too).  launch_clear_max zeroes maxbits of
 // every channel (and *g.list_n); launch_max_prepass folds max |S|^2 of every
 // g.step-th forward item of the whole signals (items numbered by mitem0, with
 // the forward kernel's own arithmetic) into maxbits; launch_gamma sets gamma.
@@ -245,7 +257,6 @@ int fwd_frames_per_iter(int nfft);   // F
 int fwd_threads(int nfft);           // threads per workgroup
 int fwd_lds_elems(int nfft);         // float2 capacity of the LDS buffer
 int fwd_occupancy(int nfft, int L);  // resident workgroups per CU (forward)
-int max_occupancy(int nfft, int L);  // resident workgroups per CU (threshold pre-pass)
 int fwd_rounds(int nfft, int n_src);          // coefficient rounds per thread: 3, 5 or 9
 size_t fwd_lds_bytes(int nfft);               // LDS of the forward kernel
 

@@ -12,8 +12,6 @@
 //                   frame groups.
 //   spec_list_kernel -- gamma after a speculative forward and the list of
 //                   frame groups that the final gamma changes.
-//   max_kernel   -- max |S| over every frame, two frames per FFT (the GEMM
-//                   tiers' threshold pre-pass).
 //   inv_kernel   -- the direct downsampled inverse (Sec. 2.3, Eqs. 25-26, zN_f
 //                   phase grid of the band / subdivision remark of Sec. 2.5),
 //                   its window contraction on the FP16 matrix cores with
@@ -1145,7 +1143,7 @@ template <int NF>
 __global__ __launch_bounds__(Geo<NF>::NT) void syn_kernel(SynArgs a)
 {
     using G = Geo<NF>;
-    constexpr int F = G::F, NT = G::NT, Q = NF / 16, NHI = NF / 64;
+    constexpr int F = G::F, NT = G::NT, NHI = NF / 64;
     constexpr int TS = kSynTile, PER = TS / NT;
     static_assert(TS % NT == 0, "a tile is a whole number of sample rounds");
     __shared__ v2 lds[G::LDS];
@@ -1287,125 +1285,6 @@ __global__ __launch_bounds__(256) void spec_list_kernel(GroupLaunch g)
         at = __shfl(at, 0, 64);
         if (redo)
             g.list[at + __popcll(bal & ((1ull << lane) - 1ull))] = (int32_t)it;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Threshold pre-pass of the GEMM tiers: max |S|^2 over all frames, two frames
-// per complex FFT.
-// ---------------------------------------------------------------------------
-
-template <int NF, int NZ>
-__global__ __launch_bounds__(Geo<NF>::NT, (NF == 8192 || (NF == 4096 && NZ < 16)) ? 4 : 3) void max_kernel(GroupLaunch g)
-{
-    using G = Geo<NF>;
-    constexpr int F = G::F, NT = G::NT, Q = NF / 16;
-    __shared__ v2 lds[G::LDS];
-    __shared__ float red[NT / 64];
-    __shared__ v2 twl[Twiddles<NF>::TW];
-    Twiddles<NF> tw;
-    tw.load(twl, reinterpret_cast<const v2 *>(g.twid));
-    const CA ChanDesc *ch = (const CA ChanDesc *)g.ch;
-
-    // Pass-1 role: frame pair f1 of the iteration, taps jj + r Q.  The pair
-    // (2p, 2p+1) is packed as one complex signal g x_2p + i g x_2p+1.
-    const int f1 = threadIdx.x / Q, jj = threadIdx.x % Q;
-    float gw[NZ];
-    float xa[NZ], xb[NZ];
-    int oka = 0, okb = 0;
-    auto fetch = [&](int64_t it, const Chan &d, bool new_chan) {
-        const int64_t n_pairs = (d.n_frames + 1) / 2;
-        const bool iv = it < g.item_stop;
-        const int64_t p = (iv ? it - d.item0 : 0) * F + f1;   // pair index
-        const bool pv = iv & (p < n_pairs);
-        const int cm = (int)(2 * (pv ? p : 0) * (int64_t)d.hop - d.M) + jj;
-        const bool bv = pv & (2 * p + 1 < d.n_frames);
-        const float *__restrict__ x = d.x;
-        const unsigned n = (unsigned)d.n;
-        oka = 0;
-        okb = 0;
-#pragma unroll
-        for (int r = 0; r < NZ; ++r) {
-            const int sa = cm + r * Q, sb = sa + d.hop;
-            const bool ga = pv & ((unsigned)sa < n);
-            const bool gb = bv & ((unsigned)sb < n);
-            xa[r] = x[ga ? (unsigned)sa : 0u];
-            xb[r] = x[gb ? (unsigned)sb : 0u];
-            oka |= (int)ga << r;
-            okb |= (int)gb << r;
-        }
-        if (new_chan) {
-#pragma unroll
-            for (int r = 0; r < NZ; ++r) {
-                const int tap = jj + r * Q;
-                gw[r] = tap < d.L ? reinterpret_cast<const v2 *>(d.win)[(unsigned)tap].x : 0.f;
-            }
-        }
-    };
-    int64_t it = g.item_begin + blockIdx.x;
-    int c = chan_of<true>(ch, g.n_ch, 0, it);
-    Chan a = load_chan<true>(ch, c);
-    fetch(it, a, true);
-    float best = 0.f;
-
-    for (; it < g.item_stop; it += gridDim.x) {
-        const int64_t n_pairs = (a.n_frames + 1) / 2;
-        const int64_t p0 = (it - a.item0) * F;
-        const int nvp = (int)((n_pairs - p0) < F ? (n_pairs - p0) : F);
-        const float inv_nsrc = a.inv_nsrc;
-        {
-            v2 v[16];
-#pragma unroll
-            for (int r = 0; r < 16; ++r)
-                v[r] = (r < NZ) ? mk((((oka >> r) & 1) ? xa[r] : 0.f) * gw[r],
-                                     (((okb >> r) & 1) ? xb[r] : 0.f) * gw[r])
-                                : mk(0.f, 0.f);
-            if constexpr (NZ == 4)
-                dft16_nz4(v);
-            else if constexpr (NZ == 8)
-                dft16_nz8(v);
-            else
-                dft16(v);
-            const int base = f1 * NF + jj * 16;
-#pragma unroll
-            for (int r = 0; r < 16; ++r)
-                lds[pad16(base) + r] = v[r];   // base: a multiple of 16
-        }
-        const int64_t itn = it + gridDim.x;
-        Chan an = a;
-        const bool chg = itn < g.item_stop && itn >= a.item_end;
-        if (chg) {
-            c = chan_of<true>(ch, g.n_ch, c, itn);
-            an = load_chan<true>(ch, c);
-        }
-        fetch(itn, an, chg);
-        __syncthreads();
-        tw.passes(lds, twl);
-        const int E = nvp * a.n_src;
-        for (int e = threadIdx.x; e < E; e += NT) {
-            int f, ik;
-            if constexpr (F == 1) {
-                f = 0;
-                ik = e;
-            } else {
-                split_flat(e, a.n_src, inv_nsrc, f, ik);
-            }
-            const int k = a.k1 + ik;
-            const v2 P = lds[pad16(f * NF + k)];
-            const v2 Qc = conjv(lds[pad16(f * NF + ((NF - k) & (NF - 1)))]);
-            const v2 Aa = 0.5f * (P + Qc);
-            const v2 D = P - Qc;   // A_b = -i D / 2
-            const float ma2 = Aa.x * Aa.x + Aa.y * Aa.y;
-            const float mb2 = 0.25f * (D.x * D.x + D.y * D.y);
-            best = fmaxf(best, fmaxf(ma2, mb2));
-        }
-        __syncthreads();   // LDS reads done before the next iteration's pass 1
-        if (chg || itn >= g.item_stop) {
-            // leaving this channel: fold the workgroup's maximum into it
-            block_max_flush<NT>(best, red, &a.ctrl->maxbits);
-            best = 0.f;
-        }
-        a = an;
     }
 }
 
@@ -2560,18 +2439,6 @@ hipError_t launch_maxonly_t(int L, const GroupLaunch &gl, int grid, hipStream_t 
     }
 }
 
-template <int NF>
-hipError_t launch_max_t(int L, const GroupLaunch &gl, int grid, hipStream_t s)
-{
-    const dim3 g(grid), b(Geo<NF>::NT);
-    switch (nz_rows<NF>(L)) {
-    case 4: hipLaunchKernelGGL((max_kernel<NF, 4>), g, b, 0, s, gl); break;
-    case 8: hipLaunchKernelGGL((max_kernel<NF, 8>), g, b, 0, s, gl); break;
-    default: hipLaunchKernelGGL((max_kernel<NF, 16>), g, b, 0, s, gl); break;
-    }
-    return hipGetLastError();
-}
-
 template <typename K>
 int occ_of(K kernel, int threads, size_t dyn = 0)
 {
@@ -2589,16 +2456,6 @@ int occ_fwd_t(int L)
     case 4: return occ_of(fwd_kernel<NF, 4, 9, false, true, true>, Geo<NF>::NT);
     case 8: return occ_of(fwd_kernel<NF, 8, 9, false, true, true>, Geo<NF>::NT);
     default: return occ_of(fwd_kernel<NF, 16, 9, false, true, true>, Geo<NF>::NT);
-    }
-}
-
-template <int NF>
-int occ_max_t(int L)
-{
-    switch (nz_rows<NF>(L)) {
-    case 4: return occ_of(max_kernel<NF, 4>, Geo<NF>::NT);
-    case 8: return occ_of(max_kernel<NF, 8>, Geo<NF>::NT);
-    default: return occ_of(max_kernel<NF, 16>, Geo<NF>::NT);
     }
 }
 
@@ -2621,23 +2478,6 @@ int fwd_rounds(int nfft, int n_src)
     case 8192: { constexpr int NFv = 8192; EXPR; }  \
     default: break;                                 \
     }
-
-hipError_t launch_threshold(int nfft, int L, const GroupLaunch &g, int grid, hipStream_t s)
-{
-    const unsigned cb = (unsigned)((g.n_ch + 255) / 256);
-    hipLaunchKernelGGL(clear_max_kernel, dim3(cb), dim3(256), 0, s, g);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess)
-        return e;
-    if (g.item_stop > g.item_begin && grid > 0) {
-        e = hipErrorInvalidValue;
-        SST_DISPATCH_NF(nfft, e = launch_max_t<NFv>(L, g, grid, s); break)
-        if (e != hipSuccess)
-            return e;
-    }
-    hipLaunchKernelGGL(gamma_kernel, dim3(cb), dim3(256), 0, s, g);
-    return hipGetLastError();
-}
 
 hipError_t launch_clear_max(const GroupLaunch &g, hipStream_t s)
 {
@@ -2813,12 +2653,6 @@ int fwd_occupancy(int nfft, int L)
     SST_DISPATCH_NF(nfft, return occ_fwd_t<NFv>(L))
     return 1;
 }
-int max_occupancy(int nfft, int L)
-{
-    SST_DISPATCH_NF(nfft, return occ_max_t<NFv>(L))
-    return 1;
-}
-
 // ---------------------------------------------------------------------------
 // Fixed device scratch for callers that cannot allocate (sst_forward_static).
 // Each device holds its own copy of the array for the life of the process.

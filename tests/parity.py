@@ -84,8 +84,11 @@ ZONE_MULT = 4.0   # D24(ii): flips accepted within max(1e-4, 4 e_u) of the bound
 
 
 def classify_indices(idx_g, idx_o, frac_o, S_o, Sd_o, gamma_o, nfft, z, s_pack, ny, n_dst=None,
-                     err_s=None, err_sd=None):
+                     err_s=None, err_sd=None, gamma_g=None):
     """Compare destination indices (see module doc).  ny[m] = ||y_m|| per frame.
+
+    gamma_g: the GPU's threshold when it comes from a different arithmetic
+    (the matrix-core tiers).
 
     err_s / err_sd (per frame) replace the FP32 FFT error model by the caller's
     worst-case bound on the absolute error of S and S' (the matrix-core tiers):
@@ -121,6 +124,10 @@ def classify_indices(idx_g, idx_o, frac_o, S_o, Sd_o, gamma_o, nfft, z, s_pack, 
             e_u = c * 2.0 ** -24 * ny[:, None] * (1.0 / (s_pack * mag) + np.abs(Sd_o) / (mag * mag))
             near = np.abs(mag - gamma_o) <= 1e-5 * gamma_o
             tol = np.maximum(1e-4, ZONE_MULT * e_u)
+    if gamma_g is not None:
+        # a tier whose gamma comes from its own arithmetic: coefficients whose
+        # |S| lies between the two thresholds may be retained by one side only
+        near = near | ((mag - gamma_o) * (mag - gamma_g) <= 0.0)
     flip = diff & both
     gi = idx_g.astype(np.float64)
     with np.errstate(invalid="ignore"):

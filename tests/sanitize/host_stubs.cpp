@@ -8,7 +8,6 @@
 
 namespace sst {
 
-hipError_t launch_threshold(int, int, const GroupLaunch &, int, hipStream_t) { return hipErrorNoDevice; }
 hipError_t launch_clear_max(const GroupLaunch &, hipStream_t) { return hipErrorNoDevice; }
 hipError_t launch_max_prepass(int, int, const GroupLaunch &, int, hipStream_t) { return hipErrorNoDevice; }
 hipError_t launch_gamma(const GroupLaunch &, hipStream_t) { return hipErrorNoDevice; }
@@ -31,7 +30,6 @@ int fwd_frames_per_iter(int nfft) { return nfft >= 4096 ? 1 : 4096 / nfft; }
 int fwd_threads(int nfft) { return nfft > 4096 ? nfft / 16 : 256; }
 int fwd_lds_elems(int nfft) { const int v = nfft > 4096 ? nfft : 4096; return v + v / 16; }
 int fwd_occupancy(int, int) { return 1; }
-int max_occupancy(int, int) { return 1; }
 int fwd_rounds(int, int) { return 9; }
 size_t fwd_lds_bytes(int nfft) { return 8 * (size_t)fwd_lds_elems(nfft); }
 
