@@ -189,6 +189,22 @@ sst::ChanDesc chan_desc(const sst_plan_s *pl, const unsigned char *ws, const flo
     return d;
 }
 
+// Words per residue row of the decimated inverse window table: at least
+// (2 JL) / H + 2 (JL = M + 63 + 16 H), rounded up to a stride whose residue
+// mod 64 spreads the lanes' reads over the LDS banks (each lane of a wave
+// reads its own residue row; of the strides, these residues leave the fewest
+// lanes sharing a bank over a range of hops).
+int inv_dec_row(int M, int hop)
+{
+    const int reach = M + 63 + 16 * hop;
+    int tr = (2 * reach) / hop + 2;
+    for (;; ++tr) {
+        const int m = tr & 63;
+        if (m == 6 || m == 10 || m == 26 || m == 38 || m == 42)
+            return tr;
+    }
+}
+
 // Descriptor of one channel's inverse over frames [frame0, frame0 + nframes).
 sst::InvDesc inv_desc(const sst_plan_s *pl, const float *T, int64_t frame0, int64_t nframes,
                       const int32_t *ridge, int n_comp, int hw, float *xhat, const float *xref,
@@ -225,7 +241,7 @@ sst::InvDesc inv_desc(const sst_plan_s *pl, const float *T, int64_t frame0, int6
     a.g_scale = pl->inv_g_scale;
     a.g_unscale = pl->inv_g_unscale;
     a.dec_reach = pl->M + 63 + 16 * pl->p.hop;
-    a.dec_row = (2 * a.dec_reach) / pl->p.hop + 2;
+    a.dec_row = inv_dec_row(pl->M, pl->p.hop);
     a.accumulate = accumulate ? 1 : 0;
     if (frame0 == 0 && nframes == pl->n_frames) {
         a.span_lo = 0;
@@ -269,8 +285,7 @@ bool inv_wide_fits(const sst_plan_s *pl)
 // Words of the plan's decimated inverse window table (InvDesc::dec_row times the hop).
 int inv_dec_words(const sst_plan_s *pl)
 {
-    const int reach = pl->M + 63 + 16 * pl->p.hop;
-    return pl->p.hop * ((2 * reach) / pl->p.hop + 2);
+    return pl->p.hop * inv_dec_row(pl->M, pl->p.hop);
 }
 
 // max_dec: the largest decimated window table of the list (inv_dec_words);

@@ -1477,34 +1477,39 @@ __host__ __device__ inline int inv_group_kbp(int max_k)
     return ((max_k + 15) & ~15) + 8;
 }
 
-// Window contraction of one wave's 64 samples (sample group cg of the tile)
-// over the staged frames [kb, kb + kn) of the tile: acc0 and acc1 (columns
-// 0..31 and 32..63) accumulate Z 2^(sc + tg) = sum_m c~[m, d] g[n - mH].
-// Only the frames whose windows reach the wave's samples are visited (the
-// others meet g = 0 in every column of the wave), in steps of 16 from a
-// multiple of 16 (the staged rows are zero past kn).  ZERO: the sums start
-// here (the first step's products take a zero accumulator in place of acc).
-template <bool DEC, int KBP, bool ZERO>
-__device__ __forceinline__ void wave_mfma(f32x16 &acc0, f32x16 &acc1, const unsigned short *aph,
-                                          const unsigned short *apl, const unsigned *gpk,
-                                          int tile_lo, int cg, int wave, int col, int half, int mlo,
-                                          int kb, int kn, int M, int H, int JL, int TR, float invH)
+// The frame steps of one wave's 64 samples (sample group cg of the tile) over
+// the staged frames [kb, kb + kn): steps of 16 from kw0 (a multiple of 16,
+// relative to kb) while k0 <= kw1, covering the frames whose windows reach
+// the wave's samples (the others meet g = 0 in every column of the wave).
+// Uniform over the wave, packed as kw0 | (kw1 + 1) << 16 (0 <= kw0, kw1 + 1
+// < 2^15).  Then the lane's window addressing: j0 = n - m H of
+// its first frame (k0 + 8 half) for column 0; with the decimated table, the
+// word offsets (from the table's start) of that frame's residue row entries
+// for columns 0 and 31 + 1, packed as off0 | off1 << 16.
+struct WaveSteps {
+    int kw;     // packed kw0, kw1
+    int lane;   // DEC: packed offsets; otherwise j0
+};
+template <bool DEC>
+__device__ __forceinline__ WaveSteps wave_steps(int tile_lo, int cg, int wave, int col, int half,
+                                                int mlo, int kb, int kn, int M, int H, int JL,
+                                                int TR, float invH)
 {
+    WaveSteps w;
     const int w_lo = tile_lo + 256 * cg + 64 * __builtin_amdgcn_readfirstlane(wave);
     const int wm_lo = w_lo - M > 0 ? (w_lo - M + H - 1) / H : 0;
     const int wm_hi = (w_lo + 63 + M) / H;
     int kw0 = wm_lo - mlo - kb, kw1 = wm_hi - mlo - kb;
     kw0 = kw0 > 0 ? kw0 & ~15 : 0;
     kw1 = kw1 < kn - 1 ? kw1 : kn - 1;
-    // j = n - m H of the lane's first frame (k0 + 8 half) for column 0
-    int j0 = w_lo + col - mlo * H - (kb + kw0 + 8 * half) * H;
-    // DEC: the lane's 8 values g[j - i H], i = 0..7, are the words p[7 - i] of
-    // its residue row; a step of 16 frames moves p by -16.  Every j a step
-    // reaches lies within JL of 0: the steps start up to 15 frames before the
-    // wave's first frame and end up to 15 after its last, and a wave spans 64
-    // samples, so |j| <= M + 63 + 15 H.
-    const unsigned *pc0 = gpk, *pc1 = gpk;
+    w.kw = kw0 | ((kw1 < 0 ? 0 : kw1 + 1) << 16);
+    const int j0 = w_lo + col - mlo * H - (kb + kw0 + 8 * half) * H;
     if constexpr (DEC) {
+        // The lane's 8 values g[j - i H], i = 0..7, are the words p[7 - i] of
+        // its residue row; a step of 16 frames moves p by -16.  Every j a step
+        // reaches lies within JL of 0: the steps start up to 15 frames before
+        // the wave's first frame and end up to 15 after its last, and a wave
+        // spans 64 samples, so |j| <= M + 63 + 15 H.
         // u0 = q0 H + r0 and u1 = u0 + 32 = q1 H + r1, 0 <= u0 < 2^24: the
         // float quotient is within one of the exact one, then corrected
         const int u0 = j0 + JL;
@@ -1517,8 +1522,30 @@ __device__ __forceinline__ void wave_mfma(f32x16 &acc0, f32x16 &acc1, const unsi
         int r1 = u1 - q1 * H;
         q1 += r1 >= H ? 1 : (r1 < 0 ? -1 : 0);
         r1 = u1 - q1 * H;
-        pc0 = gpk + r0 * TR + q0 - 7;
-        pc1 = gpk + r1 * TR + q1 - 7;
+        // every word read lies in the table (fewer than 2^16 words)
+        w.lane = (r0 * TR + q0 - 7) | ((r1 * TR + q1 - 7) << 16);
+    } else {
+        w.lane = j0;
+    }
+    return w;
+}
+
+// Window contraction of one wave's 64 samples over the steps ws: acc0 and
+// acc1 (columns 0..31 and 32..63) accumulate Z 2^(sc + tg) =
+// sum_m c~[m, d] g[n - mH] (the staged rows are zero past kn).  ZERO: the
+// sums start here (the first step's products take a zero accumulator in
+// place of acc); returns false, leaving acc untouched, when no frame reaches
+// the wave's samples (the sums are zero).
+template <bool DEC, int KBP, bool ZERO>
+__device__ __forceinline__ bool wave_mfma(f32x16 &acc0, f32x16 &acc1, const unsigned short *aph,
+                                          const unsigned short *apl, const unsigned *gpk,
+                                          const WaveSteps &ws, int M, int H)
+{
+    int j0 = ws.lane;
+    const unsigned *pc0 = gpk, *pc1 = gpk;
+    if constexpr (DEC) {
+        pc0 = gpk + (ws.lane & 0xffff);
+        pc1 = gpk + ((unsigned)ws.lane >> 16);
     }
     // one step of 16 frames; FRESH: the first step of a fresh sum, whose
     // products take a zero accumulator operand (no register clearing)
@@ -1562,18 +1589,17 @@ __device__ __forceinline__ void wave_mfma(f32x16 &acc0, f32x16 &acc1, const unsi
         pc0 -= 16;
         pc1 -= 16;
     };
-    int k0 = kw0;
+    int k0 = ws.kw & 0xffff;
+    const int kw1 = (ws.kw >> 16) - 1;
     if constexpr (ZERO) {
-        if (k0 > kw1) {   // no frame reaches the wave's samples
-            acc0 = f32x16{};
-            acc1 = f32x16{};
-            return;
-        }
+        if (k0 > kw1)   // no frame reaches the wave's samples
+            return false;
         step(k0, IntC<1>{});
         k0 += 16;
     }
     for (; k0 <= kw1; k0 += 16)
         step(k0, IntC<0>{});
+    return true;
 }
 
 // ONE: every tile's frames fit one staged block (K <= KB), so the sums start
@@ -1692,6 +1718,16 @@ __global__ __launch_bounds__(256, TF > 1 ? 4 : (ONE ? (DEC ? 6 : 5) : 4)) void i
     const v2 *__restrict__ Trow = reinterpret_cast<const v2 *>(a.T) + (int64_t)(mlo - frame0) * a.n_dst;
     const unsigned short *aph = ahi + col * KBP + 8 * half;   // this lane's A row and k chunk
     const unsigned short *apl = alo + col * KBP + 8 * half;
+    // ONE with the decimated table: each sample group's frame steps and
+    // window addressing do not depend on the destination group; they are set
+    // once per tile (the clamped-table variants, short of registers, set
+    // them per group)
+    WaveSteps wst[ONE && DEC ? TF : 1];
+    if constexpr (ONE && DEC) {
+#pragma unroll
+        for (int cg = 0; cg < TF; ++cg)
+            wst[cg] = wave_steps<DEC>(tile_lo, cg, wave, col, half, mlo, 0, K, M, H, JL, TR, invH);
+    }
     float y[TF][2];
 #pragma unroll
     for (int cg = 0; cg < TF; ++cg)
@@ -1753,10 +1789,6 @@ __global__ __launch_bounds__(256, TF > 1 ? 4 : (ONE ? (DEC ? 6 : 5) : 4)) void i
             sb = sb > 100 ? 100 : (sb < -100 ? -100 : sb);   // 2^sb stays a normal float
             if (kb == 0) {
                 sc = sb;
-                if constexpr (ONE) {
-                    acc0 = f32x16{};
-                    acc1 = f32x16{};
-                }
             } else if (sb < sc) {
                 // a later block needs a smaller power: rescale the sums (exact)
                 const float f = ldexpf(1.f, sb - sc);
@@ -1784,8 +1816,9 @@ __global__ __launch_bounds__(256, TF > 1 ? 4 : (ONE ? (DEC ? 6 : 5) : 4)) void i
             }
             __syncthreads();
             if constexpr (!ONE) {
-                wave_mfma<DEC, KBP, false>(acc0, acc1, aph, apl, gpk, tile_lo, 0, wave, col, half,
-                                           mlo, kb, kn, M, H, JL, TR, invH);
+                const WaveSteps ws = wave_steps<DEC>(tile_lo, 0, wave, col, half, mlo, kb, kn, M, H,
+                                                     JL, TR, invH);
+                wave_mfma<DEC, KBP, false>(acc0, acc1, aph, apl, gpk, ws, M, H);
             }
         }
         // rows 8 (i/4) + 4 half + i mod 4 = 2 dd + p: dd = 4 (i/4) + 2 half + (i mod 4) / 2
@@ -1794,8 +1827,13 @@ __global__ __launch_bounds__(256, TF > 1 ? 4 : (ONE ? (DEC ? 6 : 5) : 4)) void i
 #pragma unroll
         for (int cg = 0; cg < TF; ++cg) {
             if constexpr (ONE) {
-                wave_mfma<DEC, KBP, true>(acc0, acc1, aph, apl, gpk, tile_lo, cg, wave, col, half,
-                                          mlo, 0, K, M, H, JL, TR, invH);
+                WaveSteps ws;
+                if constexpr (DEC)
+                    ws = wst[cg];
+                else
+                    ws = wave_steps<DEC>(tile_lo, cg, wave, col, half, mlo, 0, K, M, H, JL, TR, invH);
+                if (!wave_mfma<DEC, KBP, true>(acc0, acc1, aph, apl, gpk, ws, M, H))
+                    continue;   // no frame reaches these samples: the sums are zero
             }
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
@@ -1804,17 +1842,23 @@ __global__ __launch_bounds__(256, TF > 1 ? 4 : (ONE ? (DEC ? 6 : 5) : 4)) void i
                 nm = nm >= G ? nm - G : nm;
                 nm = nm >= G ? nm - G : nm;
                 const v2 w = phasor(tlo, thi, (int)nm, a.lo_bits);                             // e^{i 2 pi n/G}
-                v2 e = phasor(tlo, thi, mulmod(bb, nm, Gi, a.g_pow2, a.inv_G), a.lo_bits);   // bin bb
-                const v2 w4 = cmul(cmul(w, w), cmul(w, w));
+                const v2 e = phasor(tlo, thi, mulmod(bb, nm, Gi, a.g_pow2, a.inv_G), a.lo_bits);   // bin bb
+                const v2 w2 = cmul(w, w), w4 = cmul(w2, w2);
                 const f32x16 &acc = c ? acc1 : acc0;
-                float t = 0.f;
+                // sum over the lane's 8 rows of Re(e w^(4 g + s) Z): with
+                // V_g = Z_(g,0) + w Z_(g,1), the sum is Re(e P), P = sum_g w4^g V_g
+                // (Horner in w4)
+                auto vg = [&](int g4) {
+                    return mk(fmaf(w.x, acc[4 * g4 + 2], fmaf(-w.y, acc[4 * g4 + 3], acc[4 * g4])),
+                              fmaf(w.x, acc[4 * g4 + 3], fmaf(w.y, acc[4 * g4 + 2], acc[4 * g4 + 1])));
+                };
+                v2 p = vg(3);
 #pragma unroll
-                for (int g4 = 0; g4 < 4; ++g4) {
-                    const v2 e1 = cmul(e, w);   // next bin
-                    t += e.x * acc[4 * g4] - e.y * acc[4 * g4 + 1];
-                    t += e1.x * acc[4 * g4 + 2] - e1.y * acc[4 * g4 + 3];
-                    e = cmul(e, w4);
+                for (int g4 = 2; g4 >= 0; --g4) {
+                    const v2 v = vg(g4);
+                    p = mk(fmaf(p.x, w4.x, fmaf(-p.y, w4.y, v.x)), fmaf(p.x, w4.y, fmaf(p.y, w4.x, v.y)));
                 }
+                float t = fmaf(e.x, p.x, -e.y * p.y);
                 t += __shfl_xor(t, 32, 64);
                 y[cg][c] += t * unscale;
             }
