@@ -1912,32 +1912,12 @@ __global__ __launch_bounds__(256, TF > 1 ? 4 : (ONE ? (DEC ? 6 : 5) : 4)) void i
 // term by term, as inv_kernel<true, true, kInvWideTF>: the same coefficients,
 // splits, products and power-of-two scales per group.
 template <int NG>
-__device__ __forceinline__ void wave_mfma_groups(f32x16 (&acc)[NG][2], const unsigned short *aph,
+__device__ __forceinline__ bool wave_mfma_groups(f32x16 (&acc)[NG][2], const unsigned short *aph,
                                                  const unsigned short *apl, int gstride,
-                                                 const unsigned *gpk, int tile_lo, int cg, int wave,
-                                                 int col, int half, int mlo, int kn, int M, int H,
-                                                 int JL, int TR, float invH, int ng)
+                                                 const unsigned *gpk, const WaveSteps &ws, int ng)
 {
-    const int w_lo = tile_lo + 256 * cg + 64 * __builtin_amdgcn_readfirstlane(wave);
-    const int wm_lo = w_lo - M > 0 ? (w_lo - M + H - 1) / H : 0;
-    const int wm_hi = (w_lo + 63 + M) / H;
-    int kw0 = wm_lo - mlo, kw1 = wm_hi - mlo;
-    kw0 = kw0 > 0 ? kw0 & ~15 : 0;
-    kw1 = kw1 < kn - 1 ? kw1 : kn - 1;
-    const int j0 = w_lo + col - mlo * H - (kw0 + 8 * half) * H;
-    // residue rows of the decimated window table (see wave_mfma)
-    const int u0 = j0 + JL;
-    int q0 = (int)((float)u0 * invH);
-    int r0 = u0 - q0 * H;
-    q0 += r0 >= H ? 1 : (r0 < 0 ? -1 : 0);
-    r0 = u0 - q0 * H;
-    const int u1 = u0 + 32;
-    int q1 = (int)((float)u1 * invH);
-    int r1 = u1 - q1 * H;
-    q1 += r1 >= H ? 1 : (r1 < 0 ? -1 : 0);
-    r1 = u1 - q1 * H;
-    const unsigned *pc0 = gpk + r0 * TR + q0 - 7;
-    const unsigned *pc1 = gpk + r1 * TR + q1 - 7;
+    const unsigned *pc0 = gpk + (ws.lane & 0xffff);
+    const unsigned *pc1 = gpk + ((unsigned)ws.lane >> 16);
     auto step = [&](int k0, auto fresh) {
         constexpr bool FRESH = decltype(fresh)::value != 0;
         f16x8v fh[2], fl[2];
@@ -1978,16 +1958,14 @@ __device__ __forceinline__ void wave_mfma_groups(f32x16 (&acc)[NG][2], const uns
         pc0 -= 16;
         pc1 -= 16;
     };
-    int k0 = kw0;
-    if (k0 > kw1) {   // no frame reaches the wave's samples
-#pragma unroll
-        for (int g = 0; g < NG; ++g)
-            acc[g][0] = acc[g][1] = f32x16{};
-        return;
-    }
+    int k0 = ws.kw & 0xffff;
+    const int kw1 = (ws.kw >> 16) - 1;
+    if (k0 > kw1)   // no frame reaches the wave's samples: the sums are zero
+        return false;
     step(k0, IntC<1>{});
     for (k0 += 16; k0 <= kw1; k0 += 16)
         step(k0, IntC<0>{});
+    return true;
 }
 
 template <int NG>
@@ -2166,30 +2144,38 @@ __global__ __launch_bounds__(256, NG >= 4 ? 2 : 3) void inv_kernel_g(InvLaunch l
 #pragma unroll 1
         for (int cg = 0; cg < TF; ++cg) {
             f32x16 acc[NG][2];
-            wave_mfma_groups<NG>(acc, aph, apl, GS, gpk, tile_lo, cg, wave, col, half, mlo, K, M,
-                                 H, JL, TR, invH, ng);
+            const WaveSteps ws =
+                wave_steps<true>(tile_lo, cg, wave, col, half, mlo, 0, K, M, H, JL, TR, invH);
+            if (!wave_mfma_groups<NG>(acc, aph, apl, GS, gpk, ws, ng))
+                continue;   // no frame reaches these samples
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
                 uint32_t nm = n0g + (uint32_t)(256 * cg + 64 * wave + col + 32 * c);
                 nm = nm >= G ? nm - G : nm;
                 nm = nm >= G ? nm - G : nm;
                 const v2 w = phasor(tlo, thi, (int)nm, a.lo_bits);   // e^{i 2 pi n/G}
-                const v2 w4 = cmul(cmul(w, w), cmul(w, w));
+                const v2 w2 = cmul(w, w), w4 = cmul(w2, w2);
                 float tsum = 0.f;
 #pragma unroll
                 for (int g = 0; g < NG; ++g) {
                     if (g >= ng)
                         break;
                     const uint32_t bb = (uint32_t)(zk1 + D0 + 16 * g + 2 * half);
-                    v2 e = phasor(tlo, thi, mulmod(bb, nm, Gi, a.g_pow2, a.inv_G), a.lo_bits);
-                    float t = 0.f;
+                    const v2 e = phasor(tlo, thi, mulmod(bb, nm, Gi, a.g_pow2, a.inv_G), a.lo_bits);
+                    // Re(e P), P = sum_g4 w4^g4 (Z_(g4,0) + w Z_(g4,1)), as in inv_kernel
+                    const f32x16 &z = acc[g][c];
+                    auto vg = [&](int g4) {
+                        return mk(fmaf(w.x, z[4 * g4 + 2], fmaf(-w.y, z[4 * g4 + 3], z[4 * g4])),
+                                  fmaf(w.x, z[4 * g4 + 3], fmaf(w.y, z[4 * g4 + 2], z[4 * g4 + 1])));
+                    };
+                    v2 pp = vg(3);
 #pragma unroll
-                    for (int g4 = 0; g4 < 4; ++g4) {
-                        const v2 e1 = cmul(e, w);
-                        t += e.x * acc[g][c][4 * g4] - e.y * acc[g][c][4 * g4 + 1];
-                        t += e1.x * acc[g][c][4 * g4 + 2] - e1.y * acc[g][c][4 * g4 + 3];
-                        e = cmul(e, w4);
+                    for (int g4 = 2; g4 >= 0; --g4) {
+                        const v2 v = vg(g4);
+                        pp = mk(fmaf(pp.x, w4.x, fmaf(-pp.y, w4.y, v.x)),
+                                fmaf(pp.x, w4.y, fmaf(pp.y, w4.x, v.y)));
                     }
+                    const float t = fmaf(e.x, pp.x, -e.y * pp.y);
                     tsum += t * ldexpf(a.g_unscale, -scg[g]);
                 }
                 tsum += __shfl_xor(tsum, 32, 64);
