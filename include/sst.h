@@ -374,9 +374,12 @@ void sst_batch_destroy(sst_batch_t batch);
  *                  larger values are capped)
  *   seed_step      speculative relative threshold: seed the running maximum
  *                  with every seed_step-th frame group (>= 1)
- *   inv_tf         inverse: groups of 256 output samples per workgroup, 1 or 4
- *                  (4 only when the frames 1024 samples meet fit the staged
- *                  block; SST_E_UNSUPPORTED otherwise)
+ *   inv_tf         inverse: groups of 256 output samples per workgroup, 1, 4
+ *                  or 8 (4 only when the frames 1024 samples meet fit the
+ *                  staged block; 8 when the frames 2048 samples meet fit it
+ *                  and the hop-decimated window table fits; SST_E_UNSUPPORTED
+ *                  otherwise); 0 = the widest that fits (or 4 when inv_groups
+ *                  asks for 2 or 4)
  *   inv_groups     inverse with inv_tf 4: destination groups of 16 bins staged
  *                  together, 1 (one at a time), 2 or 4 (groups of the tile's
  *                  zones together, sharing each window operand read and each
@@ -397,7 +400,7 @@ typedef struct {
 sst_status sst_plan_get_tuning(sst_plan_t plan, sst_tuning *out);
 
 /* sst_plan_set_tuning -- set the launch choices (before or after bind).
- * Errors: SST_E_ARG (negative values, inv_tf not 0/1/4, inv_groups not
+ * Errors: SST_E_ARG (negative values, inv_tf not 0/1/4/8, inv_groups not
  * 0/1/2/4), SST_E_UNSUPPORTED. */
 sst_status sst_plan_set_tuning(sst_plan_t plan, const sst_tuning *tuning);
 

@@ -287,6 +287,18 @@ int inv_dec_words(const sst_plan_s *pl)
 {
     return pl->p.hop * inv_dec_row(pl->M, pl->p.hop);
 }
+// Extra-wide tiles (2048 samples) stage every frame they meet in one block
+// and need the hop-decimated window table.
+bool inv_xwide_fits(const sst_plan_s *pl)
+{
+    return inv_max_k(pl->M, pl->p.hop, sst::kInvXWideTF) <= sst::kInvWideKB &&
+           inv_dec_words(pl) <= sst::kInvDecMax;
+}
+// The default tile width: the widest that fits.
+int inv_default_tf(const sst_plan_s *pl)
+{
+    return inv_xwide_fits(pl) ? sst::kInvXWideTF : (inv_wide_fits(pl) ? sst::kInvWideTF : 1);
+}
 
 // max_dec: the largest decimated window table of the list (inv_dec_words);
 // max_L: its longest window; tf: sample groups per workgroup of every channel.
@@ -313,7 +325,7 @@ sst::InvLaunch inv_launch(const sst::InvDesc *dev, int n_ch, int64_t blk_begin, 
 // bits).
 bool inv_groups_fit(const sst_plan_s *pl, int tf, int groups)
 {
-    if (tf <= 1 || inv_dec_words(pl) > sst::kInvDecMax)
+    if (tf != sst::kInvWideTF || inv_dec_words(pl) > sst::kInvDecMax)
         return false;
     sst::InvLaunch l = inv_launch(nullptr, 1, 0, inv_max_k(pl->M, pl->p.hop, tf),
                                   pl->n_lo + pl->n_hi, pl->p.win_len, inv_dec_words(pl), tf,
@@ -327,13 +339,20 @@ int inv_groups_of(const sst_plan_s *pl)
     return (g > 1 && inv_groups_fit(pl, pl->inv_tf, g)) ? g : 1;
 }
 // Kind of inverse tile of a plan: 0 narrow, 1 wide, 2 / 3 wide with 2 / 4
-// groups staged together.
+// groups staged together, 4 extra-wide.
 int inv_kind_of(const sst_plan_s *pl)
 {
     if (pl->inv_tf <= 1)
         return 0;
+    if (pl->inv_tf == sst::kInvXWideTF)
+        return 4;
     const int g = inv_groups_of(pl);
     return g == 4 ? 3 : (g == 2 ? 2 : 1);
+}
+constexpr int kInvKinds = 5;
+int inv_kind_tf(int kind)
+{
+    return kind == 0 ? 1 : (kind == 4 ? sst::kInvXWideTF : sst::kInvWideTF);
 }
 
 // Round to BF16, nearest even.
@@ -538,8 +557,8 @@ sst_status sst_plan(const sst_params *params, sst_plan_t *out)
     pl->lo_bits = (bits + 1) / 2;
     pl->n_lo = 1 << pl->lo_bits;
     pl->n_hi = (pl->G + pl->n_lo - 1) >> pl->lo_bits;
-    // Wide inverse tiles whenever their frames fit one staged block.
-    pl->inv_tf = inv_wide_fits(pl) ? sst::kInvWideTF : 1;
+    // The widest inverse tiles whose frames fit one staged block.
+    pl->inv_tf = inv_default_tf(pl);
 
     // Workspace layout.
     size_t off = align_up(sizeof(sst::Ctrl));
@@ -1114,14 +1133,21 @@ sst_status apply_tuning(sst_plan_s *pl, const sst_tuning &t)
 {
     if (t.fwd_wg_per_cu < 0 || t.seed_step < 0)
         return fail(SST_E_ARG, "tuning values must be >= 0");
-    if (t.inv_tf != 0 && t.inv_tf != 1 && t.inv_tf != sst::kInvWideTF)
-        return fail(SST_E_ARG, "inv_tf must be 0, 1 or 4");
+    if (t.inv_tf != 0 && t.inv_tf != 1 && t.inv_tf != sst::kInvWideTF &&
+        t.inv_tf != sst::kInvXWideTF)
+        return fail(SST_E_ARG, "inv_tf must be 0, 1, 4 or 8");
     if (t.inv_groups < 0 || t.inv_groups == 3 || t.inv_groups > 4)
         return fail(SST_E_ARG, "inv_groups must be 0, 1, 2 or 4");
     if (t.inv_tf == sst::kInvWideTF && !inv_wide_fits(pl))
         return fail(SST_E_UNSUPPORTED, "inv_tf 4: the frames 1024 output samples meet exceed "
                                        "the staged block");
-    const int tf = t.inv_tf ? t.inv_tf : (inv_wide_fits(pl) ? sst::kInvWideTF : 1);
+    if (t.inv_tf == sst::kInvXWideTF && !inv_xwide_fits(pl))
+        return fail(SST_E_UNSUPPORTED, "inv_tf 8: the frames 2048 output samples meet exceed "
+                                       "the staged block, or the window table is too long");
+    // grouped staging runs on tiles of four groups: the default width for it is 4
+    const int tf = t.inv_tf ? t.inv_tf
+                            : (t.inv_groups > 1 ? (inv_wide_fits(pl) ? sst::kInvWideTF : 1)
+                                                : inv_default_tf(pl));
     if (t.inv_groups > 1 && !inv_groups_fit(pl, tf, t.inv_groups))
         return fail(SST_E_UNSUPPORTED, "inv_groups 2 / 4 need inv_tf 4, the hop-decimated window "
                                        "table and the staged groups within a third / half of "
@@ -1319,11 +1345,13 @@ sst_status sst_autotune(sst_plan_t pl, const float *x, float *T, const int32_t *
     // inverse: tile width, and the grouped staging of the wide tiles
     if (st == SST_OK && ridge) {
         float best_inv = -1.f;
-        const int choices[4][2] = {{1, 1}, {sst::kInvWideTF, 1}, {sst::kInvWideTF, 2},
-                                   {sst::kInvWideTF, 4}};
+        const int choices[5][2] = {{1, 1}, {sst::kInvWideTF, 1}, {sst::kInvWideTF, 2},
+                                   {sst::kInvWideTF, 4}, {sst::kInvXWideTF, 1}};
         for (const auto &ch : choices) {
             const int tf = ch[0], gr = ch[1];
-            if (tf > 1 && !inv_wide_fits(pl))
+            if (tf == sst::kInvWideTF && !inv_wide_fits(pl))
+                continue;
+            if (tf == sst::kInvXWideTF && !inv_xwide_fits(pl))
                 continue;
             if (gr > 1 && !inv_groups_fit(pl, tf, gr))
                 continue;
@@ -1590,7 +1618,7 @@ sst_status sst_batch_commit(sst_batch_t b, void *stream)
     b->idesc.assign(b->plans.size(), sst::InvDesc{});
     b->inv_pos.assign(b->plans.size(), 0);
     size_t pos = 0;
-    for (int kind = 0; kind < 4; ++kind) {
+    for (int kind = 0; kind < kInvKinds; ++kind) {
         int64_t blk = 0;
         for (size_t c = 0; c < b->plans.size(); ++c) {
             const sst_plan_s *pl = b->plans[c];
@@ -1738,7 +1766,7 @@ sst_status sst_batch_inverse(sst_batch_t b, int32_t c_begin, int32_t c_end, void
     const sst::InvDesc *dev = reinterpret_cast<const sst::InvDesc *>(b->ws + b->off_idesc);
     // one launch per kind of tile: the range's channels of that kind are a
     // contiguous run of the descriptor array
-    for (int kind = 0; kind < 4; ++kind) {
+    for (int kind = 0; kind < kInvKinds; ++kind) {
         int p0 = -1, p1 = -1;
         int max_k = 2, max_tab = 1, max_L = 1, max_dec = 1;
         bool any_err = false;
@@ -1759,11 +1787,11 @@ sst_status sst_batch_inverse(sst_batch_t b, int32_t c_begin, int32_t c_end, void
         if (p0 < 0)
             continue;
         sst::InvLaunch l = inv_launch(dev + p0, p1 - p0 + 1, b->idesc[(size_t)p0].blk0, max_k,
-                                      max_tab, max_L, max_dec, kind ? sst::kInvWideTF : 1,
+                                      max_tab, max_L, max_dec, inv_kind_tf(kind),
                                       kind == 3 ? 4 : (kind == 2 ? 2 : 1));
         // grouped tiles of several channels may need more than one channel's
         // LDS (the maxima of different channels); up to the CU's 160 KiB
-        if (sst::inv_lds_bytes(l) > (kind >= 2 ? 160 * 1024 : 64 * 1024))
+        if (sst::inv_lds_bytes(l) > ((kind == 2 || kind == 3) ? 160 * 1024 : 64 * 1024))
             return fail(SST_E_UNSUPPORTED, "inverse tiles need more than 64 KiB of LDS "
                                            "(window too long for the hop)");
         const int64_t blocks = b->idesc[(size_t)p1].blk_end - l.blk_begin;

@@ -103,7 +103,8 @@ struct InvLaunch {
     int max_tab;            // LDS float2 entries of the largest phase tables in the list
     int max_gtab;           // LDS words of the largest window table in the list
     int dec;                // window tables decimated by the hop (inv_gtab_words)
-    int tf;                 // groups of kInvTileSamples per workgroup (1 or kInvWideTF)
+    int tf;                 // groups of kInvTileSamples per workgroup (1, kInvWideTF or
+                            // kInvXWideTF; the last needs dec)
     int groups;             // groups of 16 destinations staged together (1, 2 or 4; 2 and 4
                             // need tf > 1 and dec)
 };
@@ -115,6 +116,7 @@ constexpr int kInvDecMax = 10240;
 
 constexpr int kInvTileSamples = 256;   // output samples per group of four inverse waves
 constexpr int kInvWideTF = 4;          // groups per workgroup of the wide inverse tiles
+constexpr int kInvXWideTF = 8;         // groups per workgroup of the extra-wide tiles
 constexpr int kInvWideKB = 144;        // frames a wide tile may meet (one staged block)
 // LDS of the grouped inverse with g groups staged: three workgroups per CU
 // for two groups, two for four

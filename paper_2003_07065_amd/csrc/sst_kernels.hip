@@ -1419,8 +1419,9 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 // Denominator: for samples whose frames all exist it depends on n mod H only
 // and comes from a table built on the host in float64; near the ends of the
 // signal it is summed here.
-// Wide tiles.  A workgroup covers TF x 256 consecutive output samples (each
-// wave TF groups of 64): the zone coefficients of the tile's frames are
+// Wide tiles.  A workgroup covers TF x 256 consecutive output samples (TF = 4,
+// or 8 with the decimated window table; each wave TF groups of 64, two
+// columns of 32 per group): the zone coefficients of the tile's frames are
 // staged once per group of 16 bins and serve every sample group, and the
 // tables are built once per TF x 256 samples.  Frames a tile meets grow by
 // 256 TF / H, so a wide tile stages (256 TF + 2M) / H frames where TF narrow
@@ -1606,7 +1607,7 @@ __device__ __forceinline__ bool wave_mfma(f32x16 &acc0, f32x16 &acc1, const unsi
 // after the staging and need no registers during it.  DEC: the window table is
 // decimated by the hop, so a lane's 8 window values are consecutive words;
 // otherwise they are gathered with clamped indices.  TF: sample groups of 256
-// per workgroup (1, or 4 with ONE).  Waves per SIMD: the most that each
+// per workgroup (1, or 4 or 8 with ONE).  Waves per SIMD: the most that each
 // variant fits without spilling registers.
 template <bool ONE, bool DEC, int TF>
 __global__ __launch_bounds__(256, TF > 1 ? 4 : (ONE ? (DEC ? 6 : 5) : 4)) void inv_kernel(InvLaunch l)
@@ -1718,20 +1719,23 @@ __global__ __launch_bounds__(256, TF > 1 ? 4 : (ONE ? (DEC ? 6 : 5) : 4)) void i
     const v2 *__restrict__ Trow = reinterpret_cast<const v2 *>(a.T) + (int64_t)(mlo - frame0) * a.n_dst;
     const unsigned short *aph = ahi + col * KBP + 8 * half;   // this lane's A row and k chunk
     const unsigned short *apl = alo + col * KBP + 8 * half;
-    // ONE with the decimated table: each sample group's frame steps and
-    // window addressing do not depend on the destination group; they are set
-    // once per tile (the clamped-table variants, short of registers, set
-    // them per group)
-    WaveSteps wst[ONE && DEC ? TF : 1];
-    if constexpr (ONE && DEC) {
+    // ONE with the decimated table and up to four sample groups: each sample
+    // group's frame steps and window addressing do not depend on the
+    // destination group; they are set once per tile (the other variants,
+    // short of registers, set them per destination group)
+    constexpr bool HOIST = ONE && DEC && TF <= 4;
+    WaveSteps wst[HOIST ? TF : 1];
+    if constexpr (HOIST) {
 #pragma unroll
         for (int cg = 0; cg < TF; ++cg)
             wst[cg] = wave_steps<DEC>(tile_lo, cg, wave, col, half, mlo, 0, K, M, H, JL, TR, invH);
     }
-    float y[TF][2];
+    // y[cg]: the sum for sample 256 cg + 64 wave + col + 32 half of the tile
+    // (both halves of a column pair hold both sums; each keeps its own)
+    float y[TF];
 #pragma unroll
     for (int cg = 0; cg < TF; ++cg)
-        y[cg][0] = y[cg][1] = 0.f;
+        y[cg] = 0.f;
     for (int d0 = d_lo; d0 <= d_hi; d0 += 16) {
         f32x16 acc0, acc1;
         if constexpr (!ONE) {
@@ -1828,7 +1832,7 @@ __global__ __launch_bounds__(256, TF > 1 ? 4 : (ONE ? (DEC ? 6 : 5) : 4)) void i
         for (int cg = 0; cg < TF; ++cg) {
             if constexpr (ONE) {
                 WaveSteps ws;
-                if constexpr (DEC)
+                if constexpr (HOIST)
                     ws = wst[cg];
                 else
                     ws = wave_steps<DEC>(tile_lo, cg, wave, col, half, mlo, 0, K, M, H, JL, TR, invH);
@@ -1837,10 +1841,9 @@ __global__ __launch_bounds__(256, TF > 1 ? 4 : (ONE ? (DEC ? 6 : 5) : 4)) void i
             }
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
-                // nm = n mod G: n - tile_lo < 1024 and G >= 512, so two steps suffice
+                // nm = n mod G (n - tile_lo < 2048, so the sum stays below 2^31)
                 uint32_t nm = n0g + (uint32_t)(256 * cg + 64 * wave + col + 32 * c);
-                nm = nm >= G ? nm - G : nm;
-                nm = nm >= G ? nm - G : nm;
+                nm = pow2 ? (nm & (G - 1)) : nm % G;
                 const v2 w = phasor(tlo, thi, (int)nm, a.lo_bits);                             // e^{i 2 pi n/G}
                 const v2 e = phasor(tlo, thi, mulmod(bb, nm, Gi, a.g_pow2, a.inv_G), a.lo_bits);   // bin bb
                 const v2 w2 = cmul(w, w), w4 = cmul(w2, w2);
@@ -1860,19 +1863,18 @@ __global__ __launch_bounds__(256, TF > 1 ? 4 : (ONE ? (DEC ? 6 : 5) : 4)) void i
                 }
                 float t = fmaf(e.x, p.x, -e.y * p.y);
                 t += __shfl_xor(t, 32, 64);
-                y[cg][c] += t * unscale;
+                if (half == c)
+                    y[cg] += t * unscale;
             }
         }
     }
 
-    // denominator and output: lanes of the first half write their two samples
+    // denominator and output: every lane writes its sample of each group
     double d2 = 0.0, r2 = 0.0;
 #pragma unroll
-    for (int cg = 0; cg < TF; ++cg)
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-        const int n = tile_lo + 256 * cg + wave * 64 + col + 32 * c;
-        const bool writer = half == 0 && n <= tile_hi;
+    for (int cg = 0; cg < TF; ++cg) {
+        const int n = tile_lo + 256 * cg + wave * 64 + col + 32 * half;
+        const bool writer = n <= tile_hi;
         float xv = 0.f;
         if (writer) {
             const int flo = n - M > 0 ? (n - M + H - 1) / H : 0;
@@ -1887,7 +1889,7 @@ __global__ __launch_bounds__(256, TF > 1 ? 4 : (ONE ? (DEC ? 6 : 5) : 4)) void i
                     dv += win[n - m * H + M].x;
                 dv *= win[M].x;
             }
-            xv = dv > 0.f ? y[cg][c] / dv : 0.f;
+            xv = dv > 0.f ? y[cg] / dv : 0.f;
             float *out = a.xhat + (int64_t)q * a.n + n;
             if (a.accumulate)
                 xv += *out;
@@ -2600,7 +2602,11 @@ hipError_t launch_inverse(const InvLaunch &l, int64_t blocks, bool clear_err, hi
         // the host sets tf > 1 only when every tile's frames fit one block
         if (l.max_k > InvGeo<kInvWideTF>::KB)
             return hipErrorInvalidValue;
-        if (l.groups == 4 && l.dec)
+        if (l.tf == kInvXWideTF) {
+            if (!l.dec || l.groups > 1)
+                return hipErrorInvalidValue;
+            hipLaunchKernelGGL((inv_kernel<true, true, kInvXWideTF>), g, b, lds, s, l);
+        } else if (l.groups == 4 && l.dec)
             hipLaunchKernelGGL((inv_kernel_g<4>), g, b, lds, s, l);
         else if (l.groups == 2 && l.dec)
             hipLaunchKernelGGL((inv_kernel_g<2>), g, b, lds, s, l);

@@ -260,7 +260,8 @@ def test_forward_static_rejects_oversized_workspace():
 def test_tuning_set_get_and_validation():
     p = sst.Plan(**_params())
     t = p.get_tuning()
-    assert t["inv_tf"] == 4 and t["seed_step"] == 0    # c2 shape: a 1024-sample tile meets 130 frames
+    # c2 shape: a 1024-sample tile meets 130 frames, a 2048-sample one 194
+    assert t["inv_tf"] == 4 and t["seed_step"] == 0
     p.set_tuning(fwd_wg_per_cu=2, seed_step=64, inv_tf=1)
     t = p.get_tuning()
     assert (t["fwd_wg_per_cu"], t["seed_step"], t["inv_tf"]) == (2, 64, 1)
@@ -273,9 +274,10 @@ def test_tuning_set_get_and_validation():
     # hop 4 with a 1023-tap window: 1024 samples meet 512 frames, beyond the staged block
     q = sst.Plan(**_params(hop=4))
     assert q.get_tuning()["inv_tf"] == 1
-    with pytest.raises(sst.SSTError) as e:
-        q.set_tuning(inv_tf=4)
-    assert e.value.status == sst.SST_E_UNSUPPORTED
+    for tf in (4, 8):
+        with pytest.raises(sst.SSTError) as e:
+            q.set_tuning(inv_tf=tf)
+        assert e.value.status == sst.SST_E_UNSUPPORTED
 
 
 def test_tuning_inverse_groups():
@@ -285,10 +287,17 @@ def test_tuning_inverse_groups():
     c3 = dict(nfft=8192, win_len=2047, sigma=256.0, hop=32, f_hi=5000.0, subdiv=8)
     p = sst.Plan(**_params(**c3))     # 1024 samples meet 98 frames: 4 groups in about 79 KiB
     t = p.get_tuning()
-    assert (t["inv_tf"], t["inv_groups"]) == (4, 1)
-    for g in (2, 4, 1):
-        p.set_tuning(inv_groups=g)
-        assert p.get_tuning()["inv_groups"] == g
+    assert (t["inv_tf"], t["inv_groups"]) == (8, 1)   # 2048 samples meet 130 frames
+    for g in (2, 4):
+        p.set_tuning(inv_groups=g)   # grouped staging takes tiles of 1024 samples
+        assert (p.get_tuning()["inv_tf"], p.get_tuning()["inv_groups"]) == (4, g)
+    p.set_tuning(inv_groups=1)
+    assert (p.get_tuning()["inv_tf"], p.get_tuning()["inv_groups"]) == (8, 1)
+    p.set_tuning(inv_tf=4, inv_groups=1)
+    assert (p.get_tuning()["inv_tf"], p.get_tuning()["inv_groups"]) == (4, 1)
+    with pytest.raises(sst.SSTError) as e:
+        p.set_tuning(inv_tf=8, inv_groups=2)
+    assert e.value.status == sst.SST_E_UNSUPPORTED
     p.set_tuning(inv_tf=1)
     assert p.get_tuning()["inv_groups"] == 1   # narrow tiles stage one group at a time
     with pytest.raises(sst.SSTError) as e:

@@ -691,8 +691,9 @@ def test_colstats_epilogue_of_the_production_forward(sst, name, n, cfg):
 @pytest.mark.parametrize("hw", [26, 40])
 def test_inverse_grouped_staging(sst, hw):
     """The wide inverse with 4 or 2 destination groups of a tile staged at once
-    (hw 26: one pass of 4 or two of 2; hw 40: 4 + 2 or 2 + 2 + 2) against the
-    one-group-at-a-time kernel and the oracle, on the same T: c3 shape
+    (hw 26: one pass of 4 or two of 2; hw 40: 4 + 2 or 2 + 2 + 2), and the
+    extra-wide tiles of 2048 samples, against the one-group-at-a-time kernel
+    and the oracle, on the same T: c3 shape
     (N_f 8192, H 32, z 8), N = 2^16, ridges of a tone and of a sweep, with
     frames of no ridge (-1); and chunked calls that accumulate."""
     cfg = SSTConfig(25600.0, 2047, 256.0, 32, 8192, 0.0, 5000.0, 8, "rel", 1e-3, hw)
@@ -716,19 +717,29 @@ def test_inverse_grouped_staging(sst, hw):
         plan.set_tuning(inv_tf=4, inv_groups=groups)
         assert plan.get_tuning()["inv_groups"] == groups
         xs[groups] = plan.inverse(Tg, rg, hw).cpu().numpy()
+    # extra-wide tiles (2048 samples, 130 frames): the default here
+    plan.set_tuning()
+    assert (plan.get_tuning()["inv_tf"], plan.get_tuning()["inv_groups"]) == (8, 1)
+    xs["x8"] = plan.inverse(Tg, rg, hw).cpu().numpy()
+
+    def chunked():
+        a = nfr // 2 + 5
+        xa = torch.zeros((2, n), dtype=torch.float32, device="cuda")
+        plan.inverse(Tg[:a], rg[:, :a].contiguous(), hw, frame0=0, xhat=xa, accumulate=True)
+        plan.inverse(Tg[a:], rg[:, a:].contiguous(), hw, frame0=a, xhat=xa, accumulate=True)
+        return xa.cpu().numpy()
+    xa8 = chunked()
     plan.set_tuning(inv_tf=4, inv_groups=4)
-    a = nfr // 2 + 5
-    xa = torch.zeros((2, n), dtype=torch.float32, device="cuda")
-    plan.inverse(Tg[:a], rg[:, :a].contiguous(), hw, frame0=0, xhat=xa, accumulate=True)
-    plan.inverse(Tg[a:], rg[:, a:].contiguous(), hw, frame0=a, xhat=xa, accumulate=True)
-    xa = xa.cpu().numpy()
+    xa = chunked()
     for q in range(2):
         xo = oracle.inverse(T32.astype(np.complex128), ridge[q], hw, o.g, cfg.hop, cfg.nfft,
                             o.band.k1, cfg.subdiv, n)
         e4, e2, e1 = relf(xs[4][q], xo), relf(xs[2][q], xo), relf(xs[1][q], xo)
-        ea = relf(xa[q], xo)
+        e8, ea, ea8 = relf(xs["x8"][q], xo), relf(xa[q], xo), relf(xa8[q], xo)
         d4, d2 = relf(xs[4][q], xs[1][q]), relf(xs[2][q], xs[1][q])
+        d8 = relf(xs["x8"][q], xs[1][q])
         _say(f"[inverse groups] hw={hw} comp {q}: relF 4 groups {e4:.2e}, 2 groups {e2:.2e}, "
-             f"one group {e1:.2e}, chunked {ea:.2e}; vs one group {d4:.2e} / {d2:.2e}")
-        assert max(e4, e2, e1, ea) <= 1e-5
-        assert d4 <= 1e-6 and d2 <= 1e-6
+             f"one group {e1:.2e}, 2048-sample tiles {e8:.2e}, chunked {ea:.2e} / {ea8:.2e}; "
+             f"vs one group {d4:.2e} / {d2:.2e} / {d8:.2e}")
+        assert max(e4, e2, e1, e8, ea, ea8) <= 1e-5
+        assert d4 <= 1e-6 and d2 <= 1e-6 and d8 <= 1e-6
