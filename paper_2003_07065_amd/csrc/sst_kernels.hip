@@ -1494,7 +1494,7 @@ struct WaveSteps {
 template <bool DEC>
 __device__ __forceinline__ WaveSteps wave_steps(int tile_lo, int cg, int wave, int col, int half,
                                                 int mlo, int kb, int kn, int M, int H, int JL,
-                                                int TR, float invH)
+                                                int TR, uint32_t hinv)
 {
     WaveSteps w;
     const int w_lo = tile_lo + 256 * cg + 64 * __builtin_amdgcn_readfirstlane(wave);
@@ -1512,19 +1512,21 @@ __device__ __forceinline__ WaveSteps wave_steps(int tile_lo, int cg, int wave, i
         // the wave's first frame and end up to 15 after its last, and a wave
         // spans 64 samples, so |j| <= M + 63 + 15 H.
         // u0 = q0 H + r0 and u1 = u0 + 32 = q1 H + r1, 0 <= u0 < 2^24: the
-        // float quotient is within one of the exact one, then corrected
-        const int u0 = j0 + JL;
-        int q0 = (int)((float)u0 * invH);
-        int r0 = u0 - q0 * H;
-        q0 += r0 >= H ? 1 : (r0 < 0 ? -1 : 0);
-        r0 = u0 - q0 * H;
-        const int u1 = u0 + 32;
-        int q1 = (int)((float)u1 * invH);
-        int r1 = u1 - q1 * H;
-        q1 += r1 >= H ? 1 : (r1 < 0 ? -1 : 0);
-        r1 = u1 - q1 * H;
+        // high word of u m, m = floor(2^32 / H) (hinv), is the quotient or one
+        // less, then corrected
+        const uint32_t u0 = (uint32_t)(j0 + JL), u1 = u0 + 32;
+        uint32_t q0 = __umulhi(u0, hinv), q1 = __umulhi(u1, hinv);
+        uint32_t r0 = u0 - q0 * (uint32_t)H, r1 = u1 - q1 * (uint32_t)H;
+        if (r0 >= (uint32_t)H) {
+            ++q0;
+            r0 -= H;
+        }
+        if (r1 >= (uint32_t)H) {
+            ++q1;
+            r1 -= H;
+        }
         // every word read lies in the table (fewer than 2^16 words)
-        w.lane = (r0 * TR + q0 - 7) | ((r1 * TR + q1 - 7) << 16);
+        w.lane = (int)((r0 * TR + q0 - 7) | ((r1 * TR + q1 - 7) << 16));
     } else {
         w.lane = j0;
     }
@@ -1643,7 +1645,7 @@ __global__ __launch_bounds__(256, TF > 1 ? 4 : (ONE ? (DEC ? 6 : 5) : 4)) void i
     const int tile_lo = span_lo + (int)(local - (unsigned)q * tiles) * (kInvTile * TF);
     const int tile_hi = tile_lo + kInvTile * TF - 1 < span_end ? tile_lo + kInvTile * TF - 1 : span_end;
     const int M = a.M, H = a.hop, Gi = a.G;
-    const float invH = 1.0f / (float)H;
+    const uint32_t hinv = 0xffffffffu / (uint32_t)H;   // floor(2^32 / H) unless H is 1
     const int frame0 = (int)a.frame0, nfr = (int)a.nframes, nframes_all = (int)a.n_frames;
     const v2 *__restrict__ win = reinterpret_cast<const v2 *>(a.win);
 
@@ -1712,6 +1714,9 @@ __global__ __launch_bounds__(256, TF > 1 ? 4 : (ONE ? (DEC ? 6 : 5) : 4)) void i
     const int zk1 = a.z * a.k1;
     const uint32_t G = (uint32_t)Gi;
     const bool pow2 = a.g_pow2 != 0;
+    // e^{i 2 pi 32 / G} and e^{i 2 pi 128 / G} (tables complete: the barrier above)
+    const v2 w32 = phasor(tlo, thi, (int)(32u % G), a.lo_bits);
+    const v2 w128 = phasor(tlo, thi, (int)(128u % G), a.lo_bits);
     const uint32_t mh0 = (uint32_t)(mlo * H) % G;    // (m_lo H) mod G
     const uint32_t n0g = (uint32_t)tile_lo % G;      // tile_lo mod G
     const uint32_t hg = (uint32_t)H % G;             // H mod G
@@ -1728,7 +1733,7 @@ __global__ __launch_bounds__(256, TF > 1 ? 4 : (ONE ? (DEC ? 6 : 5) : 4)) void i
     if constexpr (HOIST) {
 #pragma unroll
         for (int cg = 0; cg < TF; ++cg)
-            wst[cg] = wave_steps<DEC>(tile_lo, cg, wave, col, half, mlo, 0, K, M, H, JL, TR, invH);
+            wst[cg] = wave_steps<DEC>(tile_lo, cg, wave, col, half, mlo, 0, K, M, H, JL, TR, hinv);
     }
     // y[cg]: the sum for sample 256 cg + 64 wave + col + 32 half of the tile
     // (both halves of a column pair hold both sums; each keeps its own)
@@ -1821,13 +1826,16 @@ __global__ __launch_bounds__(256, TF > 1 ? 4 : (ONE ? (DEC ? 6 : 5) : 4)) void i
             __syncthreads();
             if constexpr (!ONE) {
                 const WaveSteps ws = wave_steps<DEC>(tile_lo, 0, wave, col, half, mlo, kb, kn, M, H,
-                                                     JL, TR, invH);
+                                                     JL, TR, hinv);
                 wave_mfma<DEC, KBP, false>(acc0, acc1, aph, apl, gpk, ws, M, H);
             }
         }
         // rows 8 (i/4) + 4 half + i mod 4 = 2 dd + p: dd = 4 (i/4) + 2 half + (i mod 4) / 2
         const uint32_t bb = (uint32_t)(zk1 + d0 + 2 * half);
         const float unscale = ldexpf(a.g_unscale, -sc);
+        // the second column of a pair (n + 32) takes the first's phasors
+        // times these: e^{i 2 pi 32 bb / G}
+        const v2 e32 = phasor(tlo, thi, mulmod(bb, 32u % G, Gi, a.g_pow2, a.inv_G), a.lo_bits);
 #pragma unroll
         for (int cg = 0; cg < TF; ++cg) {
             if constexpr (ONE) {
@@ -1835,18 +1843,24 @@ __global__ __launch_bounds__(256, TF > 1 ? 4 : (ONE ? (DEC ? 6 : 5) : 4)) void i
                 if constexpr (HOIST)
                     ws = wst[cg];
                 else
-                    ws = wave_steps<DEC>(tile_lo, cg, wave, col, half, mlo, 0, K, M, H, JL, TR, invH);
+                    ws = wave_steps<DEC>(tile_lo, cg, wave, col, half, mlo, 0, K, M, H, JL, TR, hinv);
                 if (!wave_mfma<DEC, KBP, true>(acc0, acc1, aph, apl, gpk, ws, M, H))
                     continue;   // no frame reaches these samples: the sums are zero
             }
+            // nm = n mod G of the first column (n - tile_lo < 2048, so the
+            // sum stays below 2^31)
+            uint32_t nm = n0g + (uint32_t)(256 * cg + 64 * wave + col);
+            nm = pow2 ? (nm & (G - 1)) : nm % G;
+            v2 w = phasor(tlo, thi, (int)nm, a.lo_bits);                             // e^{i 2 pi n/G}
+            v2 e = phasor(tlo, thi, mulmod(bb, nm, Gi, a.g_pow2, a.inv_G), a.lo_bits);   // bin bb
+            v2 w4 = cmul(cmul(w, w), cmul(w, w));
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
-                // nm = n mod G (n - tile_lo < 2048, so the sum stays below 2^31)
-                uint32_t nm = n0g + (uint32_t)(256 * cg + 64 * wave + col + 32 * c);
-                nm = pow2 ? (nm & (G - 1)) : nm % G;
-                const v2 w = phasor(tlo, thi, (int)nm, a.lo_bits);                             // e^{i 2 pi n/G}
-                const v2 e = phasor(tlo, thi, mulmod(bb, nm, Gi, a.g_pow2, a.inv_G), a.lo_bits);   // bin bb
-                const v2 w2 = cmul(w, w), w4 = cmul(w2, w2);
+                if (c == 1) {   // n + 32: w32, w32^4 and e32 (one rounding each)
+                    w = cmul(w, w32);
+                    w4 = cmul(w4, w128);
+                    e = cmul(e, e32);
+                }
                 const f32x16 &acc = c ? acc1 : acc0;
                 // sum over the lane's 8 rows of Re(e w^(4 g + s) Z): with
                 // V_g = Z_(g,0) + w Z_(g,1), the sum is Re(e P), P = sum_g w4^g V_g
@@ -2001,7 +2015,7 @@ __global__ __launch_bounds__(256, NG >= 4 ? 2 : 3) void inv_kernel_g(InvLaunch l
     const int tile_lo = span_lo + (int)(local - (unsigned)q * tiles) * (kInvTile * TF);
     const int tile_hi = tile_lo + kInvTile * TF - 1 < span_end ? tile_lo + kInvTile * TF - 1 : span_end;
     const int M = a.M, H = a.hop, Gi = a.G;
-    const float invH = 1.0f / (float)H;
+    const uint32_t hinv = 0xffffffffu / (uint32_t)H;   // floor(2^32 / H) unless H is 1
     const int frame0 = (int)a.frame0, nfr = (int)a.nframes, nframes_all = (int)a.n_frames;
     const v2 *__restrict__ win = reinterpret_cast<const v2 *>(a.win);
 
@@ -2147,7 +2161,7 @@ __global__ __launch_bounds__(256, NG >= 4 ? 2 : 3) void inv_kernel_g(InvLaunch l
         for (int cg = 0; cg < TF; ++cg) {
             f32x16 acc[NG][2];
             const WaveSteps ws =
-                wave_steps<true>(tile_lo, cg, wave, col, half, mlo, 0, K, M, H, JL, TR, invH);
+                wave_steps<true>(tile_lo, cg, wave, col, half, mlo, 0, K, M, H, JL, TR, hinv);
             if (!wave_mfma_groups<NG>(acc, aph, apl, GS, gpk, ws, ng))
                 continue;   // no frame reaches these samples
 #pragma unroll
