@@ -409,7 +409,9 @@ sst_status sst_plan_set_tuning(sst_plan_t plan, const sst_tuning *tuning);
  * buffers and keep the fastest: every forward choice (workgroups per CU,
  * threshold seed step) is timed over the whole signal with HIP events, then,
  * when ridge and xhat are given, every inverse tile width.  Each candidate
- * runs once untimed and `reps` times timed (reps >= 1).  Blocks until done
+ * runs once untimed and `reps` times timed (reps >= 1); when those take under
+ * 20 ms in all, it is timed again over as many calls as fill about 20 ms (at
+ * most 1000) and that mean is used.  Blocks until done
  * (a set-up call); T and xhat hold the last candidate's results.
  *   x, T           as for sst_forward over all frames
  *   ridge, n_comp, hw, xhat   as for sst_inverse (optional: NULL ridge skips

@@ -1297,22 +1297,34 @@ sst_status sst_autotune(sst_plan_t pl, const float *x, float *T, const int32_t *
     }
     sst_status st = SST_OK;
     // time reps calls of fn after one untimed call; ms per call, < 0 on error
+    // mean time of one call: once untimed, then reps calls; when those take
+    // under 20 ms in all, again over as many calls as fill about 20 ms (at
+    // most 1000), so that short calls are not timed at the events' noise
     auto timed = [&](auto fn) -> float {
         if ((st = fn()) != SST_OK)
             return -1.f;
-        hipError_t he = hipEventRecord(ev[0], s);
-        for (int r = 0; r < reps && st == SST_OK && he == hipSuccess; ++r)
-            st = fn();
-        if (he == hipSuccess)
-            he = hipEventRecord(ev[1], s);
-        if (he == hipSuccess)
-            he = hipEventSynchronize(ev[1]);
-        float ms = 0.f;
-        if (he == hipSuccess)
-            he = hipEventElapsedTime(&ms, ev[0], ev[1]);
-        if (he != hipSuccess && st == SST_OK)
-            st = hip_fail(he, "autotune timing");
-        return st == SST_OK ? ms / reps : -1.f;
+        auto run = [&](int n) -> float {
+            hipError_t he = hipEventRecord(ev[0], s);
+            for (int r = 0; r < n && st == SST_OK && he == hipSuccess; ++r)
+                st = fn();
+            if (he == hipSuccess)
+                he = hipEventRecord(ev[1], s);
+            if (he == hipSuccess)
+                he = hipEventSynchronize(ev[1]);
+            float ms = 0.f;
+            if (he == hipSuccess)
+                he = hipEventElapsedTime(&ms, ev[0], ev[1]);
+            if (he != hipSuccess && st == SST_OK)
+                st = hip_fail(he, "autotune timing");
+            return st == SST_OK ? ms : -1.f;
+        };
+        const float ms = run(reps);
+        if (ms < 0.f || ms >= 20.f)
+            return ms < 0.f ? -1.f : ms / reps;
+        const float per = ms / reps;
+        const int n = per > 0.02f ? std::min(1000, (int)(20.f / per) + 1) : 1000;
+        const float ms2 = run(n);
+        return ms2 < 0.f ? -1.f : ms2 / n;
     };
     sst_tuning cur = pl->tune;
     sst_tuning chosen = cur;
