@@ -309,6 +309,9 @@ struct Twiddles {
             t3[r] = twid[(unsigned)((NF / (256 * G::R3)) * k3 * r)];
         tw4 = twid;
     }
+    // LAST = false leaves out the radix-2 pass 4 (N_f = 8192): its outputs
+    // are then formed where they are read (out4)
+    template <bool LAST = true>
     __device__ __forceinline__ void passes(v2 *lds, const v2 *tbl) const
     {
         v2 w2[16];
@@ -319,9 +322,20 @@ struct Twiddles {
             w2[r] = tbl[(r - 1) * 16 + k2];
         P2::run(lds, w2);
         P3::run(lds, t3);
-        if constexpr (G::P4)
+        if constexpr (G::P4 && LAST)
             pass4(lds);
     }
+    // Output k of pass 4 from its inputs (pass 4 left out): butterfly
+    // j = k mod 4096 of elements u = j and v = j + 4096 gives u + W v at j and
+    // u - W v at j + 4096, W = W_8192^j (wj), the products of pass4 itself.
+    __device__ __forceinline__ v2 out4(const v2 *lds, int k, v2 wj) const
+    {
+        const int j = k & (NF / 2 - 1);
+        const v2 u = lds[pad16(j)];
+        const v2 t = cmul(lds[pad16(j) + padded_stride(NF / 2)], wj);
+        return (k & (NF / 2)) ? u - t : u + t;
+    }
+    __device__ __forceinline__ v2 w4_of(int j) const { return tw4[(unsigned)j]; }
     // Radix-2 pass of stride 4096 (N_f = 8192, one frame): butterfly j pairs
     // elements j and j + 4096 with twiddle W_8192^j.
     __device__ __forceinline__ void pass4(v2 *lds) const
@@ -623,6 +637,25 @@ __global__ __launch_bounds__(Geo<NF>::NT, DEBUG ? 2 : ((NF == 8192 || (NF == 409
         else
             chi[e - 64] = twid[(unsigned)(e - 64) * 64u];
     }
+    // N_f = 8192: the radix-2 pass 4 is left out and only the outputs that are
+    // read are formed (the in-band bins and their mirrors: 3202 of 8192 on a
+    // band of 0 .. N_f / 5), each from its two inputs.
+    constexpr bool FUSE4 = G::P4;
+    static_assert(!FUSE4 || F == 1, "pass 4 is left out with one frame per item");
+    // Y[k] and conj(Y[N_f - k]) of frame f after the FFT passes.  Left-out
+    // pass 4: the mirror's butterfly is 4096 - (k mod 4096), whose twiddle is
+    // -conj(W_8192^(k mod 4096)) exactly; bins 0 and 4096 are their own mirrors.
+    auto ypair = [&](int f, int k, v2 &P, v2 &Qc) {
+        if constexpr (FUSE4) {
+            const int j = k & (NF / 2 - 1);
+            const v2 wj = tw.w4_of(j);
+            P = tw.out4(lds, k, wj);
+            Qc = conjv(j == 0 ? P : tw.out4(lds, NF - k, mk(-wj.x, wj.y)));
+        } else {
+            P = lds[pad16(f * NF + k)];
+            Qc = conjv(lds[pad16(f * NF + ((NF - k) & (NF - 1)))]);
+        }
+    };
     const CA ChanDesc *ch = (const CA ChanDesc *)g.ch;
 
     // Pass-1 role of this thread: frame f1 of the iteration, taps jj + r Q.
@@ -739,7 +772,7 @@ __global__ __launch_bounds__(Geo<NF>::NT, DEBUG ? 2 : ((NF == 8192 || (NF == 409
         }
         fetch(itn, an, chg);
         __syncthreads();
-        tw.passes(lds, twl);
+        tw.template passes<!FUSE4>(lds, twl);
         __builtin_amdgcn_s_setprio(1);
 
         if constexpr (MODE == kFwdStft) {
@@ -758,8 +791,8 @@ __global__ __launch_bounds__(Geo<NF>::NT, DEBUG ? 2 : ((NF == 8192 || (NF == 409
                     split_flat(e, a.n_src, inv_nsrc, f, ik);
                 }
                 const int k = a.k1 + ik;
-                const v2 P = lds[pad16(f * NF + k)];
-                const v2 Qc = conjv(lds[pad16(f * NF + ((NF - k) & (NF - 1)))]);
+                v2 P, Qc;
+                ypair(f, k, P, Qc);
                 const v2 phk = cphase_of(clo, chi, (k * a.M) & (NF - 1));
                 __builtin_nontemporal_store(cmul(phk, 0.5f * (P + Qc)), Sp + e);
                 if (Sdp) {
@@ -785,8 +818,8 @@ __global__ __launch_bounds__(Geo<NF>::NT, DEBUG ? 2 : ((NF == 8192 || (NF == 409
                     split_flat(e, a.n_src, inv_nsrc, f, ik);
                 }
                 const int k = a.k1 + ik;
-                const v2 P = lds[pad16(f * NF + k)];
-                const v2 Qc = conjv(lds[pad16(f * NF + ((NF - k) & (NF - 1)))]);
+                v2 P, Qc;
+                ypair(f, k, P, Qc);
                 best = fmaxf(best, mag2_of(0.5f * (P + Qc)));
             }
             if (chg || itn >= g.item_stop) {
@@ -850,7 +883,9 @@ __global__ __launch_bounds__(Geo<NF>::NT, DEBUG ? 2 : ((NF == 8192 || (NF == 409
                 continue;
             const int k = a.k1 + ik;
             v2 P, Qc;
-            if constexpr (F == 1) {
+            if constexpr (FUSE4) {
+                ypair(f, k, P, Qc);
+            } else if constexpr (F == 1) {
                 // k = k1 + tid + i NT: P at pk0 + i (NT + NT/16), the mirror
                 // bin N_f - k at qk0 - i (NT + NT/16) (bin 0 is its own mirror)
                 P = lds[pk0 + i * padded_stride(NT)];
