@@ -238,18 +238,23 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmArgs a)
             for (int c = 0; c < CT; ++c)
                 acc[c] = f32x16{};
             const int64_t abase = (int64_t)rt * a.ksteps * 64 + lane;
-            u4v an = afrag[abase];
-            u4v anl = SPLIT ? afrag_lo[abase] : u4v{};
             const u4v *ap = afrag + abase, *apl = afrag_lo + abase;
             const unsigned short *bp = xhi + col * a.hop + 8 * half;   // k = 0, column tile 0
             const int cstride = 32 * a.hop;                             // next column tile
-            for (int ks = 0; ks < a.ksteps; ++ks) {
-                const u4v ac = an, acl = anl;
-                if (ks + 1 < a.ksteps) {
-                    an = ap[(ks + 1) * 64];
-                    if constexpr (SPLIT)
-                        anl = apl[(ks + 1) * 64];
-                }
+            // The A fragments (from L2) are loaded AD steps ahead into a ring of
+            // registers, so that later steps' loads are in flight while this
+            // one's products run.  The main loop covers whole blocks of AD steps
+            // without branches (a load past the last step takes the last
+            // fragment again); the remaining steps use what the ring holds.
+            constexpr int AD = 4;
+            const int klast = a.ksteps - 1;
+            u4v ring[AD], ringl[AD];
+#pragma unroll
+            for (int u = 0; u < AD; ++u) {
+                ring[u] = ap[min(u, klast) * 64];
+                ringl[u] = SPLIT ? apl[min(u, klast) * 64] : u4v{};
+            }
+            auto step = [&](int ks, u4v ac, u4v acl) {
 #pragma unroll
                 for (int c = 0; c < CT; ++c) {
                     const unsigned short *q = bp + c * cstride + ks * 16;
@@ -261,7 +266,22 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmArgs a)
                         acc[c] = mma<PREC>(acl, b, acc[c]);
                     }
                 }
+            };
+            const int kmain = a.ksteps - a.ksteps % AD;
+            for (int k0 = 0; k0 < kmain; k0 += AD) {
+#pragma unroll
+                for (int u = 0; u < AD; ++u) {
+                    const u4v ac = ring[u], acl = ringl[u];
+                    ring[u] = ap[min(k0 + u + AD, klast) * 64];
+                    if constexpr (SPLIT)
+                        ringl[u] = apl[min(k0 + u + AD, klast) * 64];
+                    step(k0 + u, ac, acl);
+                }
             }
+#pragma unroll
+            for (int u = 0; u < AD - 1; ++u)
+                if (kmain + u < a.ksteps)
+                    step(kmain + u, ring[u], ringl[u]);
             // epilogue: IF estimate, destination, histogram (Eqs. 12-13, 27-29)
 #pragma unroll
             for (int c = 0; c < CT; ++c) {
