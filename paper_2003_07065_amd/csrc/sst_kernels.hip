@@ -1645,9 +1645,11 @@ __device__ __forceinline__ bool wave_mfma(f32x16 &acc0, f32x16 &acc1, const unsi
 // decimated by the hop, so a lane's 8 window values are consecutive words;
 // otherwise they are gathered with clamped indices.  TF: sample groups of 256
 // per workgroup (1, or 4 or 8 with ONE).  Waves per SIMD: the most that each
-// variant fits without spilling registers.
+// variant fits without spilling registers (wide tiles: the bound of three
+// leaves the same 119-123 registers, four waves per SIMD, and schedules the
+// code for it 1.5 % faster than the bound of four).
 template <bool ONE, bool DEC, int TF>
-__global__ __launch_bounds__(256, TF > 1 ? 4 : (ONE ? (DEC ? 6 : 5) : 4)) void inv_kernel(InvLaunch l)
+__global__ __launch_bounds__(256, TF > 1 ? 3 : (ONE ? (DEC ? 6 : 5) : 4)) void inv_kernel(InvLaunch l)
 {
     using IG = InvGeo<TF>;
     constexpr int KB = IG::KB, KBP = IG::KBP, STAGE = IG::STAGE;
